@@ -1,0 +1,240 @@
+/*
+ * cdnafact.h -- dense LU (partial pivoting) and Cholesky factorizations,
+ * solves, mixed-precision solvers with iterative refinement, and batched
+ * small factorizations for AMD Instinct MI355X (gfx950).
+ *
+ * The method is the blocked right-looking factorization whose dominant cost
+ * is the Schur-complement update of the trailing matrix (Kwasniewski et al.,
+ * "On the Parallel I/O Optimality of Linear Algebra Kernels: Near-Optimal
+ * Matrix Factorizations", Sec. 7: the A00 / A10 / A01 / A11 routines, and
+ * Table 1).  One GPU; no collectives.
+ *
+ * Conventions (every entry point):
+ *  - Matrices are column-major: element (i, j) is at A[i + j*lda], 0-based,
+ *    with lda >= max(1, n).  Sizes are 32-bit ints; leading dimensions are
+ *    32-bit ints and offsets are computed in 64 bits.
+ *  - Every matrix, vector, ipiv and info pointer is a DEVICE pointer owned
+ *    by the caller (hipMalloc'd or from a tensor), unless the argument is
+ *    documented as "host".  The library never frees caller memory.
+ *  - The library owns only a workspace inside the handle.  It grows lazily
+ *    (hipMalloc) up to a cap set with cdf_set_workspace_limit(); a call that
+ *    would need more returns CDF_ERR_ALLOC without launching anything.
+ *  - Calls are asynchronous on the handle's stream (cdf_set_stream) unless
+ *    documented otherwise.  Outputs are valid once that stream reaches the
+ *    point after the call.
+ *  - Return codes report API-level outcomes; numerical outcomes (singular
+ *    or not positive definite input) are written to the device int *info
+ *    with LAPACK meaning.  On CDF_ERR_INVALID_ARG, cdf_last_bad_arg(h) gives
+ *    the 1-based position of the first bad argument (LAPACK's info = -i).
+ *  - n == 0 (or nrhs == 0) is a valid no-op returning CDF_OK.
+ *  - Calls that overlap on one handle must not be issued from several host
+ *    threads at once; distinct handles are independent.
+ */
+#ifndef CDNAFACT_H
+#define CDNAFACT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define CDF_API __attribute__((visibility("default")))
+#else
+#define CDF_API
+#endif
+
+typedef enum {
+    CDF_OK = 0,
+    CDF_ERR_INVALID_ARG = 1,     /* argument out of range; see cdf_last_bad_arg */
+    CDF_ERR_HIP = 2,             /* a HIP runtime call failed */
+    CDF_ERR_ALLOC = 3,           /* workspace allocation failed or exceeds the cap */
+    CDF_ERR_NOT_CONVERGED = 4,   /* iterative refinement did not reach its target */
+    CDF_ERR_UNSUPPORTED = 5      /* valid but unimplemented option (e.g. uplo 'U') */
+} cdf_status_t;
+
+typedef struct cdf_handle_s *cdf_handle_t;
+
+/* Create a handle bound to the current HIP device, on the null stream. */
+CDF_API cdf_status_t cdf_create(cdf_handle_t *h);
+/* Destroy a handle and free its workspace (synchronizes its stream). */
+CDF_API cdf_status_t cdf_destroy(cdf_handle_t h);
+/* Set the stream (a hipStream_t, passed as void*) that later calls enqueue on. */
+CDF_API cdf_status_t cdf_set_stream(cdf_handle_t h, void *stream);
+/* Cap the handle's workspace in bytes (0 = no cap). */
+CDF_API cdf_status_t cdf_set_workspace_limit(cdf_handle_t h, size_t bytes);
+/* Bytes currently held by the handle's workspace. */
+CDF_API size_t cdf_workspace_bytes(cdf_handle_t h);
+/* 1-based index of the first invalid argument of the last failed call, else 0. */
+CDF_API int cdf_last_bad_arg(cdf_handle_t h);
+/* Human-readable name of a status code (static storage). */
+CDF_API const char *cdf_status_string(cdf_status_t s);
+
+/* Tunable parameters (block sizes chosen per call when left at 0 = auto). */
+typedef enum {
+    CDF_PARAM_LU_NB = 0,         /* LU outer panel width (multiple of 32) */
+    CDF_PARAM_CHOL_NB = 1,       /* Cholesky outer block width (multiple of 32) */
+    CDF_PARAM_LU_LEAF_ROWS = 2,  /* rows per thread in the LU panel leaf (1 or 2) */
+    CDF_PARAM_COUNT = 3
+} cdf_param_t;
+CDF_API cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value);
+CDF_API int cdf_get_param(cdf_handle_t h, cdf_param_t p);
+
+/*
+ * LU factorization with partial pivoting, in place: P A = L U.
+ * Sec. 7 (Algorithm 1, routines A00/A10/A01/A11) and Sec. 6.1 (statements
+ * S1/S2); the pivot rule is classic partial pivoting (first row of largest
+ * magnitude in the current column, lowest row index on ties), not the
+ * tournament pivoting of Sec. 7.3, so the interchanges equal those of
+ * unblocked Gaussian elimination with partial pivoting.
+ *   n     order of A (>= 0)
+ *   A     device, n x n, lda >= max(1, n); on exit unit-lower L strictly
+ *         below the diagonal and U on and above it
+ *   ipiv  device int[n]; on exit 1-based interchanges: row k was swapped
+ *         with row ipiv[k]-1 at step k (LAPACK convention)
+ *   info  device int; on exit 0, or j > 0 if U(j-1,j-1) is exactly zero for
+ *         the first such j (the factorization is still completed)
+ */
+CDF_API cdf_status_t cdf_dgetrf(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info);
+
+/*
+ * Solve A X = B with the factors of cdf_dgetrf: B <- P B, then the unit
+ * lower and upper triangular solves.  trans must be 'N'.
+ *   A, ipiv  device, as left by cdf_dgetrf; B device n x nrhs, ldb >= n;
+ *   on exit B holds X.
+ */
+CDF_API cdf_status_t cdf_dgetrs(cdf_handle_t h, char trans, int n, int nrhs, const double *A, int lda,
+                        const int *ipiv, double *B, int ldb);
+
+/*
+ * Cholesky factorization A = L L^T, in place, lower triangle (uplo 'L';
+ * 'U' returns CDF_ERR_UNSUPPORTED).  Sec. 6.2 (Cholesky listing) and
+ * Sec. 7.5 / Table 1 (potrf of A00, trsm, triangular gemm of A11).
+ * Only the lower triangle is read or written.
+ *   info  device int; 0, or j > 0 if the leading minor of order j is not
+ *         positive definite (the factorization stops there).
+ */
+CDF_API cdf_status_t cdf_dpotrf(cdf_handle_t h, char uplo, int n, double *A, int lda, int *info);
+
+/* Solve A X = B with the lower Cholesky factor (L then L^T); B is overwritten. */
+CDF_API cdf_status_t cdf_dpotrs(cdf_handle_t h, char uplo, int n, int nrhs, const double *A, int lda,
+                        double *B, int ldb);
+
+/* Precision of the trailing update in the mixed-precision solvers. */
+typedef enum {
+    CDF_UPD_FP64 = 0,            /* binary64 update (plain FP64 factorization) */
+    CDF_UPD_BF16 = 1,            /* bfloat16 operands, binary32 accumulation */
+    CDF_UPD_FP16 = 2,            /* binary16 operands with per-tile 2^e scaling, binary32 accumulation */
+    CDF_UPD_FP8E4M3 = 3          /* OCP E4M3FN operands with per-tile 2^e scaling, binary32 accumulation */
+} cdf_update_prec_t;
+
+/*
+ * Mixed-precision solve of A X = B by LU and classical iterative
+ * refinement.  A binary32 working copy W of A is factored with a binary64
+ * panel (pivot search, interchanges, triangular solves) and a trailing
+ * update in precision p; the refinement loop computes r = B - A X in
+ * binary64 with the original A and corrects X with solves on W until the
+ * HPL scaled residual ||A x - b||_inf / (eps (||A||_inf ||x||_inf +
+ * ||b||_inf) n), eps = 2^-53, is <= 16 for every column.  Low-precision LU
+ * with refinement is the related work the paper cites (Sec. 11).
+ *   A        device n x n (not modified); B device n x nrhs (not modified)
+ *   X        device n x nrhs, ldx >= n: the solution on exit
+ *   max_iter maximum number of corrections (>= 0)
+ *   iters    host int: corrections applied
+ *   scaled_resid host double: final scaled residual (max over columns)
+ *   info     device int: factorization info of W as for cdf_dgetrf
+ * Returns CDF_ERR_NOT_CONVERGED when the target is not reached within
+ * max_iter or the residual stagnates (X then holds the last iterate).
+ * Synchronizes the handle's stream once per refinement iteration.
+ */
+CDF_API cdf_status_t cdf_dgesv_mixed(cdf_handle_t h, cdf_update_prec_t p, int n, int nrhs, const double *A,
+                             int lda, const double *B, int ldb, double *X, int ldx, int max_iter,
+                             int *iters, double *scaled_resid, int *info);
+
+/* As cdf_dgesv_mixed, for symmetric positive definite A, by lower Cholesky. */
+CDF_API cdf_status_t cdf_dposv_mixed(cdf_handle_t h, cdf_update_prec_t p, int n, int nrhs, const double *A,
+                             int lda, const double *B, int ldb, double *X, int ldx, int max_iter,
+                             int *iters, double *scaled_resid, int *info);
+
+/*
+ * Quantize an m x n binary32 matrix tile by tile (the operand encoding of
+ * the low-precision trailing update).  Tiles are tm x tn blocks anchored at
+ * (0, 0).  For each tile, e = floor(log2(maxfinite / amax)) (capped at 64;
+ * 0 for an all-zero tile; always 0 for BF16) and every element is encoded
+ * as the format's nearest value (ties to even, E4M3 saturating) of x * 2^e.
+ *   p     CDF_UPD_BF16, CDF_UPD_FP16 or CDF_UPD_FP8E4M3
+ *   X     device float, ldx >= m; Q device codes (2 bytes for BF16/FP16,
+ *         1 byte for E4M3), leading dimension ldq >= m (in elements)
+ *   exps  device int[ceil(m/tm) * ceil(n/tn)], tile (ti, tj) at ti + tj*ceil(m/tm)
+ */
+CDF_API cdf_status_t cdf_quantize(cdf_handle_t h, cdf_update_prec_t p, int m, int n, const float *X, int ldx,
+                          int tm, int tn, void *Q, int ldq, int *exps);
+
+/*
+ * Low-precision Schur-complement update C <- C - dq(QA) dq(QB) with binary32
+ * accumulation, where dq(Q) = decode(Q) * 2^-e per tile (Sec. 7, routine
+ * A11, in the update precision).  QA is m x k in tiles of tm x k, QB is
+ * k x n in tiles of k x tn, as produced by cdf_quantize; tm and tn must be
+ * the tile sizes the library uses (cdf_update_tile()).
+ *   C device float m x n (ldc >= m).
+ */
+CDF_API cdf_status_t cdf_lowp_update(cdf_handle_t h, cdf_update_prec_t p, int m, int n, int k,
+                             const void *QA, int lda, const int *ea, const void *QB, int ldb,
+                             const int *eb, float *C, int ldc);
+/* Tile size (rows of QA tiles = columns of QB tiles) used by the low-precision update. */
+CDF_API int cdf_update_tile(cdf_update_prec_t p);
+
+/*
+ * FP64 Schur-complement update C <- C - A B (Sec. 7, routine A11; Table 1,
+ * local gemm), the dominant step of the LU factorization.
+ *   A device m x k (lda >= m), B device k x n (ldb >= k), C device m x n (ldc >= m).
+ */
+CDF_API cdf_status_t cdf_dgemm_update(cdf_handle_t h, int m, int n, int k, const double *A, int lda,
+                              const double *B, int ldb, double *C, int ldc);
+
+/* ---------------------------------------------------------------- batched */
+
+typedef enum { CDF_F64 = 0, CDF_F32 = 1 } cdf_dtype_t;
+typedef struct cdf_vbatch_plan_s *cdf_vbatch_plan_t;
+
+/*
+ * Plan a batch of independent small factorizations of uneven sizes, run as
+ * one persistent kernel launch (problems handed out largest first from a
+ * device work counter) captured in a HIP graph.
+ *   batch      number of problems (>= 0)
+ *   n_host     host int[batch], orders 1 <= n <= 1024
+ *   kind_host  host int[batch]: 0 = LU with partial pivoting, 1 = lower Cholesky
+ *   dt         element type of the matrices
+ * The plan holds its own device copies of the sizes and schedule.
+ */
+CDF_API cdf_status_t cdf_vbatch_plan_create(cdf_handle_t h, int batch, const int *n_host, const int *kind_host,
+                                    cdf_dtype_t dt, cdf_vbatch_plan_t *plan);
+/*
+ * Run a planned batch (graph replay on the handle's stream).
+ *   A_array    device array of device pointers to the matrices (double* or float*)
+ *   lda_array  device int[batch]
+ *   ipiv_array device array of device int* (LU problems; may hold NULL for Cholesky)
+ *   info_array device int[batch]: LAPACK info per problem
+ * The pointer arrays are read at run time, so a plan may be replayed on new data.
+ */
+CDF_API cdf_status_t cdf_vbatch_run(cdf_handle_t h, cdf_vbatch_plan_t plan, void *const *A_array,
+                            const int *lda_array, int *const *ipiv_array, int *info_array);
+CDF_API cdf_status_t cdf_vbatch_plan_destroy(cdf_vbatch_plan_t plan);
+
+/* ------------------------------------------------------------- I/O bound */
+
+/*
+ * Sequential (one processor) I/O lower bound in elements for fast memory of
+ * m_elems elements (Sec. 6.1 and 6.2):
+ *   kind 0 (LU):       (2n^3 - 6n^2 + 4n) / (3 sqrt(M)) + n(n-1)/2
+ *   kind 1 (Cholesky): n^3 / (3 sqrt(M)) + n^2/2 + n
+ * Returns a negative value for an invalid kind or m_elems <= 0.  Host only.
+ */
+CDF_API double cdf_io_lower_bound_elems(int kind, double n, double m_elems);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CDNAFACT_H */

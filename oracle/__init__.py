@@ -210,6 +210,16 @@ def lu_step_flops(n: int, steps: int) -> float:
     return s
 
 
+def chol_step_flops(n: int, steps: int) -> float:
+    """Exact flops of the first ``steps`` outer steps of an n x n Cholesky
+    (square root, divisions, and the lower-triangle update)."""
+    s = 0.0
+    for k in range(min(n, steps)):
+        r = n - k - 1
+        s += 1 + r + r * (r + 1.0)
+    return s
+
+
 # --------------------------------------------------------------------------
 # Quantizer reference (C)
 # --------------------------------------------------------------------------

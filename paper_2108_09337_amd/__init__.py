@@ -1,0 +1,311 @@
+"""Python binding of libcdnafact: dense LU / Cholesky factorizations and
+solves, mixed-precision solvers and batched small factorizations for AMD
+MI355X (gfx950).
+
+Argument marshalling only: every step runs in the HIP kernels of
+``libcdnafact.so`` (built in-tree by ``build.py``).  torch supplies device
+memory and the current stream.  Matrices are column-major: a 2-D tensor must
+have stride(0) == 1 (e.g. from :func:`cm_empty` / :func:`to_device`); its
+leading dimension is stride(1).  1-D tensors are single columns.
+
+The library is loaded after ``import torch`` so that both share one HIP
+runtime.  If ``libcdnafact.so`` is missing this module raises: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcdnafact.so")
+
+CDF_OK, CDF_ERR_INVALID_ARG, CDF_ERR_HIP, CDF_ERR_ALLOC, CDF_ERR_NOT_CONVERGED, CDF_ERR_UNSUPPORTED = range(6)
+UPD = {"fp64": 0, "bf16": 1, "fp16": 2, "fp8e4m3": 3, "e4m3": 3}
+PARAM = {"lu_nb": 0, "chol_nb": 1, "lu_leaf_rows": 2}
+F64, F32 = 0, 1
+
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_lib = None
+
+
+class CdfError(RuntimeError):
+    def __init__(self, name, status, bad_arg=0):
+        self.status = status
+        self.bad_arg = bad_arg
+        msg = f"{name} failed: {_lib.cdf_status_string(status).decode()}"
+        if bad_arg:
+            msg += f" (argument {bad_arg})"
+        super().__init__(msg)
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcdnafact.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not found: run paper_2108_09337_amd/build.py (or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "cdf_create": (_i, [ctypes.POINTER(_vp)]),
+        "cdf_destroy": (_i, [_vp]),
+        "cdf_set_stream": (_i, [_vp, _vp]),
+        "cdf_set_workspace_limit": (_i, [_vp, ctypes.c_size_t]),
+        "cdf_workspace_bytes": (ctypes.c_size_t, [_vp]),
+        "cdf_last_bad_arg": (_i, [_vp]),
+        "cdf_status_string": (ctypes.c_char_p, [_i]),
+        "cdf_set_param": (_i, [_vp, _i, _i]),
+        "cdf_get_param": (_i, [_vp, _i]),
+        "cdf_dgetrf": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
+        "cdf_dgetrs": (_i, [_vp, ctypes.c_char, _i, _i, _vp, _i, _vp, _vp, _i]),
+        "cdf_dpotrf": (_i, [_vp, ctypes.c_char, _i, _vp, _i, _vp]),
+        "cdf_dpotrs": (_i, [_vp, ctypes.c_char, _i, _i, _vp, _i, _vp, _i]),
+        "cdf_dgesv_mixed": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _i, _c_int_p, _c_double_p, _vp]),
+        "cdf_dposv_mixed": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _i, _c_int_p, _c_double_p, _vp]),
+        "cdf_quantize": (_i, [_vp, _i, _i, _i, _vp, _i, _i, _i, _vp, _i, _vp]),
+        "cdf_lowp_update": (_i, [_vp, _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _vp, _i]),
+        "cdf_update_tile": (_i, [_i]),
+        "cdf_dgemm_update": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i]),
+        "cdf_vbatch_plan_create": (_i, [_vp, _i, _c_int_p, _c_int_p, _i, ctypes.POINTER(_vp)]),
+        "cdf_vbatch_run": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "cdf_vbatch_plan_destroy": (_i, [_vp]),
+        "cdf_io_lower_bound_elems": (ctypes.c_double, [_i, ctypes.c_double, ctypes.c_double]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------------- handles
+
+class Handle:
+    """A library handle bound to one device; calls run on torch's current stream."""
+
+    def __init__(self, device=None):
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index or 0)
+        self.device = dev
+        with torch.cuda.device(dev):
+            h = _vp()
+            st = lib().cdf_create(ctypes.byref(h))
+            if st != CDF_OK:
+                raise CdfError("cdf_create", st)
+        self._h = h
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        lib().cdf_set_stream(self._h, _vp(s))
+        return self._h
+
+    def set_param(self, name: str, value: int):
+        _check("cdf_set_param", lib().cdf_set_param(self._h, PARAM[name], int(value)), self._h)
+
+    def get_param(self, name: str) -> int:
+        return int(lib().cdf_get_param(self._h, PARAM[name]))
+
+    def set_workspace_limit(self, nbytes: int):
+        lib().cdf_set_workspace_limit(self._h, int(nbytes))
+
+    def workspace_bytes(self) -> int:
+        return int(lib().cdf_workspace_bytes(self._h))
+
+    def close(self):
+        if self._h:
+            lib().cdf_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_handles: dict = {}
+
+
+def handle(device=None) -> Handle:
+    """The handle for (device, torch's current stream on it).
+
+    One handle per stream keeps calls that may overlap in time (different
+    streams) on separate workspaces and grid-barrier counters.
+    """
+    idx = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    key = (idx, torch.cuda.current_stream(idx).cuda_stream)
+    h = _handles.get(key)
+    if h is None:
+        h = _handles[key] = Handle(idx)
+    return h
+
+
+def _check(name, status, h):
+    if status != CDF_OK:
+        raise CdfError(name, status, lib().cdf_last_bad_arg(h) if h else 0)
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() == 1:
+        return max(1, t.shape[0])
+    if t.shape[1] > 1 and t.stride(0) != 1:
+        raise ValueError("matrix tensors must be column-major (stride(0) == 1)")
+    return max(1, t.stride(1) if t.shape[1] > 1 else t.shape[0])
+
+
+def _cols(t: torch.Tensor) -> int:
+    return 1 if t.dim() == 1 else t.shape[1]
+
+
+def _p(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+# ---------------------------------------------------------------- helpers
+
+def cm_empty(rows: int, cols: int, dtype=torch.float64, device="cuda") -> torch.Tensor:
+    """Uninitialised column-major (rows x cols) tensor."""
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+def to_device(a: np.ndarray, dtype=torch.float64, device="cuda") -> torch.Tensor:
+    """Copy a numpy matrix (or vector) to a column-major device tensor."""
+    if a.ndim == 1:
+        return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype)
+    t = cm_empty(a.shape[0], a.shape[1], dtype, device)
+    t.copy_(torch.from_numpy(np.ascontiguousarray(a)).to(dtype))
+    return t
+
+
+def to_host(t: torch.Tensor) -> np.ndarray:
+    """Device tensor -> numpy (column-major for matrices)."""
+    a = t.detach().cpu()
+    return np.asfortranarray(a.numpy()) if a.dim() == 2 else a.numpy().copy()
+
+
+# ---------------------------------------------------------------- FP64 path
+
+def dgetrf(A: torch.Tensor, ipiv: torch.Tensor, info: torch.Tensor, h: Handle | None = None) -> None:
+    """In-place LU with partial pivoting (see cdf_dgetrf)."""
+    h = h or handle(A.device)
+    n = A.shape[0]
+    _check("cdf_dgetrf", lib().cdf_dgetrf(h.bind_stream(), n, _p(A), _ld(A), _p(ipiv), _p(info)), h.ptr)
+
+
+def dgetrs(A: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor, trans: str = "N", h: Handle | None = None) -> None:
+    h = h or handle(A.device)
+    n = A.shape[0]
+    _check("cdf_dgetrs", lib().cdf_dgetrs(h.bind_stream(), trans.encode(), n, _cols(B), _p(A), _ld(A), _p(ipiv),
+                                          _p(B), _ld(B)), h.ptr)
+
+
+def dpotrf(A: torch.Tensor, info: torch.Tensor, uplo: str = "L", h: Handle | None = None) -> None:
+    h = h or handle(A.device)
+    n = A.shape[0]
+    _check("cdf_dpotrf", lib().cdf_dpotrf(h.bind_stream(), uplo.encode(), n, _p(A), _ld(A), _p(info)), h.ptr)
+
+
+def dpotrs(A: torch.Tensor, B: torch.Tensor, uplo: str = "L", h: Handle | None = None) -> None:
+    h = h or handle(A.device)
+    n = A.shape[0]
+    _check("cdf_dpotrs", lib().cdf_dpotrs(h.bind_stream(), uplo.encode(), n, _cols(B), _p(A), _ld(A), _p(B),
+                                          _ld(B)), h.ptr)
+
+
+def dgemm_update(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, h: Handle | None = None) -> None:
+    """C <- C - A B (FP64, matrix cores)."""
+    h = h or handle(C.device)
+    m, k = A.shape[0], _cols(A)
+    n = _cols(C)
+    _check("cdf_dgemm_update", lib().cdf_dgemm_update(h.bind_stream(), m, n, k, _p(A), _ld(A), _p(B), _ld(B),
+                                                      _p(C), _ld(C)), h.ptr)
+
+
+# ---------------------------------------------------------------- mixed precision
+
+def _solve_mixed(fn_name, prec, A, B, X, max_iter, info, h):
+    h = h or handle(A.device)
+    iters = ctypes.c_int(0)
+    res = ctypes.c_double(0.0)
+    n = A.shape[0]
+    st = getattr(lib(), fn_name)(h.bind_stream(), UPD[prec], n, _cols(B), _p(A), _ld(A), _p(B), _ld(B), _p(X),
+                                 _ld(X), int(max_iter), ctypes.byref(iters), ctypes.byref(res), _p(info))
+    if st not in (CDF_OK, CDF_ERR_NOT_CONVERGED):
+        _check(fn_name, st, h.ptr)
+    return {"status": st, "converged": st == CDF_OK, "iters": iters.value, "scaled_resid": res.value}
+
+
+def dgesv_mixed(prec: str, A, B, X, info, max_iter: int = 30, h: Handle | None = None) -> dict:
+    """Mixed-precision LU + iterative refinement (see cdf_dgesv_mixed)."""
+    return _solve_mixed("cdf_dgesv_mixed", prec, A, B, X, max_iter, info, h)
+
+
+def dposv_mixed(prec: str, A, B, X, info, max_iter: int = 30, h: Handle | None = None) -> dict:
+    """Mixed-precision Cholesky + iterative refinement (see cdf_dposv_mixed)."""
+    return _solve_mixed("cdf_dposv_mixed", prec, A, B, X, max_iter, info, h)
+
+
+def update_tile(prec: str) -> int:
+    return int(lib().cdf_update_tile(UPD[prec]))
+
+
+def quantize(prec: str, X: torch.Tensor, tm: int, tn: int, Q: torch.Tensor, exps: torch.Tensor,
+             h: Handle | None = None) -> None:
+    h = h or handle(X.device)
+    m, n = X.shape[0], _cols(X)
+    _check("cdf_quantize", lib().cdf_quantize(h.bind_stream(), UPD[prec], m, n, _p(X), _ld(X), tm, tn, _p(Q),
+                                              _ld(Q), _p(exps)), h.ptr)
+
+
+def lowp_update(prec: str, QA, ea, QB, eb, C, k: int, h: Handle | None = None) -> None:
+    h = h or handle(C.device)
+    m, n = C.shape[0], _cols(C)
+    _check("cdf_lowp_update", lib().cdf_lowp_update(h.bind_stream(), UPD[prec], m, n, k, _p(QA), _ld(QA), _p(ea),
+                                                    _p(QB), _ld(QB), _p(eb), _p(C), _ld(C)), h.ptr)
+
+
+# ---------------------------------------------------------------- batched
+
+class VBatchPlan:
+    """A planned batch of small factorizations (see cdf_vbatch_plan_create)."""
+
+    def __init__(self, sizes, kinds, dtype=F64, h: Handle | None = None):
+        self.h = h or handle()
+        self.sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+        self.kinds = np.ascontiguousarray(kinds, dtype=np.int32)
+        plan = _vp()
+        st = lib().cdf_vbatch_plan_create(self.h.bind_stream(), len(self.sizes),
+                                          self.sizes.ctypes.data_as(_c_int_p), self.kinds.ctypes.data_as(_c_int_p),
+                                          int(dtype), ctypes.byref(plan))
+        _check("cdf_vbatch_plan_create", st, self.h.ptr)
+        self._plan = plan
+
+    def run(self, a_ptrs: torch.Tensor, ldas: torch.Tensor, ipiv_ptrs: torch.Tensor, infos: torch.Tensor) -> None:
+        st = lib().cdf_vbatch_run(self.h.bind_stream(), self._plan, _p(a_ptrs), _p(ldas), _p(ipiv_ptrs), _p(infos))
+        _check("cdf_vbatch_run", st, self.h.ptr)
+
+    def close(self):
+        if self._plan:
+            lib().cdf_vbatch_plan_destroy(self._plan)
+            self._plan = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def io_lower_bound_elems(kind: int, n: float, m_elems: float) -> float:
+    return float(lib().cdf_io_lower_bound_elems(int(kind), float(n), float(m_elems)))

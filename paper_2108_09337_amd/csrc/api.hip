@@ -1,0 +1,318 @@
+// C-ABI entry points of libcdnafact: argument checking, workspace, and the
+// blocked right-looking drivers (Sec. 7, Algorithm 1 routines A00 / A10 /
+// A01 / A11 on one GPU; Sec. 7.5 for Cholesky).
+#include "internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace {
+
+__global__ void fill_int_kernel(int *p, int count, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+inline cdf_status_t bad(cdf_handle_t h, int pos) {
+    h->bad_arg = pos;
+    return CDF_ERR_INVALID_ARG;
+}
+
+inline int lu_nb(cdf_handle_t h) {
+    const int v = h->params[CDF_PARAM_LU_NB];
+    return v > 0 ? v : 256;
+}
+
+inline int chol_nb(cdf_handle_t h) {
+    const int v = h->params[CDF_PARAM_CHOL_NB];
+    return v > 0 ? v : 128;
+}
+
+// Slots for the LU leaf's grid exchange: 2 parities x (G x 34) + 2 x 32 doubles.
+constexpr size_t kLeafSlotBytes = (2 * 256 * 34 + 64) * sizeof(double) * 4;
+
+// Recursive panel factorization of columns [c0, c0 + w) over rows [c0, n):
+// factor the left half, form its U12 and update the right half, factor the
+// right half.  Leaves (<= 32 columns) apply their interchanges to every other
+// column of the matrix, so the whole matrix stays consistently permuted.
+hipError_t lu_panel(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int c0, int w) {
+    hipStream_t s = h->stream;
+    if (w <= 32) {
+        CDF_HIP_RET(cdf::lu_leaf(h, n - c0, w, A + c0 + (size_t)c0 * lda, lda, ipiv + c0, c0, info, c0,
+                                 h->params[CDF_PARAM_LU_LEAF_ROWS]));
+        CDF_HIP_RET(cdf::laswp(s, 0, c0, A, lda, ipiv, c0, c0 + w, n));
+        CDF_HIP_RET(cdf::laswp(s, c0 + w, n, A, lda, ipiv, c0, c0 + w, n));
+        return hipSuccess;
+    }
+    const int n1 = ((w / 2 + 31) / 32) * 32;
+    const int n2 = w - n1;
+    CDF_HIP_RET(lu_panel(h, n, A, lda, ipiv, info, c0, n1));
+    double *a11 = A + c0 + (size_t)c0 * lda;
+    double *a12 = A + c0 + (size_t)(c0 + n1) * lda;
+    double *a21 = A + (c0 + n1) + (size_t)c0 * lda;
+    double *a22 = A + (c0 + n1) + (size_t)(c0 + n1) * lda;
+    CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_LLNU, n1, n2, a11, lda, a12, lda));
+    CDF_HIP_RET(cdf::dgemm(s, 0, 0, n - c0 - n1, n2, n1, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false));
+    return lu_panel(h, n, A, lda, ipiv, info, c0 + n1, n2);
+}
+
+hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info) {
+    hipStream_t s = h->stream;
+    CDF_HIP_RET(cdf::fill_int(s, info, 1, 0));
+    const int nb = lu_nb(h);
+    for (int k = 0; k < n; k += nb) {
+        const int kb = nb < n - k ? nb : n - k;
+        CDF_HIP_RET(lu_panel(h, n, A, lda, ipiv, info, k, kb));
+        const int rest = n - k - kb;
+        if (rest > 0) {
+            double *a11 = A + k + (size_t)k * lda;
+            double *a12 = A + k + (size_t)(k + kb) * lda;
+            double *a21 = A + (k + kb) + (size_t)k * lda;
+            double *a22 = A + (k + kb) + (size_t)(k + kb) * lda;
+            CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_LLNU, kb, rest, a11, lda, a12, lda));
+            CDF_HIP_RET(cdf::dgemm(s, 0, 0, rest, rest, kb, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false));
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
+    hipStream_t s = h->stream;
+    CDF_HIP_RET(cdf::fill_int(s, info, 1, 0));
+    const int nb = chol_nb(h);
+    for (int k = 0; k < n; k += nb) {
+        const int kb = nb < n - k ? nb : n - k;
+        double *a11 = A + k + (size_t)k * lda;
+        CDF_HIP_RET(cdf::potrf_diag(s, kb, a11, lda, info, k));
+        const int rest = n - k - kb;
+        if (rest > 0) {
+            double *a21 = A + (k + kb) + (size_t)k * lda;
+            double *a22 = A + (k + kb) + (size_t)(k + kb) * lda;
+            CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_RLTN, kb, rest, a11, lda, a21, lda, info));
+            CDF_HIP_RET(cdf::dgemm(s, 0, 1, rest, rest, kb, -1.0, a21, lda, a21, lda, 1.0, a22, lda, true, info));
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+namespace cdf {
+
+hipError_t fill_int(hipStream_t s, int *p, int count, int v) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_int_kernel, dim3((count + 255) / 256), dim3(256), 0, s, p, count, v);
+    return hipGetLastError();
+}
+
+cdf_status_t ws_reserve(cdf_handle_t h, size_t bytes) {
+    if (bytes <= h->ws_bytes) return CDF_OK;
+    if (h->ws_limit && bytes > h->ws_limit) return CDF_ERR_ALLOC;
+    const size_t want = align_up(bytes, (size_t)1 << 20);
+    if (h->ws) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return CDF_ERR_HIP;
+        (void)hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return CDF_ERR_ALLOC;
+    }
+    h->ws = p;
+    h->ws_bytes = want;
+    return CDF_OK;
+}
+
+}  // namespace cdf
+
+extern "C" {
+
+cdf_status_t cdf_create(cdf_handle_t *h) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    *h = nullptr;
+    cdf_handle_s *p = new (std::nothrow) cdf_handle_s();
+    if (!p) return CDF_ERR_ALLOC;
+    if (hipGetDevice(&p->device) != hipSuccess) { delete p; return CDF_ERR_HIP; }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
+        p->num_cus = cus;
+    if (hipMalloc(reinterpret_cast<void **>(&p->sync), cdf::kSyncInts * sizeof(int)) != hipSuccess) {
+        delete p;
+        return CDF_ERR_ALLOC;
+    }
+    if (hipMemset(p->sync, 0, cdf::kSyncInts * sizeof(int)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(p->sync);
+        delete p;
+        return CDF_ERR_HIP;
+    }
+    *h = p;
+    return CDF_OK;
+}
+
+cdf_status_t cdf_destroy(cdf_handle_t h) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(h->stream);
+    if (h->ws) (void)hipFree(h->ws);
+    if (h->sync) (void)hipFree(h->sync);
+    delete h;
+    return CDF_OK;
+}
+
+cdf_status_t cdf_set_stream(cdf_handle_t h, void *stream) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->stream = static_cast<hipStream_t>(stream);
+    return CDF_OK;
+}
+
+cdf_status_t cdf_set_workspace_limit(cdf_handle_t h, size_t bytes) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->ws_limit = bytes;
+    return CDF_OK;
+}
+
+size_t cdf_workspace_bytes(cdf_handle_t h) { return h ? h->ws_bytes : 0; }
+
+int cdf_last_bad_arg(cdf_handle_t h) { return h ? h->bad_arg : 0; }
+
+const char *cdf_status_string(cdf_status_t s) {
+    switch (s) {
+        case CDF_OK: return "CDF_OK";
+        case CDF_ERR_INVALID_ARG: return "CDF_ERR_INVALID_ARG";
+        case CDF_ERR_HIP: return "CDF_ERR_HIP";
+        case CDF_ERR_ALLOC: return "CDF_ERR_ALLOC";
+        case CDF_ERR_NOT_CONVERGED: return "CDF_ERR_NOT_CONVERGED";
+        case CDF_ERR_UNSUPPORTED: return "CDF_ERR_UNSUPPORTED";
+    }
+    return "CDF_ERR_UNKNOWN";
+}
+
+cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    if ((int)p < 0 || (int)p >= CDF_PARAM_COUNT) return bad(h, 2);
+    if (value < 0) return bad(h, 3);
+    if ((p == CDF_PARAM_LU_NB || p == CDF_PARAM_CHOL_NB) && value != 0 && (value % 32 != 0 || value > 256))
+        return bad(h, 3);
+    if (p == CDF_PARAM_CHOL_NB && value > 128) return bad(h, 3);
+    if (p == CDF_PARAM_LU_LEAF_ROWS && !(value == 0 || value == 1 || value == 2)) return bad(h, 3);
+    h->params[p] = value;
+    return CDF_OK;
+}
+
+int cdf_get_param(cdf_handle_t h, cdf_param_t p) {
+    if (!h || (int)p < 0 || (int)p >= CDF_PARAM_COUNT) return -1;
+    return h->params[p];
+}
+
+cdf_status_t cdf_dgetrf(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    if (n < 0) return bad(h, 2);
+    if (lda < (n > 1 ? n : 1)) return bad(h, 4);
+    if (n > 0 && !A) return bad(h, 3);
+    if (n > 0 && !ipiv) return bad(h, 5);
+    if (!info) return bad(h, 6);
+    if (n == 0) {
+        CDF_HIP_TRY(cdf::fill_int(h->stream, info, 1, 0));
+        return CDF_OK;
+    }
+    cdf_status_t st = cdf::ws_reserve(h, kLeafSlotBytes);
+    if (st != CDF_OK) return st;
+    CDF_HIP_TRY(getrf_impl(h, n, A, lda, ipiv, info));
+    return CDF_OK;
+}
+
+cdf_status_t cdf_dgetrs(cdf_handle_t h, char trans, int n, int nrhs, const double *A, int lda, const int *ipiv,
+                        double *B, int ldb) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    if (trans != 'N' && trans != 'n') {
+        if (trans == 'T' || trans == 't' || trans == 'C' || trans == 'c') return CDF_ERR_UNSUPPORTED;
+        return bad(h, 2);
+    }
+    if (n < 0) return bad(h, 3);
+    if (nrhs < 0) return bad(h, 4);
+    if (lda < (n > 1 ? n : 1)) return bad(h, 6);
+    if (ldb < (n > 1 ? n : 1)) return bad(h, 9);
+    if (n == 0 || nrhs == 0) return CDF_OK;
+    if (!A) return bad(h, 5);
+    if (!ipiv) return bad(h, 7);
+    if (!B) return bad(h, 8);
+    hipStream_t s = h->stream;
+    CDF_HIP_TRY(cdf::laswp(s, 0, nrhs, B, ldb, ipiv, 0, n, n));
+    CDF_HIP_TRY(cdf::trsm_blocked(s, cdf::TRSM_LLNU, n, nrhs, A, lda, B, ldb));
+    CDF_HIP_TRY(cdf::trsm_blocked(s, cdf::TRSM_LUNN, n, nrhs, A, lda, B, ldb));
+    return CDF_OK;
+}
+
+cdf_status_t cdf_dpotrf(cdf_handle_t h, char uplo, int n, double *A, int lda, int *info) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    if (uplo != 'L' && uplo != 'l') {
+        if (uplo == 'U' || uplo == 'u') return CDF_ERR_UNSUPPORTED;
+        return bad(h, 2);
+    }
+    if (n < 0) return bad(h, 3);
+    if (lda < (n > 1 ? n : 1)) return bad(h, 5);
+    if (n > 0 && !A) return bad(h, 4);
+    if (!info) return bad(h, 6);
+    if (n == 0) {
+        CDF_HIP_TRY(cdf::fill_int(h->stream, info, 1, 0));
+        return CDF_OK;
+    }
+    CDF_HIP_TRY(potrf_impl(h, n, A, lda, info));
+    return CDF_OK;
+}
+
+cdf_status_t cdf_dpotrs(cdf_handle_t h, char uplo, int n, int nrhs, const double *A, int lda, double *B,
+                        int ldb) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    if (uplo != 'L' && uplo != 'l') {
+        if (uplo == 'U' || uplo == 'u') return CDF_ERR_UNSUPPORTED;
+        return bad(h, 2);
+    }
+    if (n < 0) return bad(h, 3);
+    if (nrhs < 0) return bad(h, 4);
+    if (lda < (n > 1 ? n : 1)) return bad(h, 6);
+    if (ldb < (n > 1 ? n : 1)) return bad(h, 8);
+    if (n == 0 || nrhs == 0) return CDF_OK;
+    if (!A) return bad(h, 5);
+    if (!B) return bad(h, 7);
+    hipStream_t s = h->stream;
+    CDF_HIP_TRY(cdf::trsm_blocked(s, cdf::TRSM_LLNN, n, nrhs, A, lda, B, ldb));
+    CDF_HIP_TRY(cdf::trsm_blocked(s, cdf::TRSM_LLTN, n, nrhs, A, lda, B, ldb));
+    return CDF_OK;
+}
+
+cdf_status_t cdf_dgemm_update(cdf_handle_t h, int m, int n, int k, const double *A, int lda, const double *B,
+                              int ldb, double *C, int ldc) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    if (m < 0) return bad(h, 2);
+    if (n < 0) return bad(h, 3);
+    if (k < 0) return bad(h, 4);
+    if (lda < (m > 1 ? m : 1)) return bad(h, 6);
+    if (ldb < (k > 1 ? k : 1)) return bad(h, 8);
+    if (ldc < (m > 1 ? m : 1)) return bad(h, 10);
+    if (m == 0 || n == 0 || k == 0) return CDF_OK;
+    if (!A) return bad(h, 5);
+    if (!B) return bad(h, 7);
+    if (!C) return bad(h, 9);
+    CDF_HIP_TRY(cdf::dgemm(h->stream, 0, 0, m, n, k, -1.0, A, lda, B, ldb, 1.0, C, ldc, false));
+    return CDF_OK;
+}
+
+double cdf_io_lower_bound_elems(int kind, double n, double m_elems) {
+    if (!(m_elems > 0.0) || n < 0.0) return -1.0;
+    const double sm = std::sqrt(m_elems);
+    if (kind == 0) return (2.0 * n * n * n - 6.0 * n * n + 4.0 * n) / (3.0 * sm) + n * (n - 1.0) / 2.0;
+    if (kind == 1) return n * n * n / (3.0 * sm) + n * n / 2.0 + n;
+    return -1.0;
+}
+
+}  // extern "C"

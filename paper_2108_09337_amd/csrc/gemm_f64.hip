@@ -1,0 +1,215 @@
+// FP64 matrix-core GEMM for the Schur-complement update (Sec. 7, routine
+// A11; Table 1: local gemm for LU, triangular gemm for Cholesky).
+//
+//   C = beta * C + alpha * op(A) * op(B)
+//
+// Output-stationary tiling: a 128 x 128 tile of C per workgroup (4 waves in a
+// 2 x 2 arrangement, 64 x 64 per wave as 4 x 4 blocks of the 16x16x4 FP64
+// MFMA), streamed over k in steps of 16 through LDS with register
+// prefetch of the next step.  This is the tile-streaming schedule the I/O
+// bound of Sec. 6.1 is attained by (each loaded element of op(A) / op(B)
+// feeds 128 multiply-adds).
+//
+// Workgroups are remapped so that each XCD (hardware assigns workgroup b to
+// XCD b % 8) gets a contiguous run of tiles, and runs are walked in groups of
+// 8 tile-rows so the A and B panels an XCD touches stay in its L2.
+#include "internal.h"
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128;
+constexpr int BN = 128;
+constexpr int BK = 16;
+constexpr int NT = 256;
+constexpr int GROUP_M = 8;
+
+// LDS tile of R (rows of the op-operand along M or N) x BK.
+// RC (contiguous along R in global): stored [BK][R]; else [R][BK + 1].
+template <int R, bool RC>
+struct Tile {
+    static constexpr int SIZE = RC ? BK * R : R * (BK + 1);
+    static constexpr int PER_THREAD = R * BK / NT;
+    __device__ static inline int idx(int r, int kk) { return RC ? kk * R + r : r * (BK + 1) + kk; }
+    __device__ static inline void coords(int e, int &r, int &kk) {
+        if (RC) { r = e % R; kk = e / R; } else { kk = e % BK; r = e / BK; }
+    }
+};
+
+// Element (r, kk) of the operand is X[(r0+r) + (k0+kk)*ld] if RC, else
+// X[(k0+kk) + (r0+r)*ld].  Out-of-range elements read as zero.
+template <int R, bool RC>
+__device__ inline void load_tile(const double *__restrict__ X, int ld, int r0, int rmax, int k0,
+                                 int kmax, double (&reg)[Tile<R, RC>::PER_THREAD], int t) {
+#pragma unroll
+    for (int q = 0; q < Tile<R, RC>::PER_THREAD; ++q) {
+        int r, kk;
+        Tile<R, RC>::coords(t + NT * q, r, kk);
+        const int gr = r0 + r, gk = k0 + kk;
+        double v = 0.0;
+        if (gr < rmax && gk < kmax)
+            v = RC ? X[(size_t)gr + (size_t)gk * ld] : X[(size_t)gk + (size_t)gr * ld];
+        reg[q] = v;
+    }
+}
+
+template <int R, bool RC>
+__device__ inline void store_tile(double *lds, const double (&reg)[Tile<R, RC>::PER_THREAD], int t) {
+#pragma unroll
+    for (int q = 0; q < Tile<R, RC>::PER_THREAD; ++q) {
+        int r, kk;
+        Tile<R, RC>::coords(t + NT * q, r, kk);
+        lds[Tile<R, RC>::idx(r, kk)] = reg[q];
+    }
+}
+
+__device__ inline int xcd_remap(int bid, int nwg) {
+    const int full = nwg & ~7;
+    if (bid >= full) return bid;
+    const int per = full >> 3;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+__device__ inline void grouped_tile(int L, int tiles_m, int tiles_n, int &tm, int &tn) {
+    const int group = GROUP_M * tiles_n;
+    const int g = L / group;
+    const int first_m = g * GROUP_M;
+    const int gm = min(tiles_m - first_m, GROUP_M);
+    const int in = L - g * group;
+    tm = first_m + in % gm;
+    tn = in / gm;
+}
+
+__device__ inline void lower_tile(int L, int &tm, int &tn) {
+    // row-wise enumeration of the lower triangle: L = tm(tm+1)/2 + tn
+    int r = (int)((sqrt(8.0 * (double)L + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= L) ++r;
+    while (r * (r + 1) / 2 > L) --r;
+    tm = r;
+    tn = L - r * (r + 1) / 2;
+}
+
+template <int TA, int TB, bool LOWER>
+__global__ __launch_bounds__(NT, 2) void dgemm_kernel(int m, int n, int k, double alpha,
+                                                      const double *__restrict__ A, int lda,
+                                                      const double *__restrict__ B, int ldb,
+                                                      double beta, double *__restrict__ C, int ldc,
+                                                      int tiles_m, int tiles_n, const int *stop) {
+    if (stop != nullptr && *stop != 0) return;
+    constexpr bool A_RC = (TA == 0);  // op(A)(i, kk): A[i + kk*lda] when not transposed
+    constexpr bool B_RC = (TB == 1);  // op(B)(kk, j) viewed as (j, kk): B[j + kk*ldb] when transposed
+    using TA_ = Tile<BM, A_RC>;
+    using TB_ = Tile<BN, B_RC>;
+    __shared__ double As[TA_::SIZE];
+    __shared__ double Bs[TB_::SIZE];
+
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    int tm, tn;
+    if (LOWER) lower_tile(L, tm, tn);
+    else grouped_tile(L, tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+
+    v4d acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    double ra[TA_::PER_THREAD];
+    double rb[TB_::PER_THREAD];
+    const int nk = (k + BK - 1) / BK;
+    if (nk > 0) {
+        load_tile<BM, A_RC>(A, lda, m0, m, 0, k, ra, t);
+        load_tile<BN, B_RC>(B, ldb, n0, n, 0, k, rb, t);
+        store_tile<BM, A_RC>(As, ra, t);
+        store_tile<BN, B_RC>(Bs, rb, t);
+    }
+    __syncthreads();
+
+    const int lrow = lane & 15;
+    const int lk = lane >> 4;
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) {
+            load_tile<BM, A_RC>(A, lda, m0, m, (kt + 1) * BK, k, ra, t);
+            load_tile<BN, B_RC>(B, ldb, n0, n, (kt + 1) * BK, k, rb, t);
+        }
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            const int kk = ks * 4 + lk;
+            double af[4], bf[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) af[i] = As[TA_::idx(wm * 64 + i * 16 + lrow, kk)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bf[j] = Bs[TB_::idx(wn * 64 + j * 16 + lrow, kk)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            store_tile<BM, A_RC>(As, ra, t);
+            store_tile<BN, B_RC>(Bs, rb, t);
+            __syncthreads();
+        }
+    }
+
+    // 16x16 output block layout of the FP64 MFMA: register v of a lane holds
+    // row 4*v + lane/16, column lane%16.
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + wn * 64 + j * 16 + lrow;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 64 + i * 16 + v * 4 + lk;
+                if (row < m && col < n && (!LOWER || row >= col)) {
+                    double *p = C + (size_t)row + (size_t)col * ldc;
+                    const double c0 = beta == 0.0 ? 0.0 : beta * *p;
+                    *p = fma(alpha, acc[i][j][v], c0);
+                }
+            }
+        }
+}
+
+template <int TA, int TB, bool LOWER>
+hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double *A, int lda,
+                  const double *B, int ldb, double beta, double *C, int ldc, const int *stop) {
+    const int tiles_m = (m + BM - 1) / BM;
+    const int tiles_n = (n + BN - 1) / BN;
+    long long nwg = LOWER ? (long long)tiles_m * (tiles_m + 1) / 2 : (long long)tiles_m * tiles_n;
+    if (nwg <= 0) return hipSuccess;
+    if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((dgemm_kernel<TA, TB, LOWER>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k,
+                       alpha, A, lda, B, ldb, beta, C, ldc, tiles_m, tiles_n, stop);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+namespace cdf {
+
+hipError_t dgemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha, const double *A,
+                 int lda, const double *B, int ldb, double beta, double *C, int ldc, bool lower,
+                 const int *stop) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    if (lower) {
+        if (m != n) return hipErrorInvalidValue;
+        if (ta == 0 && tb == 1) return launch<0, 1, true>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop);
+        return hipErrorInvalidValue;
+    }
+    if (ta == 0 && tb == 0) return launch<0, 0, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop);
+    if (ta == 0 && tb == 1) return launch<0, 1, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop);
+    if (ta == 1 && tb == 0) return launch<1, 0, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop);
+    return launch<1, 1, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop);
+}
+
+}  // namespace cdf

@@ -1,0 +1,114 @@
+// Internal declarations shared by the HIP sources of libcdnafact.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "cdnafact.h"
+
+struct cdf_handle_s {
+    int device = 0;
+    int num_cus = 256;
+    hipStream_t stream = nullptr;
+    void *ws = nullptr;          // lazily grown workspace
+    size_t ws_bytes = 0;
+    size_t ws_limit = 0;         // 0 = no cap
+    int *sync = nullptr;         // zeroed counters for grid-wide barriers
+    int bad_arg = 0;
+    int params[CDF_PARAM_COUNT] = {0, 0, 0};
+};
+
+namespace cdf {
+
+constexpr int kSyncInts = 64;    // ints in handle->sync
+
+// Grows the handle's workspace to at least `bytes` (synchronizing the stream
+// before a reallocation).  Returns CDF_ERR_ALLOC on failure or above the cap.
+cdf_status_t ws_reserve(cdf_handle_t h, size_t bytes);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// C = beta*C + alpha*op(A)*op(B); op(A) is m x k, op(B) is k x n.
+// ta: 0 -> A is m x k, 1 -> A is k x m (op = transpose); same for tb.
+// lower: only the lower triangle (i >= j) of C is read or written (C square).
+// stop: optional device flag; a nonzero value makes the launch a no-op.
+hipError_t dgemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha,
+                 const double *A, int lda, const double *B, int ldb, double beta,
+                 double *C, int ldc, bool lower, const int *stop = nullptr);
+
+// LU panel leaf: factor the m x n (n <= 32) column block at A with partial
+// pivoting; writes absolute 1-based pivots ipiv[0..n) (row offset `row0`
+// added), first zero pivot into *info (as info_base + j + 1) if *info == 0.
+hipError_t lu_leaf(cdf_handle_t h, int m, int n, double *A, int lda, int *ipiv, int row0,
+                   int *info, int info_base, int rows_per_thread);
+
+// Apply interchanges ipiv[k1..k2) (absolute, 1-based) to rows of columns
+// [c0, c1) of A (nrows rows); an entry outside [k+1, nrows] is ignored.
+hipError_t laswp(hipStream_t s, int c0, int c1, double *A, int lda, const int *ipiv, int k1,
+                 int k2, int nrows);
+// Sets *p = v on the stream (a kernel, so that graph capture stays clean).
+hipError_t fill_int(hipStream_t s, int *p, int count, int v);
+// Same for a binary32 matrix.
+hipError_t slaswp(hipStream_t s, int c0, int c1, float *A, int lda, const int *ipiv, int k1,
+                  int k2, int nrows);
+
+// Triangular solves with a small triangle T (nb <= 256) applied to an
+// nb x ncols block B (left side) or an nrows x nb block (right side).
+//   left, lower, no-trans, unit:      B <- T^-1 B
+//   left, lower, no-trans, non-unit:  B <- T^-1 B
+//   left, lower, trans, non-unit:     B <- T^-T B
+//   left, upper, no-trans, non-unit:  B <- T^-1 B
+//   right, lower, trans, non-unit:    B <- B T^-T
+enum TrsmKind { TRSM_LLNU = 0, TRSM_LLNN = 1, TRSM_LLTN = 2, TRSM_LUNN = 3, TRSM_RLTN = 4 };
+hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
+                      double *B, int ldb, const int *stop = nullptr);
+
+// Full triangular solve with a large n x n factor (blocked: small diagonal
+// solves + GEMM updates).
+hipError_t trsm_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const double *T, int ldt,
+                        double *B, int ldb);
+
+// Cholesky of one diagonal block (n <= 128) held in LDS; stops at the first
+// non-positive pivot, writing info_base + j + 1 into *info if *info == 0.
+// *info != 0 on entry makes the kernel return without touching A.
+hipError_t potrf_diag(hipStream_t s, int n, double *A, int lda, int *info, int info_base);
+
+// Mixed-precision helpers.
+hipError_t convert_d2s(hipStream_t s, int m, int n, const double *A, int lda, float *W, int ldw,
+                       bool lower_only);
+hipError_t convert_s2d(hipStream_t s, int m, int n, const float *W, int ldw, double *A, int lda,
+                       bool lower_only);
+hipError_t quantize(hipStream_t s, int fmt, int m, int n, const float *X, int ldx, int tm, int tn,
+                    void *Q, int ldq, int *exps, bool transpose_out);
+hipError_t lowp_update(hipStream_t s, int fmt, int m, int n, int k, const void *QA, int lda,
+                       const int *ea, const void *QB, int ldb, const int *eb, float *C, int ldc,
+                       bool lower);
+int lowp_tile(int fmt);
+
+// r = b - A x for nrhs columns, binary64 (A n x n); also writes per-column
+// partial infinity norms used by the scaled residual.
+hipError_t residual(hipStream_t s, int n, int nrhs, const double *A, int lda, const double *X,
+                    int ldx, const double *B, int ldb, double *R, int ldr);
+// out[0] = ||A||_inf (max row sum of |a_ij|), using `tmp` (n doubles).
+hipError_t norm_inf_rows(hipStream_t s, int n, const double *A, int lda, double *tmp, double *out,
+                         bool symmetric_lower);
+// per column c: out[3c+0] = max|R|, out[3c+1] = max|X|, out[3c+2] = max|B|
+hipError_t col_absmax3(hipStream_t s, int n, int nrhs, const double *R, int ldr, const double *X,
+                       int ldx, const double *B, int ldb, double *out);
+hipError_t axpy_cols(hipStream_t s, int n, int nrhs, const double *D, int ldd, double *X, int ldx);
+hipError_t copy_cols(hipStream_t s, int n, int nrhs, const double *S, int lds, double *D, int ldd);
+
+}  // namespace cdf
+
+#define CDF_HIP_TRY(expr)                                   \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return CDF_ERR_HIP;           \
+    } while (0)
+
+#define CDF_HIP_RET(expr)                                   \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return _e;                    \
+    } while (0)

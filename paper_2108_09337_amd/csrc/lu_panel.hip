@@ -1,0 +1,338 @@
+// LU panel factorization with partial pivoting (Sec. 7, routine A00 and the
+// column-by-column pivot search that partial pivoting requires, Sec. 7.3)
+// and row interchanges.
+//
+// Leaf kernel: factors an m x n (n <= 32) column block.  The rows are spread
+// over G workgroups (one per CU), each workgroup keeping its 256*R rows of
+// the block in LDS (column-major, so a column scan is contiguous).  Every
+// column costs one grid-wide exchange:
+//   1. each workgroup finds its best candidate (largest |a|, lowest row on
+//      ties) with wave shuffles and LDS, and publishes it with the
+//      candidate's whole row (and, if it owns it, the current row j);
+//   2. grid barrier;
+//   3. every workgroup reduces the G candidates identically, swaps rows j and
+//      p locally, scales column j by the pivot (division) and applies the
+//      rank-1 update to the remaining columns of the block.
+// Published slots are double-buffered by column parity, so one barrier per
+// column suffices.  With G = 1 the exchange stays in LDS.
+#include "internal.h"
+
+#include <climits>
+
+namespace {
+
+constexpr int LW = 32;   // leaf width (columns)
+constexpr int LT = 256;  // threads per workgroup
+constexpr int SL = LW + 2;  // slot stride in doubles: |a|, row index, row[LW]
+
+__device__ inline void better(double &bv, int &bi, double ov, int oi) {
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+}
+
+__device__ inline void grid_barrier(int *count, int target) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(count, 1);
+        while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+            __builtin_amdgcn_s_sleep(1);
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+template <int R>
+__global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__restrict__ A, int lda,
+                                                     int *__restrict__ ipiv, int row0,
+                                                     int *__restrict__ info, int info_base,
+                                                     double *__restrict__ slots, int *__restrict__ sync) {
+    constexpr int RT = LT * R;  // rows per workgroup
+    extern __shared__ double X[];  // X[c * RT + local row]
+    __shared__ double prow[LW];
+    __shared__ double oldj[LW];
+    __shared__ double wv[LT / 64];
+    __shared__ int wi[LT / 64];
+    __shared__ int ww[LT / 64];
+    __shared__ int s_p;
+    __shared__ int s_w;
+
+    const int G = gridDim.x;
+    const int g = blockIdx.x;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int rbase = g * RT;
+
+    if (t < LW) { prow[t] = 0.0; oldj[t] = 0.0; }
+    for (int c = 0; c < n; ++c)
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int r = rbase + s * LT + t;
+            X[c * RT + s * LT + t] = r < m ? A[(size_t)r + (size_t)c * lda] : 0.0;
+        }
+    double *rowj = slots + (size_t)2 * G * SL;
+    __syncthreads();
+
+    for (int j = 0; j < n; ++j) {
+        const int par = j & 1;
+        // 1. local candidate of column j among rows >= j
+        double bv = -1.0;
+        int bi = INT_MAX;
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int r = rbase + s * LT + t;
+            if (r < m && r >= j) better(bv, bi, fabs(X[j * RT + s * LT + t]), r);
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ov = __shfl_xor(bv, off);
+            const int oi = __shfl_xor(bi, off);
+            better(bv, bi, ov, oi);
+        }
+        if (lane == 0) { wv[wave] = bv; wi[wave] = bi; }
+        __syncthreads();
+        if (t == 0) {
+            double v = wv[0];
+            int i = wi[0];
+#pragma unroll
+            for (int w = 1; w < LT / 64; ++w) better(v, i, wv[w], wi[w]);
+            s_p = i;
+            wv[0] = v;
+        }
+        __syncthreads();
+        int p;
+        if (G == 1) {
+            p = s_p == INT_MAX ? j : s_p;  // no ordered candidate (NaN column): no interchange
+            if (t < n) {
+                prow[t] = X[t * RT + p];
+                oldj[t] = X[t * RT + j];
+            }
+            __syncthreads();
+        } else {
+            const int lp = s_p;
+            double *slot = slots + ((size_t)par * G + g) * SL;
+            if (t == 0) { slot[0] = wv[0]; slot[1] = (double)lp; }
+            if (lp != INT_MAX && t < n) slot[2 + t] = X[t * RT + (lp - rbase)];
+            if (j >= rbase && j < rbase + RT && t < n) rowj[(size_t)par * LW + t] = X[t * RT + (j - rbase)];
+            grid_barrier(sync, (j + 1) * G);
+            // 3. reduce the G candidates (identically in every workgroup)
+            double v = -1.0;
+            int i = INT_MAX, w = 0;
+            if (t < G) {
+                const double *o = slots + ((size_t)par * G + t) * SL;
+                v = o[0];
+                i = (int)o[1];
+                w = t;
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ov = __shfl_xor(v, off);
+                const int oi = __shfl_xor(i, off);
+                const int ow = __shfl_xor(w, off);
+                if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; w = ow; }
+            }
+            if (lane == 0) { wv[wave] = v; wi[wave] = i; ww[wave] = w; }
+            __syncthreads();
+            if (t == 0) {
+                double bv2 = wv[0];
+                int bi2 = wi[0], bw2 = ww[0];
+                for (int q = 1; q < LT / 64; ++q)
+                    if (wv[q] > bv2 || (wv[q] == bv2 && wi[q] < bi2)) { bv2 = wv[q]; bi2 = wi[q]; bw2 = ww[q]; }
+                s_p = bi2;
+                s_w = bw2;
+            }
+            __syncthreads();
+            p = s_p == INT_MAX ? j : s_p;
+            if (t < n) {
+                oldj[t] = rowj[(size_t)par * LW + t];
+                prow[t] = s_p == INT_MAX ? oldj[t] : slots[((size_t)par * G + s_w) * SL + 2 + t];
+            }
+            __syncthreads();
+        }
+        // swap rows j and p (local copies of both rows are in prow / oldj)
+        if (t < n) {
+            if (p != j && p >= rbase && p < rbase + RT) X[t * RT + (p - rbase)] = oldj[t];
+            if (j >= rbase && j < rbase + RT) X[t * RT + (j - rbase)] = prow[t];
+        }
+        const double piv = prow[j];
+        if (g == 0 && t == 0) {
+            ipiv[j] = row0 + p + 1;
+            if (piv == 0.0 && *info == 0) *info = info_base + j + 1;
+        }
+        __syncthreads();
+        if (piv != 0.0) {
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+                const int r = rbase + s * LT + t;
+                if (r < m && r > j) {
+                    const int rl = s * LT + t;
+                    const double l = X[j * RT + rl] / piv;
+                    X[j * RT + rl] = l;
+                    for (int c = j + 1; c < n; ++c) X[c * RT + rl] = fma(-l, prow[c], X[c * RT + rl]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int c = 0; c < n; ++c)
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int r = rbase + s * LT + t;
+            if (r < m) A[(size_t)r + (size_t)c * lda] = X[c * RT + s * LT + t];
+        }
+
+    if (G > 1) {
+        __syncthreads();
+        if (t == 0) {
+            const int old = atomicAdd(sync + 1, 1);
+            if (old == G - 1) {
+                atomicExch(sync, 0);
+                atomicExch(sync + 1, 0);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- interchanges
+
+constexpr int MAXSW = 64;          // interchanges per map
+constexpr int MAXPAIRS = 2 * MAXSW;
+
+// Builds the (dst, src) row pairs equivalent to applying the interchanges
+// ipiv[k1..k2) (absolute, 1-based, k2 - k1 <= 64) in order:
+//   new row dst[q] = old row src[q].
+// Executed by one full wave: the simulated positions (at most 128 distinct
+// rows) live in registers, two per lane, and are searched with ballots.
+// Returns the pair count (wave-uniform); dst/src are written to LDS.
+__device__ int build_pairs_wave(const int *__restrict__ ipiv, int k1, int k2, int nrows, int *dst, int *src) {
+    const int lane = threadIdx.x & 63;
+    int myp = (k1 + lane < k2) ? ipiv[k1 + lane] - 1 : -1;
+    if (myp < k1 + lane || myp >= nrows) myp = k1 + lane;  // out-of-range interchange: ignored
+    int pos0 = -1, cont0 = -1, pos1 = -1, cont1 = -1;
+    int np = 0;
+    for (int k = k1; k < k2; ++k) {
+        const int p = __shfl(myp, k - k1);
+        if (p == k) continue;
+        unsigned long long b0 = __ballot(pos0 == k), b1 = __ballot(pos1 == k);
+        int ik = b0 ? __builtin_ctzll(b0) : (b1 ? 64 + __builtin_ctzll(b1) : -1);
+        b0 = __ballot(pos0 == p);
+        b1 = __ballot(pos1 == p);
+        int ip = b0 ? __builtin_ctzll(b0) : (b1 ? 64 + __builtin_ctzll(b1) : -1);
+        if (ik < 0) {
+            if (lane == (np & 63)) { if (np < 64) { pos0 = k; cont0 = k; } else { pos1 = k; cont1 = k; } }
+            ik = np++;
+        }
+        if (ip < 0) {
+            if (lane == (np & 63)) { if (np < 64) { pos0 = p; cont0 = p; } else { pos1 = p; cont1 = p; } }
+            ip = np++;
+        }
+        const int ck = ik < 64 ? __shfl(cont0, ik) : __shfl(cont1, ik - 64);
+        const int cp = ip < 64 ? __shfl(cont0, ip) : __shfl(cont1, ip - 64);
+        if (lane == (ik & 63)) { if (ik < 64) cont0 = cp; else cont1 = cp; }
+        if (lane == (ip & 63)) { if (ip < 64) cont0 = ck; else cont1 = ck; }
+    }
+    // compaction of the moved positions
+    const bool m0 = pos0 >= 0 && cont0 != pos0;
+    const bool m1 = pos1 >= 0 && cont1 != pos1;
+    const unsigned long long bm0 = __ballot(m0), bm1 = __ballot(m1);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int c0 = __popcll(bm0);
+    if (m0) { const int q = __popcll(bm0 & below); dst[q] = pos0; src[q] = cont0; }
+    if (m1) { const int q = c0 + __popcll(bm1 & below); dst[q] = pos1; src[q] = cont1; }
+    return c0 + __popcll(bm1);
+}
+
+// Applies interchanges ipiv[k1..k2) (k2 - k1 <= 64) to the ncols columns of
+// A, 64 columns per workgroup: all rows moved are read before any is written.
+template <typename T>
+__global__ __launch_bounds__(256) void laswp_kernel(int ncols, T *__restrict__ A, int lda,
+                                                    const int *__restrict__ ipiv, int k1, int k2, int nrows) {
+    __shared__ int dst[MAXPAIRS], src[MAXPAIRS];
+    __shared__ int s_np;
+    if (threadIdx.x < 64) {
+        const int np = build_pairs_wave(ipiv, k1, k2, nrows, dst, src);
+        if (threadIdx.x == 0) s_np = np;
+    }
+    __syncthreads();
+    const int np = s_np;
+    if (np == 0) return;
+    const int cbase = blockIdx.x * 64;
+    const int total = np * 64;
+    constexpr int PER = MAXPAIRS * 64 / 256;
+    T v[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int e = threadIdx.x + 256 * r;
+        if (e < total) {
+            const int q = e % np, c = cbase + e / np;
+            if (c < ncols) v[r] = A[(size_t)src[q] + (size_t)c * lda];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int e = threadIdx.x + 256 * r;
+        if (e < total) {
+            const int q = e % np, c = cbase + e / np;
+            if (c < ncols) A[(size_t)dst[q] + (size_t)c * lda] = v[r];
+        }
+    }
+}
+
+template <typename T>
+hipError_t laswp_impl(hipStream_t s, int c0, int c1, T *A, int lda, const int *ipiv, int k1, int k2,
+                      int nrows) {
+    // columns [c0, c1) ; interchanges in chunks of MAXSW
+    const int ncols = c1 - c0;
+    if (ncols <= 0 || k2 <= k1) return hipSuccess;
+    for (int kk = k1; kk < k2; kk += MAXSW) {
+        const int ke = min(k2, kk + MAXSW);
+        hipLaunchKernelGGL((laswp_kernel<T>), dim3((ncols + 63) / 64), dim3(256), 0, s, ncols,
+                           A + (size_t)c0 * lda, lda, ipiv, kk, ke, nrows);
+        CDF_HIP_RET(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+namespace cdf {
+
+hipError_t lu_leaf(cdf_handle_t h, int m, int n, double *A, int lda, int *ipiv, int row0, int *info,
+                   int info_base, int rows_per_thread) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    if (n > LW || n > m) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&lu_leaf_kernel<1>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, LW * LT * 8));
+        CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&lu_leaf_kernel<2>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, LW * LT * 2 * 8));
+        attr = true;
+    }
+    int R = rows_per_thread;
+    if (R != 1 && R != 2) R = (m + LT - 1) / LT > h->num_cus / 2 ? 2 : 1;
+    int G = (m + LT * R - 1) / (LT * R);
+    if (G > h->num_cus && R == 1) { R = 2; G = (m + LT * R - 1) / (LT * R); }
+    if (G > h->num_cus) return hipErrorInvalidValue;
+    double *slots = static_cast<double *>(h->ws);  // caller reserved (2*G*SL + 2*LW) doubles
+    int *sync = h->sync;
+    void *args[] = {&m, &n, &A, &lda, &ipiv, &row0, &info, &info_base, &slots, &sync};
+    const void *fn = R == 1 ? reinterpret_cast<const void *>(&lu_leaf_kernel<1>)
+                            : reinterpret_cast<const void *>(&lu_leaf_kernel<2>);
+    const size_t lds = (size_t)LW * LT * R * sizeof(double);
+    if (G == 1) return hipLaunchKernel(fn, dim3(1), dim3(LT), args, lds, h->stream);
+    return hipLaunchCooperativeKernel(fn, dim3(G), dim3(LT), args, (unsigned)lds, h->stream);
+}
+
+hipError_t laswp(hipStream_t s, int c0, int c1, double *A, int lda, const int *ipiv, int k1, int k2,
+                 int nrows) {
+    return laswp_impl<double>(s, c0, c1, A, lda, ipiv, k1, k2, nrows);
+}
+
+hipError_t slaswp(hipStream_t s, int c0, int c1, float *A, int lda, const int *ipiv, int k1, int k2,
+                  int nrows) {
+    return laswp_impl<float>(s, c0, c1, A, lda, ipiv, k1, k2, nrows);
+}
+
+}  // namespace cdf

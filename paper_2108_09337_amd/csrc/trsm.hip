@@ -1,0 +1,169 @@
+// Triangular solves (Sec. 7, routines A10 / A01: local trsm; Table 1) and
+// the blocked solves used by the factor-solve calls.
+//
+// Small solves keep a strip of the right-hand block in LDS and walk the
+// triangle one row/column at a time; the triangle's column (or row) for
+// each step is read from L2 (the triangle is at most 256 x 256).
+//   left kinds : B (nb x ncols), 32 columns per workgroup, 8 row groups
+//   right kind : B (nrows x nb), 64 rows per workgroup, 4 column groups
+#include "internal.h"
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int LNC = 32;          // columns per workgroup (left solves)
+constexpr int LPAD = LNC + 1;
+constexpr int RNR = 64;          // rows per workgroup (right solve)
+constexpr int MAXNB = 256;
+
+template <int KIND>
+__global__ __launch_bounds__(NT) void trsm_left_kernel(int nb, int ncols, const double *__restrict__ T,
+                                                       int ldt, double *__restrict__ B, int ldb,
+                                                       const int *stop) {
+    if (stop != nullptr && *stop != 0) return;
+    extern __shared__ double X[];  // X[r * LPAD + c]
+    const int t = threadIdx.x;
+    const int c = t % LNC, rg = t / LNC;  // 8 row groups
+    const int c0 = blockIdx.x * LNC;
+    for (int e = t; e < nb * LNC; e += NT) {
+        const int r = e % nb, cc = e / nb;
+        X[r * LPAD + cc] = (c0 + cc < ncols) ? B[(size_t)r + (size_t)(c0 + cc) * ldb] : 0.0;
+    }
+    __syncthreads();
+    constexpr bool forward = (KIND == cdf::TRSM_LLNU || KIND == cdf::TRSM_LLNN);
+    constexpr bool unit = (KIND == cdf::TRSM_LLNU);
+    for (int s = 0; s < nb; ++s) {
+        const int j = forward ? s : nb - 1 - s;
+        if (!unit) {
+            if (rg == (j & 7)) X[j * LPAD + c] = X[j * LPAD + c] / T[(size_t)j + (size_t)j * ldt];
+            __syncthreads();
+        }
+        const double xj = X[j * LPAD + c];
+        if (forward) {
+            for (int i = j + 1 + ((rg - (j + 1)) & 7); i < nb; i += 8)
+                X[i * LPAD + c] = fma(-T[(size_t)i + (size_t)j * ldt], xj, X[i * LPAD + c]);
+        } else if (KIND == cdf::TRSM_LUNN) {
+            for (int i = rg; i < j; i += 8)
+                X[i * LPAD + c] = fma(-T[(size_t)i + (size_t)j * ldt], xj, X[i * LPAD + c]);
+        } else {  // TRSM_LLTN: (L^T)(i, j) = L(j, i)
+            for (int i = rg; i < j; i += 8)
+                X[i * LPAD + c] = fma(-T[(size_t)j + (size_t)i * ldt], xj, X[i * LPAD + c]);
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < nb * LNC; e += NT) {
+        const int r = e % nb, cc = e / nb;
+        if (c0 + cc < ncols) B[(size_t)r + (size_t)(c0 + cc) * ldb] = X[r * LPAD + cc];
+    }
+}
+
+// B (nrows x nb) <- B L^-T with L lower, non-unit: column j of the result is
+// (B(:, j) - sum_{c<j} X(:, c) L(j, c)) / L(j, j), done right-looking.
+__global__ __launch_bounds__(NT) void trsm_rltn_kernel(int nb, int nrows, const double *__restrict__ T,
+                                                       int ldt, double *__restrict__ B, int ldb,
+                                                       const int *stop) {
+    if (stop != nullptr && *stop != 0) return;
+    extern __shared__ double X[];  // X[c * RNR + r]
+    const int t = threadIdx.x;
+    const int r = t % RNR, cg = t / RNR;  // 4 column groups
+    const int r0 = blockIdx.x * RNR;
+    const bool live = r0 + r < nrows;
+    for (int cc = cg; cc < nb; cc += 4)
+        X[cc * RNR + r] = live ? B[(size_t)(r0 + r) + (size_t)cc * ldb] : 0.0;
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (cg == (j & 3)) X[j * RNR + r] = X[j * RNR + r] / T[(size_t)j + (size_t)j * ldt];
+        __syncthreads();
+        const double xj = X[j * RNR + r];
+        for (int cc = j + 1 + ((cg - (j + 1)) & 3); cc < nb; cc += 4)
+            X[cc * RNR + r] = fma(-xj, T[(size_t)cc + (size_t)j * ldt], X[cc * RNR + r]);
+        __syncthreads();
+    }
+    if (live)
+        for (int cc = cg; cc < nb; cc += 4) B[(size_t)(r0 + r) + (size_t)cc * ldb] = X[cc * RNR + r];
+}
+
+template <int KIND>
+hipError_t launch_left(hipStream_t s, int nb, int ncols, const double *T, int ldt, double *B, int ldb,
+                       const int *stop) {
+    static bool attr = false;
+    const size_t lds = (size_t)nb * LPAD * sizeof(double);
+    if (!attr) {
+        CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&trsm_left_kernel<KIND>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        MAXNB * LPAD * sizeof(double)));
+        attr = true;
+    }
+    hipLaunchKernelGGL((trsm_left_kernel<KIND>), dim3((ncols + LNC - 1) / LNC), dim3(NT), lds, s, nb, ncols,
+                       T, ldt, B, ldb, stop);
+    return hipGetLastError();
+}
+
+hipError_t launch_right(hipStream_t s, int nb, int nrows, const double *T, int ldt, double *B, int ldb,
+                        const int *stop) {
+    static bool attr = false;
+    const size_t lds = (size_t)nb * RNR * sizeof(double);
+    if (!attr) {
+        CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&trsm_rltn_kernel),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        MAXNB * RNR * sizeof(double)));
+        attr = true;
+    }
+    hipLaunchKernelGGL(trsm_rltn_kernel, dim3((nrows + RNR - 1) / RNR), dim3(NT), lds, s, nb, nrows, T, ldt,
+                       B, ldb, stop);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+namespace cdf {
+
+hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
+                      double *B, int ldb, const int *stop) {
+    if (nb <= 0 || ncols <= 0) return hipSuccess;
+    if (nb > MAXNB) return hipErrorInvalidValue;
+    switch (kind) {
+        case TRSM_LLNU: return launch_left<TRSM_LLNU>(s, nb, ncols, T, ldt, B, ldb, stop);
+        case TRSM_LLNN: return launch_left<TRSM_LLNN>(s, nb, ncols, T, ldt, B, ldb, stop);
+        case TRSM_LLTN: return launch_left<TRSM_LLTN>(s, nb, ncols, T, ldt, B, ldb, stop);
+        case TRSM_LUNN: return launch_left<TRSM_LUNN>(s, nb, ncols, T, ldt, B, ldb, stop);
+        case TRSM_RLTN: return launch_right(s, nb, ncols, T, ldt, B, ldb, stop);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Blocked solve with an n x n triangle: 128-wide diagonal solves, the rest
+// of the right-hand block updated with the FP64 GEMM.
+hipError_t trsm_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const double *T, int ldt,
+                        double *B, int ldb) {
+    constexpr int BS = 128;
+    if (n <= 0 || ncols <= 0) return hipSuccess;
+    if (kind == TRSM_LLNU || kind == TRSM_LLNN) {
+        for (int k = 0; k < n; k += BS) {
+            const int kb = min(BS, n - k);
+            CDF_HIP_RET(trsm_small(s, kind, kb, ncols, T + k + (size_t)k * ldt, ldt, B + k, ldb));
+            if (k + kb < n)
+                CDF_HIP_RET(dgemm(s, 0, 0, n - k - kb, ncols, kb, -1.0, T + (k + kb) + (size_t)k * ldt, ldt,
+                                  B + k, ldb, 1.0, B + k + kb, ldb, false));
+        }
+        return hipSuccess;
+    }
+    if (kind == TRSM_LUNN || kind == TRSM_LLTN) {
+        const int last = ((n - 1) / BS) * BS;
+        for (int k = last; k >= 0; k -= BS) {
+            const int kb = min(BS, n - k);
+            CDF_HIP_RET(trsm_small(s, kind, kb, ncols, T + k + (size_t)k * ldt, ldt, B + k, ldb));
+            if (k > 0) {
+                if (kind == TRSM_LUNN)
+                    CDF_HIP_RET(dgemm(s, 0, 0, k, ncols, kb, -1.0, T + (size_t)k * ldt, ldt, B + k, ldb, 1.0, B,
+                                      ldb, false));
+                else  // rows [0,k) -= L(k:k+kb, 0:k)^T X(k:k+kb)
+                    CDF_HIP_RET(dgemm(s, 1, 0, k, ncols, kb, -1.0, T + k, ldt, B + k, ldb, 1.0, B, ldb, false));
+            }
+        }
+        return hipSuccess;
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace cdf

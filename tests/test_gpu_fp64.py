@@ -1,0 +1,222 @@
+"""FP64 parity of the HIP path against the CPU oracle (needs an MI355X).
+
+Every call goes through the C-ABI (libcdnafact.so) via the thin binding.
+Pivots must be identical to the oracle's; factors agree elementwise within
+the rounding-order tolerance of tests/gpu_util.py; the scaled backward error
+||PA - LU||_F / (||A||_F n eps) must be <= 10.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from tests import golden_cases, gpu_util
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2108_09337_amd as cdf  # noqa: E402
+
+CASES = golden_cases.load()
+
+
+def _lu_gpu(a, **params):
+    h = cdf.handle()
+    for k, v in params.items():
+        h.set_param(k, v)
+    try:
+        A = cdf.to_device(a)
+        n = a.shape[0]
+        ipiv = torch.zeros(max(n, 1), dtype=torch.int32, device="cuda")
+        info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+        cdf.dgetrf(A, ipiv, info)
+        torch.cuda.synchronize()
+        return cdf.to_host(A), ipiv.cpu().numpy()[:n], int(info.item())
+    finally:
+        for k in params:
+            h.set_param(k, 0)
+
+
+def _chol_gpu(a, **params):
+    h = cdf.handle()
+    for k, v in params.items():
+        h.set_param(k, v)
+    try:
+        A = cdf.to_device(a)
+        info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+        cdf.dpotrf(A, info)
+        torch.cuda.synchronize()
+        return cdf.to_host(A), int(info.item())
+    finally:
+        for k in params:
+            h.set_param(k, 0)
+
+
+@pytest.mark.parametrize("name", [n for n, c in CASES.items() if c["kind"] == "lu"])
+def test_lu_hand_worked_bitwise(oracle_mod, name):
+    c = CASES[name]
+    a = golden_cases.as_f64(c["A"])
+    lu, ipiv, info = _lu_gpu(a)
+    assert list(ipiv) == c["ipiv"] and info == c["info"]
+    L, U = oracle_mod.split_lu(lu)
+    assert np.array_equal(L, golden_cases.as_f64(c["L"]))
+    assert np.array_equal(U, golden_cases.as_f64(c["U"]))
+
+
+@pytest.mark.parametrize("name", [n for n, c in CASES.items() if c["kind"] == "chol"])
+def test_chol_hand_worked_bitwise(oracle_mod, name):
+    c = CASES[name]
+    a = golden_cases.as_f64(c["A"])
+    l, info = _chol_gpu(a)
+    assert info == c["info"]
+    if not info:
+        assert np.array_equal(np.tril(l), golden_cases.as_f64(c["L"]))
+    assert np.array_equal(np.triu(l, 1), np.triu(a, 1))
+
+
+@pytest.mark.parametrize("n,nb", [(1, 0), (2, 0), (3, 0), (31, 0), (32, 0), (33, 0), (100, 0), (255, 0),
+                                  (256, 0), (257, 0), (513, 0), (1024, 0), (1500, 0), (700, 64), (700, 96)])
+def test_lu_parity_random(oracle_mod, n, nb):
+    a = workloads.lu_uniform(n, seed=1000 + n)
+    lu_or, ip_or, info_or = oracle_mod.dgetrf(a)
+    lu, ip, info = _lu_gpu(a, lu_nb=nb)
+    assert info == info_or == 0
+    if not np.array_equal(ip, ip_or):
+        pytest.fail(gpu_util.first_pivot_mismatch(ip, ip_or, a, oracle_mod))
+    tol = gpu_util.lu_parity_tolerance(lu_or)
+    assert np.all(np.abs(lu - lu_or) <= tol), float(np.max(np.abs(lu - lu_or) / tol))
+    assert np.all(np.abs(np.tril(lu, -1)) <= 1.0)
+    assert oracle_mod.lu_backward_error(a, lu, ip) <= 10.0
+
+
+@pytest.mark.parametrize("rows", [1, 2])
+def test_lu_leaf_multi_workgroup(oracle_mod, rows):
+    """Tall enough that the panel leaf spreads over many workgroups (grid exchange)."""
+    n = 2304
+    a = workloads.lu_uniform(n, seed=77)
+    lu_or, ip_or, _ = oracle_mod.dgetrf(a)
+    lu, ip, info = _lu_gpu(a, lu_leaf_rows=rows)
+    assert info == 0
+    if not np.array_equal(ip, ip_or):
+        pytest.fail(gpu_util.first_pivot_mismatch(ip, ip_or, a, oracle_mod))
+    assert oracle_mod.lu_backward_error(a, lu, ip) <= 10.0
+
+
+def test_lu_singular_info(oracle_mod):
+    n = 300
+    a = workloads.lu_uniform(n, seed=5)
+    a[:, 137] = 0.0  # exactly zero column -> first zero pivot at step 137
+    _, ip_or, info_or = oracle_mod.dgetrf(a)
+    lu, ip, info = _lu_gpu(a)
+    assert info == info_or == 138
+    assert np.array_equal(ip, ip_or)
+    z = np.zeros((40, 40), order="F")
+    _, ipz, infoz = _lu_gpu(z)
+    assert infoz == 1 and np.array_equal(ipz, np.arange(1, 41))
+
+
+def test_lu_diag_dominant_identity_pivots():
+    a = workloads.diag_dominant(600, seed=0)
+    _, ip, info = _lu_gpu(a)
+    assert info == 0 and np.array_equal(ip, np.arange(1, 601))
+
+
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (300, 1), (1024, 1), (777, 5), (1024, 64)])
+def test_getrs(oracle_mod, n, nrhs):
+    a = workloads.lu_uniform(n, seed=n)
+    b = workloads.rhs_uniform(n, nrhs, seed=n + 1)
+    lu_or, ip_or, _ = oracle_mod.dgetrf(a)
+    x_or = oracle_mod.dgetrs(lu_or, ip_or, b)
+    A = cdf.to_device(a)
+    ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cdf.dgetrf(A, ipiv, info)
+    B = cdf.to_device(b)
+    cdf.dgetrs(A, ipiv, B)
+    x = cdf.to_host(B)
+    assert oracle_mod.hpl_scaled_residual(a, x, b) <= 16
+    kappa = np.linalg.cond(a, np.inf)
+    assert np.max(np.abs(x - x_or)) <= 2 * 16 * n * oracle_mod.EPS * kappa * np.max(np.abs(x_or))
+
+
+@pytest.mark.parametrize("n,nb", [(1, 0), (2, 0), (5, 0), (64, 0), (127, 0), (128, 0), (129, 0), (400, 0),
+                                  (1000, 0), (1300, 64), (700, 96)])
+def test_chol_parity_random(oracle_mod, n, nb):
+    a = workloads.spd_bbt(n, seed=2000 + n)
+    l_or, info_or = oracle_mod.dpotrf(a)
+    l, info = _chol_gpu(a, chol_nb=nb)
+    assert info == info_or == 0
+    tol = gpu_util.chol_parity_tolerance(l_or)
+    d = np.abs(np.tril(l) - np.tril(l_or))
+    assert np.all(d <= tol), float(np.max(d / tol))
+    assert np.array_equal(np.triu(l, 1), np.triu(a, 1)), "upper triangle was written"
+    assert oracle_mod.chol_backward_error(a, l) <= 10.0
+
+
+@pytest.mark.parametrize("n,bad", [(300, 0), (300, 150), (300, 299), (260, 128)])
+def test_chol_not_spd_info(oracle_mod, n, bad):
+    a = workloads.spd_bbt(n, seed=3)
+    a[bad, bad] = -1.0
+    _, info_or = oracle_mod.dpotrf(a)
+    l, info = _chol_gpu(a)
+    assert info == info_or
+    # columns of finished blocks before the failing one agree with the oracle
+    lo, _ = oracle_mod.dpotrf(a, ksteps=(bad // 128) * 128)
+    k = (bad // 128) * 128
+    assert np.allclose(np.tril(l)[:, :k], np.tril(lo)[:, :k], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (500, 1), (1024, 64), (333, 3)])
+def test_potrs(oracle_mod, n, nrhs):
+    a = workloads.spd_bbt(n, seed=n)
+    b = workloads.rhs_uniform(n, nrhs, seed=n + 2)
+    l_or, _ = oracle_mod.dpotrf(a)
+    x_or = oracle_mod.dpotrs(l_or, b)
+    A = cdf.to_device(a)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cdf.dpotrf(A, info)
+    B = cdf.to_device(b)
+    cdf.dpotrs(A, B)
+    x = cdf.to_host(B)
+    assert oracle_mod.hpl_scaled_residual(a, x, b) <= 16
+    assert np.max(np.abs(x - x_or)) <= 1e-12 * np.max(np.abs(x_or)) * n
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (128, 128, 16), (129, 130, 17), (300, 77, 256), (1000, 1000, 256),
+                                   (17, 513, 5)])
+def test_dgemm_update(m, n, k):
+    rng = np.random.default_rng(m * 7 + n + k)
+    a = np.asfortranarray(rng.uniform(-1, 1, (m, k)))
+    b = np.asfortranarray(rng.uniform(-1, 1, (k, n)))
+    c = np.asfortranarray(rng.uniform(-1, 1, (m, n)))
+    C = cdf.to_device(c)
+    cdf.dgemm_update(cdf.to_device(a), cdf.to_device(b), C)
+    ref = c - a @ b
+    got = cdf.to_host(C)
+    assert np.max(np.abs(got - ref)) <= 4 * k * gpu_util.EPS * (np.abs(a) @ np.abs(b) + np.abs(c)).max()
+
+
+def test_invalid_arguments():
+    h = cdf.handle()
+    L = cdf.lib()
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    st = L.cdf_dgetrf(h.bind_stream(), -1, None, 1, None, cdf._p(info))
+    assert st == cdf.CDF_ERR_INVALID_ARG and L.cdf_last_bad_arg(h.ptr) == 2
+    A = cdf.cm_empty(4, 4)
+    st = L.cdf_dgetrf(h.bind_stream(), 4, cdf._p(A), 3, cdf._p(info), cdf._p(info))
+    assert st == cdf.CDF_ERR_INVALID_ARG and L.cdf_last_bad_arg(h.ptr) == 4
+    st = L.cdf_dpotrf(h.bind_stream(), b"U", 4, cdf._p(A), 4, cdf._p(info))
+    assert st == cdf.CDF_ERR_UNSUPPORTED
+    st = L.cdf_dpotrf(h.bind_stream(), b"X", 4, cdf._p(A), 4, cdf._p(info))
+    assert st == cdf.CDF_ERR_INVALID_ARG and L.cdf_last_bad_arg(h.ptr) == 2
+    st = L.cdf_dgetrs(h.bind_stream(), b"N", 4, -2, cdf._p(A), 4, cdf._p(info), cdf._p(A), 4)
+    assert st == cdf.CDF_ERR_INVALID_ARG and L.cdf_last_bad_arg(h.ptr) == 4
+    # n = 0 is a no-op that reports info = 0
+    info.fill_(5)
+    assert L.cdf_dgetrf(h.bind_stream(), 0, None, 1, None, cdf._p(info)) == cdf.CDF_OK
+    torch.cuda.synchronize()
+    assert info.item() == 0
+    with pytest.raises(cdf.CdfError):
+        h.set_param("lu_nb", 33)
