@@ -77,7 +77,8 @@ typedef enum {
     CDF_PARAM_LU_NB = 0,         /* LU outer panel width (multiple of 32) */
     CDF_PARAM_CHOL_NB = 1,       /* Cholesky outer block width (multiple of 32) */
     CDF_PARAM_LU_LEAF_ROWS = 2,  /* rows per thread in the LU panel leaf (1 or 2) */
-    CDF_PARAM_COUNT = 3
+    CDF_PARAM_MIXED_NB = 3,      /* block width of the mixed-precision factorizations (multiple of 32) */
+    CDF_PARAM_COUNT = 4
 } cdf_param_t;
 CDF_API cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value);
 CDF_API int cdf_get_param(cdf_handle_t h, cdf_param_t p);
@@ -159,31 +160,60 @@ CDF_API cdf_status_t cdf_dposv_mixed(cdf_handle_t h, cdf_update_prec_t p, int n,
                              int *iters, double *scaled_resid, int *info);
 
 /*
+ * The factorization step of cdf_dgesv_mixed on its own: W <- binary32(A),
+ * then blocked LU of W with a binary64 panel (pivot search, interchanges,
+ * L11^-1 A12) and the trailing update in precision p (BF16, FP16 or E4M3,
+ * 128-row / 128-column scale tiles, binary32 accumulation).
+ *   A device n x n (not modified); W device float n x n (ldw >= n), on exit
+ *   the binary32 factors as for cdf_dgetrf; ipiv device int[n] (1-based);
+ *   info device int as for cdf_dgetrf.
+ */
+CDF_API cdf_status_t cdf_sgetrf_mixed(cdf_handle_t h, cdf_update_prec_t p, int n, const double *A, int lda,
+                                      float *W, int ldw, int *ipiv, int *info);
+
+/*
+ * The factorization step of cdf_dposv_mixed on its own: lower(W) <-
+ * binary32(lower(A)), then blocked lower Cholesky of W with binary64
+ * diagonal blocks and L21 solves and the trailing update in precision p.
+ * The strict upper triangle of W is not written.
+ */
+CDF_API cdf_status_t cdf_spotrf_mixed(cdf_handle_t h, cdf_update_prec_t p, char uplo, int n, const double *A,
+                                      int lda, float *W, int ldw, int *info);
+
+/*
  * Quantize an m x n binary32 matrix tile by tile (the operand encoding of
  * the low-precision trailing update).  Tiles are tm x tn blocks anchored at
  * (0, 0).  For each tile, e = floor(log2(maxfinite / amax)) (capped at 64;
  * 0 for an all-zero tile; always 0 for BF16) and every element is encoded
  * as the format's nearest value (ties to even, E4M3 saturating) of x * 2^e.
  *   p     CDF_UPD_BF16, CDF_UPD_FP16 or CDF_UPD_FP8E4M3
- *   X     device float, ldx >= m; Q device codes (2 bytes for BF16/FP16,
- *         1 byte for E4M3), leading dimension ldq >= m (in elements)
+ *   X     device float, ldx >= m
+ *   Q     device codes (2 bytes for BF16/FP16, 1 byte for E4M3), column-major
+ *         with leading dimension ldq >= m (in elements).  Rows [m, min(ldq,
+ *         32*ceil(m/32))) are written as zero codes (the padding the update
+ *         reads).
  *   exps  device int[ceil(m/tm) * ceil(n/tn)], tile (ti, tj) at ti + tj*ceil(m/tm)
  */
 CDF_API cdf_status_t cdf_quantize(cdf_handle_t h, cdf_update_prec_t p, int m, int n, const float *X, int ldx,
                           int tm, int tn, void *Q, int ldq, int *exps);
 
 /*
- * Low-precision Schur-complement update C <- C - dq(QA) dq(QB) with binary32
- * accumulation, where dq(Q) = decode(Q) * 2^-e per tile (Sec. 7, routine
- * A11, in the update precision).  QA is m x k in tiles of tm x k, QB is
- * k x n in tiles of k x tn, as produced by cdf_quantize; tm and tn must be
- * the tile sizes the library uses (cdf_update_tile()).
- *   C device float m x n (ldc >= m).
+ * Low-precision Schur-complement update C <- C - dq(A) dq(B) with binary32
+ * accumulation (Sec. 7, routine A11, in the update precision), where dq
+ * multiplies each code's value by 2^-e of its tile.  Operands are given
+ * K-contiguous, as cdf_quantize writes them with tm = k and tn = T
+ * (T = cdf_update_tile(p)):
+ *   QA    codes of A^T (k x m, leading dimension lda); ea[i] is the exponent
+ *         of rows [T*i, T*i+T) of A
+ *   QB    codes of B (k x n, leading dimension ldb); eb[j] is the exponent of
+ *         columns [T*j, T*j+T) of B
+ *   lda, ldb multiples of 32 and >= 32*ceil(k/32); codes of rows [k, lda) are zero
+ *   C     device float m x n (ldc >= m)
  */
 CDF_API cdf_status_t cdf_lowp_update(cdf_handle_t h, cdf_update_prec_t p, int m, int n, int k,
                              const void *QA, int lda, const int *ea, const void *QB, int ldb,
                              const int *eb, float *C, int ldc);
-/* Tile size (rows of QA tiles = columns of QB tiles) used by the low-precision update. */
+/* Tile size T of the low-precision update (rows of A / columns of B per scale). */
 CDF_API int cdf_update_tile(cdf_update_prec_t p);
 
 /*

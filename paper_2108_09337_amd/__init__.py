@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libcdnafact.so")
 
 CDF_OK, CDF_ERR_INVALID_ARG, CDF_ERR_HIP, CDF_ERR_ALLOC, CDF_ERR_NOT_CONVERGED, CDF_ERR_UNSUPPORTED = range(6)
 UPD = {"fp64": 0, "bf16": 1, "fp16": 2, "fp8e4m3": 3, "e4m3": 3}
-PARAM = {"lu_nb": 0, "chol_nb": 1, "lu_leaf_rows": 2}
+PARAM = {"lu_nb": 0, "chol_nb": 1, "lu_leaf_rows": 2, "mixed_nb": 3}
 F64, F32 = 0, 1
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
@@ -69,6 +69,8 @@ def lib() -> ctypes.CDLL:
         "cdf_dpotrs": (_i, [_vp, ctypes.c_char, _i, _i, _vp, _i, _vp, _i]),
         "cdf_dgesv_mixed": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _i, _c_int_p, _c_double_p, _vp]),
         "cdf_dposv_mixed": (_i, [_vp, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _i, _c_int_p, _c_double_p, _vp]),
+        "cdf_sgetrf_mixed": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp]),
+        "cdf_spotrf_mixed": (_i, [_vp, _i, ctypes.c_char, _i, _vp, _i, _vp, _i, _vp]),
         "cdf_quantize": (_i, [_vp, _i, _i, _i, _vp, _i, _i, _i, _vp, _i, _vp]),
         "cdf_lowp_update": (_i, [_vp, _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _vp, _i]),
         "cdf_update_tile": (_i, [_i]),
@@ -254,6 +256,22 @@ def dgesv_mixed(prec: str, A, B, X, info, max_iter: int = 30, h: Handle | None =
 def dposv_mixed(prec: str, A, B, X, info, max_iter: int = 30, h: Handle | None = None) -> dict:
     """Mixed-precision Cholesky + iterative refinement (see cdf_dposv_mixed)."""
     return _solve_mixed("cdf_dposv_mixed", prec, A, B, X, max_iter, info, h)
+
+
+def sgetrf_mixed(prec: str, A, W, ipiv, info, h: Handle | None = None) -> None:
+    """W <- binary32 LU factors of A with a low-precision update (see cdf_sgetrf_mixed)."""
+    h = h or handle(A.device)
+    n = A.shape[0]
+    _check("cdf_sgetrf_mixed", lib().cdf_sgetrf_mixed(h.bind_stream(), UPD[prec], n, _p(A), _ld(A), _p(W), _ld(W),
+                                                      _p(ipiv), _p(info)), h.ptr)
+
+
+def spotrf_mixed(prec: str, A, W, info, h: Handle | None = None) -> None:
+    """lower(W) <- binary32 Cholesky factor of A with a low-precision update (see cdf_spotrf_mixed)."""
+    h = h or handle(A.device)
+    n = A.shape[0]
+    _check("cdf_spotrf_mixed", lib().cdf_spotrf_mixed(h.bind_stream(), UPD[prec], b"L", n, _p(A), _ld(A), _p(W),
+                                                      _ld(W), _p(info)), h.ptr)
 
 
 def update_tile(prec: str) -> int:

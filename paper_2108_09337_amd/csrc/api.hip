@@ -32,30 +32,62 @@ inline int chol_nb(cdf_handle_t h) {
 // Slots for the LU leaf's grid exchange: 2 parities x (G x 34) + 2 x 32 doubles.
 constexpr size_t kLeafSlotBytes = (2 * 256 * 34 + 64) * sizeof(double) * 4;
 
-// Recursive panel factorization of columns [c0, c0 + w) over rows [c0, n):
-// factor the left half, form its U12 and update the right half, factor the
-// right half.  Leaves (<= 32 columns) apply their interchanges to every other
-// column of the matrix, so the whole matrix stays consistently permuted.
-hipError_t lu_panel(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int c0, int w) {
+}  // namespace
+
+namespace cdf {
+
+// Recursive panel factorization of columns [c0, c0 + w) over rows [c0, m) of
+// the m x ncols region A: factor the left half, form its U12 and update the
+// right half, factor the right half.  Leaves (<= 32 columns) apply their
+// interchanges to every other column of the region, so the region stays
+// consistently permuted.  Pivots are written relative to the region's row 0;
+// info values are offset by info_off.
+hipError_t lu_panel(cdf_handle_t h, int m, int ncols, double *A, int lda, int *ipiv, int *info, int c0, int w,
+                    int info_off) {
     hipStream_t s = h->stream;
     if (w <= 32) {
-        CDF_HIP_RET(cdf::lu_leaf(h, n - c0, w, A + c0 + (size_t)c0 * lda, lda, ipiv + c0, c0, info, c0,
-                                 h->params[CDF_PARAM_LU_LEAF_ROWS]));
-        CDF_HIP_RET(cdf::laswp(s, 0, c0, A, lda, ipiv, c0, c0 + w, n));
-        CDF_HIP_RET(cdf::laswp(s, c0 + w, n, A, lda, ipiv, c0, c0 + w, n));
+        CDF_HIP_RET(lu_leaf(h, m - c0, w, A + c0 + (size_t)c0 * lda, lda, ipiv + c0, c0, info, info_off + c0,
+                            h->params[CDF_PARAM_LU_LEAF_ROWS]));
+        CDF_HIP_RET(laswp(s, 0, c0, A, lda, ipiv, c0, c0 + w, m));
+        CDF_HIP_RET(laswp(s, c0 + w, ncols, A, lda, ipiv, c0, c0 + w, m));
         return hipSuccess;
     }
     const int n1 = ((w / 2 + 31) / 32) * 32;
     const int n2 = w - n1;
-    CDF_HIP_RET(lu_panel(h, n, A, lda, ipiv, info, c0, n1));
+    CDF_HIP_RET(lu_panel(h, m, ncols, A, lda, ipiv, info, c0, n1, info_off));
     double *a11 = A + c0 + (size_t)c0 * lda;
     double *a12 = A + c0 + (size_t)(c0 + n1) * lda;
     double *a21 = A + (c0 + n1) + (size_t)c0 * lda;
     double *a22 = A + (c0 + n1) + (size_t)(c0 + n1) * lda;
-    CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_LLNU, n1, n2, a11, lda, a12, lda));
-    CDF_HIP_RET(cdf::dgemm(s, 0, 0, n - c0 - n1, n2, n1, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false));
-    return lu_panel(h, n, A, lda, ipiv, info, c0 + n1, n2);
+    CDF_HIP_RET(trsm_small(s, TRSM_LLNU, n1, n2, a11, lda, a12, lda));
+    CDF_HIP_RET(dgemm(s, 0, 0, m - c0 - n1, n2, n1, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false));
+    return lu_panel(h, m, ncols, A, lda, ipiv, info, c0 + n1, n2, info_off);
 }
+
+// Blocked right-looking lower Cholesky of the n x n matrix A: potrf of each
+// diagonal block, trsm of the block column below it, triangular (lower
+// tiles only) update of the trailing matrix.  Stops (all later launches are
+// no-ops) once *info != 0; info values are offset by info_off.
+hipError_t potrf_blocked(cdf_handle_t h, int n, double *A, int lda, int *info, int info_off, int nb) {
+    hipStream_t s = h->stream;
+    for (int k = 0; k < n; k += nb) {
+        const int kb = nb < n - k ? nb : n - k;
+        double *a11 = A + k + (size_t)k * lda;
+        CDF_HIP_RET(potrf_diag(s, kb, a11, lda, info, info_off + k));
+        const int rest = n - k - kb;
+        if (rest > 0) {
+            double *a21 = A + (k + kb) + (size_t)k * lda;
+            double *a22 = A + (k + kb) + (size_t)(k + kb) * lda;
+            CDF_HIP_RET(trsm_small(s, TRSM_RLTN, kb, rest, a11, lda, a21, lda, info));
+            CDF_HIP_RET(dgemm(s, 0, 1, rest, rest, kb, -1.0, a21, lda, a21, lda, 1.0, a22, lda, true, info));
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace cdf
+
+namespace {
 
 hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info) {
     hipStream_t s = h->stream;
@@ -63,7 +95,7 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
     const int nb = lu_nb(h);
     for (int k = 0; k < n; k += nb) {
         const int kb = nb < n - k ? nb : n - k;
-        CDF_HIP_RET(lu_panel(h, n, A, lda, ipiv, info, k, kb));
+        CDF_HIP_RET(cdf::lu_panel(h, n, n, A, lda, ipiv, info, k, kb, 0));
         const int rest = n - k - kb;
         if (rest > 0) {
             double *a11 = A + k + (size_t)k * lda;
@@ -78,22 +110,8 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
 }
 
 hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
-    hipStream_t s = h->stream;
-    CDF_HIP_RET(cdf::fill_int(s, info, 1, 0));
-    const int nb = chol_nb(h);
-    for (int k = 0; k < n; k += nb) {
-        const int kb = nb < n - k ? nb : n - k;
-        double *a11 = A + k + (size_t)k * lda;
-        CDF_HIP_RET(cdf::potrf_diag(s, kb, a11, lda, info, k));
-        const int rest = n - k - kb;
-        if (rest > 0) {
-            double *a21 = A + (k + kb) + (size_t)k * lda;
-            double *a22 = A + (k + kb) + (size_t)(k + kb) * lda;
-            CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_RLTN, kb, rest, a11, lda, a21, lda, info));
-            CDF_HIP_RET(cdf::dgemm(s, 0, 1, rest, rest, kb, -1.0, a21, lda, a21, lda, 1.0, a22, lda, true, info));
-        }
-    }
-    return hipSuccess;
+    CDF_HIP_RET(cdf::fill_int(h->stream, info, 1, 0));
+    return cdf::potrf_blocked(h, n, A, lda, info, 0, chol_nb(h));
 }
 
 }  // namespace
@@ -199,6 +217,7 @@ cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value) {
         return bad(h, 3);
     if (p == CDF_PARAM_CHOL_NB && value > 128) return bad(h, 3);
     if (p == CDF_PARAM_LU_LEAF_ROWS && !(value == 0 || value == 1 || value == 2)) return bad(h, 3);
+    if (p == CDF_PARAM_MIXED_NB && value != 0 && (value % 32 != 0 || value > 256)) return bad(h, 3);
     h->params[p] = value;
     return CDF_OK;
 }

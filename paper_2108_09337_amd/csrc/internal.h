@@ -16,7 +16,7 @@ struct cdf_handle_s {
     size_t ws_limit = 0;         // 0 = no cap
     int *sync = nullptr;         // zeroed counters for grid-wide barriers
     int bad_arg = 0;
-    int params[CDF_PARAM_COUNT] = {0, 0, 0};
+    int params[CDF_PARAM_COUNT] = {0, 0, 0, 0};
 };
 
 namespace cdf {
@@ -43,6 +43,14 @@ hipError_t dgemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alph
 hipError_t lu_leaf(cdf_handle_t h, int m, int n, double *A, int lda, int *ipiv, int row0,
                    int *info, int info_base, int rows_per_thread);
 
+// Recursive LU panel of columns [c0, c0+w) of the m x ncols region A (rows
+// [c0, m)); interchanges are applied to all other columns of the region;
+// pivots are relative to the region's row 0; info offset by info_off.
+hipError_t lu_panel(cdf_handle_t h, int m, int ncols, double *A, int lda, int *ipiv, int *info, int c0,
+                    int w, int info_off);
+// Blocked lower Cholesky of an n x n matrix (block width nb <= 128).
+hipError_t potrf_blocked(cdf_handle_t h, int n, double *A, int lda, int *info, int info_off, int nb);
+
 // Apply interchanges ipiv[k1..k2) (absolute, 1-based) to rows of columns
 // [c0, c1) of A (nrows rows); an entry outside [k+1, nrows] is ignored.
 hipError_t laswp(hipStream_t s, int c0, int c1, double *A, int lda, const int *ipiv, int k1,
@@ -63,6 +71,9 @@ hipError_t slaswp(hipStream_t s, int c0, int c1, float *A, int lda, const int *i
 enum TrsmKind { TRSM_LLNU = 0, TRSM_LLNN = 1, TRSM_LLTN = 2, TRSM_LUNN = 3, TRSM_RLTN = 4 };
 hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
                       double *B, int ldb, const int *stop = nullptr);
+// Same with a binary32 right-hand block (arithmetic in binary64).
+hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
+                      float *B, int ldb, const int *stop = nullptr);
 
 // Full triangular solve with a large n x n factor (blocked: small diagonal
 // solves + GEMM updates).
@@ -79,11 +90,14 @@ hipError_t convert_d2s(hipStream_t s, int m, int n, const double *A, int lda, fl
                        bool lower_only);
 hipError_t convert_s2d(hipStream_t s, int m, int n, const float *W, int ldw, double *A, int lda,
                        bool lower_only);
+// transpose_out: Q[k + i*ldq] = code(X[i, k]) (K = columns of X), else
+// Q[i + j*ldq] = code(X[i, j]) (K = rows of X).  K is zero-padded up to
+// min(ldq, 32*ceil(K/32)).
 hipError_t quantize(hipStream_t s, int fmt, int m, int n, const float *X, int ldx, int tm, int tn,
                     void *Q, int ldq, int *exps, bool transpose_out);
 hipError_t lowp_update(hipStream_t s, int fmt, int m, int n, int k, const void *QA, int lda,
                        const int *ea, const void *QB, int ldb, const int *eb, float *C, int ldc,
-                       bool lower);
+                       bool lower, const int *stop);
 int lowp_tile(int fmt);
 
 // r = b - A x for nrhs columns, binary64 (A n x n); also writes per-column

@@ -1,24 +1,785 @@
-// Mixed-precision solvers (placeholder entry points, filled in below).
+// Mixed-precision factorizations: the trailing Schur-complement update
+// (Sec. 7, routine A11) runs on low-precision matrix cores (BF16, FP16 or
+// OCP E4M3 operands, binary32 accumulation) while the panel, pivot search,
+// triangular solves and diagonal-block Cholesky stay in binary64; binary64
+// iterative refinement with the original matrix recovers full accuracy
+// (low-precision LU with refinement is the related work of Sec. 11).
+//
+// Operand encoding: tiles of 128 rows of L21 (all nb columns) and of 128
+// columns of U12 carry one power-of-two scale 2^e each, e = floor(log2(
+// maxfinite / amax)); the product of two tiles is rescaled by 2^-(ea+eb)
+// once, exactly, after the binary32 accumulation.  Quantized operands are
+// stored K-contiguous (k + row * ld), K zero-padded to a multiple of 32.
 #include "internal.h"
+
+#include <cmath>
+#include <vector>
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+enum { FMT_BF16 = 1, FMT_FP16 = 2, FMT_E4M3 = 3 };
+constexpr int QT = 128;    // quantization tile = update tile
+constexpr int KSTEP = 32;  // K of one MFMA; quantized K is padded to this
+constexpr int NT = 256;
+
+// ------------------------------------------------------------- encoders
+// Round-to-nearest-even from a binary32 value, by integer arithmetic on
+// its bits (normal range) or an exact rescale and rint (subnormal range).
+
+__device__ inline unsigned short enc_bf16(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ inline unsigned short enc_f16(float y) {  // |y| <= 65504
+    const unsigned u = __float_as_uint(y);
+    const unsigned s = (u >> 16) & 0x8000u;
+    const unsigned a = u & 0x7fffffffu;
+    if ((int)(a >> 23) - 127 >= -14) {
+        const unsigned r = (a + 0xfffu + ((a >> 13) & 1u)) >> 13;
+        return (unsigned short)(s | (r - ((127u - 15u) << 10)));
+    }
+    return (unsigned short)(s | (unsigned)rintf(__uint_as_float(a) * 16777216.0f));
+}
+
+__device__ inline unsigned char enc_e4m3(float y) {  // saturating at 448
+    const unsigned u = __float_as_uint(y);
+    const unsigned s = (u >> 24) & 0x80u;
+    const unsigned a = u & 0x7fffffffu;
+    if (a >= 0x43e00000u) return (unsigned char)(s | 0x7eu);
+    if ((int)(a >> 23) - 127 >= -6) {
+        const unsigned r = (a + 0x7ffffu + ((a >> 20) & 1u)) >> 20;
+        const unsigned c = r - ((127u - 7u) << 3);
+        return (unsigned char)(s | (c > 0x7eu ? 0x7eu : c));
+    }
+    return (unsigned char)(s | (unsigned)rintf(__uint_as_float(a) * 512.0f));
+}
+
+// e = floor(log2(maxfinite / amax)) from the binary32 fields of amax, capped at 64.
+__device__ inline int tile_exp(int fmt, float amax) {
+    if (fmt == FMT_BF16 || !(amax > 0.0f)) return 0;
+    const unsigned u = __float_as_uint(amax);
+    const int ef = (int)(u >> 23);
+    if (ef == 0) return 64;
+    const int Ef = fmt == FMT_FP16 ? 15 : 8;
+    const unsigned mf = fmt == FMT_FP16 ? 0x7fe000u : 0x600000u;  // fraction bits of 65504 / 448
+    const int e = Ef - (ef - 127) - ((u & 0x7fffffu) > mf ? 1 : 0);
+    return e > 64 ? 64 : e;
+}
+
+template <int FMT>
+__device__ inline void put_code(void *Q, size_t off, float y) {
+    if (FMT == FMT_E4M3) static_cast<unsigned char *>(Q)[off] = enc_e4m3(y);
+    else if (FMT == FMT_FP16) static_cast<unsigned short *>(Q)[off] = enc_f16(y);
+    else static_cast<unsigned short *>(Q)[off] = enc_bf16(y);
+}
+
+__device__ inline float block_max(float v, float *red) {
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    float r = red[0];
+    for (int w = 1; w < NT / 64; ++w) r = fmaxf(r, red[w]);
+    return r;
+}
+
+// One workgroup per tile (tm x tn of X).  kdim is the K extent (columns of X
+// when trans, rows otherwise); codes for K in [kdim, kpad) are written as 0
+// by the tiles on the K boundary.  trans: X rows are the output rows
+// (Q[k + i*ldq] = code(X[i, k])), via an LDS transpose; else Q[i + j*ldq] = code(X[i, j]).
+template <int FMT>
+__global__ __launch_bounds__(NT) void quantize_kernel(int m, int n, const float *__restrict__ X, int ldx, int tm,
+                                                      int tn, void *__restrict__ Q, int ldq, int *__restrict__ exps,
+                                                      int kpad, int trans) {
+    __shared__ float red[NT / 64];
+    __shared__ float chunk[64][65];
+    const int ti = blockIdx.x, tj = blockIdx.y;
+    const int i0 = ti * tm, j0 = tj * tn;
+    const int i1 = min(i0 + tm, m), j1 = min(j0 + tn, n);
+    const int h = i1 - i0, w = j1 - j0;
+    const int t = threadIdx.x;
+    float amax = 0.0f;
+    for (int e = t; e < h * w; e += NT) {
+        const int i = i0 + e % h, j = j0 + e / h;
+        amax = fmaxf(amax, fabsf(X[(size_t)i + (size_t)j * ldx]));
+    }
+    amax = block_max(amax, red);
+    const int ex = tile_exp(FMT, amax);
+    if (t == 0) exps[ti + tj * gridDim.x] = ex;
+    if (!trans) {
+        // rows are K; pad rows [m, kpad) with zeros on the last row tile
+        const int iend = (i1 == m) ? max(kpad, m) : i1;
+        const int hh = iend - i0;
+        for (int e = t; e < hh * w; e += NT) {
+            const int i = i0 + e % hh, j = j0 + e / hh;
+            const float y = i < m ? ldexpf(X[(size_t)i + (size_t)j * ldx], ex) : 0.0f;
+            put_code<FMT>(Q, (size_t)i + (size_t)j * ldq, y);
+        }
+        return;
+    }
+    // columns are K; pad columns [n, kpad) with zeros on the last column tile
+    const int jend = (j1 == n) ? max(kpad, n) : j1;
+    for (int ib = i0; ib < i1; ib += 64)
+        for (int jb = j0; jb < jend; jb += 64) {
+            __syncthreads();
+            for (int e = t; e < 64 * 64; e += NT) {
+                const int r = e % 64, c = e / 64;
+                const int i = ib + r, j = jb + c;
+                chunk[r][c] = (i < i1 && j < j1) ? X[(size_t)i + (size_t)j * ldx] : 0.0f;
+            }
+            __syncthreads();
+            for (int e = t; e < 64 * 64; e += NT) {
+                const int c = e % 64, r = e / 64;
+                const int i = ib + r, j = jb + c;
+                if (i < i1 && j < jend) put_code<FMT>(Q, (size_t)j + (size_t)i * ldq, ldexpf(chunk[r][c], ex));
+            }
+        }
+}
+
+// ------------------------------------------------------------- update GEMM
+
+template <int FMT>
+struct Frag;
+template <>
+struct Frag<FMT_BF16> {
+    typedef v8bf T;
+    __device__ static T load(const void *p, size_t off) {
+        return *reinterpret_cast<const T *>(static_cast<const unsigned short *>(p) + off);
+    }
+    __device__ static T zero() { return T{}; }
+    __device__ static v4f mma(T a, T b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Frag<FMT_FP16> {
+    typedef v8h T;
+    __device__ static T load(const void *p, size_t off) {
+        return *reinterpret_cast<const T *>(static_cast<const unsigned short *>(p) + off);
+    }
+    __device__ static T zero() { return T{}; }
+    __device__ static v4f mma(T a, T b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Frag<FMT_E4M3> {
+    typedef long T;
+    __device__ static T load(const void *p, size_t off) {
+        return *reinterpret_cast<const long *>(static_cast<const unsigned char *>(p) + off);
+    }
+    __device__ static T zero() { return 0; }
+    __device__ static v4f mma(T a, T b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0); }
+};
+
+__device__ inline int xcd_remap(int bid, int nwg) {
+    const int full = nwg & ~7;
+    if (bid >= full) return bid;
+    return (bid & 7) * (full >> 3) + (bid >> 3);
+}
+
+// C (binary32) -= dq(QA) dq(QB): 128 x 128 tile per workgroup, 64 x 64 per
+// wave as 4 x 4 blocks of the 16x16x32 MFMA; operand fragments (8 K-adjacent
+// elements per lane) are loaded straight from L2 into registers.
+template <int FMT, bool LOWER>
+__global__ __launch_bounds__(NT) void lowp_gemm_kernel(int m, int n, int kpad, const void *__restrict__ QA, int lda,
+                                                       const int *__restrict__ ea, const void *__restrict__ QB,
+                                                       int ldb, const int *__restrict__ eb, float *__restrict__ C,
+                                                       int ldc, int tiles_m, int tiles_n, const int *stop) {
+    if (stop != nullptr && *stop != 0) return;
+    using F = Frag<FMT>;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    int tm, tn;
+    if (LOWER) {
+        int r = (int)((sqrt(8.0 * (double)L + 1.0) - 1.0) * 0.5);
+        while ((r + 1) * (r + 2) / 2 <= L) ++r;
+        while (r * (r + 1) / 2 > L) --r;
+        tm = r;
+        tn = L - r * (r + 1) / 2;
+    } else {
+        constexpr int GM = 8;
+        const int group = GM * tiles_n, g = L / group, first = g * GM, gm = min(tiles_m - first, GM);
+        const int in = L - g * group;
+        tm = first + in % gm;
+        tn = in / gm;
+    }
+    const int m0 = tm * QT, n0 = tn * QT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int lrow = lane & 15, lk = lane >> 4;
+    v4f acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    size_t aoff[4], boff[4];
+    bool aok[4], bok[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = m0 + wm * 64 + i * 16 + lrow;
+        aok[i] = row < m;
+        aoff[i] = (size_t)(aok[i] ? row : 0) * lda + 8 * lk;
+        const int col = n0 + wn * 64 + i * 16 + lrow;
+        bok[i] = col < n;
+        boff[i] = (size_t)(bok[i] ? col : 0) * ldb + 8 * lk;
+    }
+    typename F::T a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        a[i] = aok[i] ? F::load(QA, aoff[i]) : F::zero();
+        b[i] = bok[i] ? F::load(QB, boff[i]) : F::zero();
+    }
+    for (int k0 = 0; k0 < kpad; k0 += KSTEP) {
+        typename F::T an[4], bn[4];
+        const bool more = k0 + KSTEP < kpad;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            an[i] = (more && aok[i]) ? F::load(QA, aoff[i] + k0 + KSTEP) : F::zero();
+            bn[i] = (more && bok[i]) ? F::load(QB, boff[i] + k0 + KSTEP) : F::zero();
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = F::mma(a[i], b[j], acc[i][j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { a[i] = an[i]; b[i] = bn[i]; }
+    }
+    const int sc = -(ea[tm] + eb[tn]);
+    // 16x16 f32 output block: register v of a lane holds row 4*(lane/16)+v, column lane%16.
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + wn * 64 + j * 16 + lrow;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 64 + i * 16 + lk * 4 + v;
+                if (row < m && col < n && (!LOWER || row >= col)) {
+                    float *p = C + (size_t)row + (size_t)col * ldc;
+                    *p = *p - ldexpf(acc[i][j][v], sc);
+                }
+            }
+        }
+}
+
+// ------------------------------------------------------------- elementwise
+
+template <typename S, typename D>
+__global__ void convert_kernel(int m, int n, const S *__restrict__ a, int lda, D *__restrict__ b, int ldb, int lower) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= m || j >= n) return;
+    if (lower && i < j) return;
+    b[(size_t)i + (size_t)j * ldb] = (D)a[(size_t)i + (size_t)j * lda];
+}
+
+// Symmetric extension: a(j, i) = a(i, j) for i > j (upper from lower).
+__global__ void symmetrize_kernel(int n, double *__restrict__ a, int lda) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= n || i <= j) return;
+    a[(size_t)j + (size_t)i * lda] = a[(size_t)i + (size_t)j * lda];
+}
+
+__global__ void add_offset_kernel(const int *__restrict__ src, int *__restrict__ dst, int count, int off) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = src[i] + off;
+}
+
+// Row sums of |A| (partial over a column slab), accumulated by atomics into rs.
+__global__ void rowsum_abs_kernel(int n, const double *__restrict__ a, int lda, double *__restrict__ rs, int cols) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j0 = blockIdx.y * cols;
+    if (i >= n) return;
+    double s = 0.0;
+    const int j1 = min(n, j0 + cols);
+    for (int j = j0; j < j1; ++j) s += fabs(a[(size_t)i + (size_t)j * lda]);
+    atomicAdd(rs + i, s);
+}
+
+__device__ inline void atomic_max_pos(double *p, double v) {
+    // values are >= 0: their bit patterns order as unsigned 64-bit integers
+    atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ void vec_absmax_kernel(int n, const double *__restrict__ x, double *__restrict__ out) {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v = fmax(v, fabs(x[i]));
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = red[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+        atomic_max_pos(out, r);
+    }
+}
+
+__global__ void zero_d_kernel(double *p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.0;
+}
+
+__global__ void axpy_kernel(int n, int nrhs, const double *__restrict__ d, int ldd, double *__restrict__ x, int ldx) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i < n && c < nrhs) x[(size_t)i + (size_t)c * ldx] += d[(size_t)i + (size_t)c * ldd];
+}
+
+__global__ void copy_kernel(int n, int nrhs, const double *__restrict__ s, int lds, double *__restrict__ d, int ldd) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i < n && c < nrhs) d[(size_t)i + (size_t)c * ldd] = s[(size_t)i + (size_t)c * lds];
+}
+
+template <int FMT>
+hipError_t quantize_t(hipStream_t s, int m, int n, const float *X, int ldx, int tm, int tn, void *Q, int ldq, int *exps,
+                      int kpad, bool trans) {
+    const int mt = (m + tm - 1) / tm, nt = (n + tn - 1) / tn;
+    hipLaunchKernelGGL((quantize_kernel<FMT>), dim3(mt, nt), dim3(NT), 0, s, m, n, X, ldx, tm, tn, Q, ldq, exps, kpad,
+                       trans ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <int FMT, bool LOWER>
+hipError_t lowp_t(hipStream_t s, int m, int n, int kpad, const void *QA, int lda, const int *ea, const void *QB, int ldb,
+                  const int *eb, float *C, int ldc, const int *stop) {
+    const int tm = (m + QT - 1) / QT, tn = (n + QT - 1) / QT;
+    const long long nwg = LOWER ? (long long)tm * (tm + 1) / 2 : (long long)tm * tn;
+    if (nwg <= 0) return hipSuccess;
+    hipLaunchKernelGGL((lowp_gemm_kernel<FMT, LOWER>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, kpad, QA, lda, ea, QB,
+                       ldb, eb, C, ldc, tm, tn, stop);
+    return hipGetLastError();
+}
+
+inline int kpad_of(int k) { return (k + KSTEP - 1) / KSTEP * KSTEP; }
+inline size_t esize(int fmt) { return fmt == FMT_E4M3 ? 1 : 2; }
+
+}  // namespace
+
+namespace cdf {
+
+int lowp_tile(int) { return QT; }
+
+hipError_t convert_d2s(hipStream_t s, int m, int n, const double *A, int lda, float *W, int ldw, bool lower_only) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((convert_kernel<double, float>), dim3((m + 255) / 256, n), dim3(256), 0, s, m, n, A, lda, W,
+                       ldw, lower_only ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t convert_s2d(hipStream_t s, int m, int n, const float *W, int ldw, double *A, int lda, bool lower_only) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3((m + 255) / 256, n), dim3(256), 0, s, m, n, W, ldw, A,
+                       lda, lower_only ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t quantize(hipStream_t s, int fmt, int m, int n, const float *X, int ldx, int tm, int tn, void *Q, int ldq,
+                    int *exps, bool transpose_out) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    const int kpad = min(transpose_out ? kpad_of(n) : kpad_of(m), ldq);
+    if (fmt == FMT_BF16) return quantize_t<FMT_BF16>(s, m, n, X, ldx, tm, tn, Q, ldq, exps, kpad, transpose_out);
+    if (fmt == FMT_FP16) return quantize_t<FMT_FP16>(s, m, n, X, ldx, tm, tn, Q, ldq, exps, kpad, transpose_out);
+    if (fmt == FMT_E4M3) return quantize_t<FMT_E4M3>(s, m, n, X, ldx, tm, tn, Q, ldq, exps, kpad, transpose_out);
+    return hipErrorInvalidValue;
+}
+
+hipError_t lowp_update(hipStream_t s, int fmt, int m, int n, int k, const void *QA, int lda, const int *ea,
+                       const void *QB, int ldb, const int *eb, float *C, int ldc, bool lower, const int *stop) {
+    if (m <= 0 || n <= 0 || k <= 0) return hipSuccess;
+    const int kp = kpad_of(k);
+#define CDF_LOWP(F)                                                                              \
+    return lower ? lowp_t<F, true>(s, m, n, kp, QA, lda, ea, QB, ldb, eb, C, ldc, stop)          \
+                 : lowp_t<F, false>(s, m, n, kp, QA, lda, ea, QB, ldb, eb, C, ldc, stop)
+    if (fmt == FMT_BF16) { CDF_LOWP(FMT_BF16); }
+    if (fmt == FMT_FP16) { CDF_LOWP(FMT_FP16); }
+    if (fmt == FMT_E4M3) { CDF_LOWP(FMT_E4M3); }
+#undef CDF_LOWP
+    return hipErrorInvalidValue;
+}
+
+hipError_t axpy_cols(hipStream_t s, int n, int nrhs, const double *D, int ldd, double *X, int ldx) {
+    hipLaunchKernelGGL(axpy_kernel, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, n, nrhs, D, ldd, X, ldx);
+    return hipGetLastError();
+}
+
+hipError_t copy_cols(hipStream_t s, int n, int nrhs, const double *S, int lds, double *D, int ldd) {
+    hipLaunchKernelGGL(copy_kernel, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, n, nrhs, S, lds, D, ldd);
+    return hipGetLastError();
+}
+
+}  // namespace cdf
+
+namespace {
+
+struct MixedWs {
+    float *W = nullptr;        // binary32 working copy, n x n
+    double *Wd = nullptr;      // binary64 copy of the finished factor (for the solves)
+    double *Afull = nullptr;   // symmetric extension of A (Cholesky residual)
+    double *P = nullptr;       // binary64 panel, n x nb
+    void *QA = nullptr, *QB = nullptr;
+    int *ea = nullptr, *eb = nullptr, *ipt = nullptr, *ipiv = nullptr;
+    double *R = nullptr, *red = nullptr;
+};
+
+constexpr size_t kSlotBytes = (2 * 256 * 34 + 64) * sizeof(double) * 4;  // LU leaf exchange (workspace head)
+
+cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool chol, MixedWs &w,
+                          bool factor_only = false) {
+    size_t off = kSlotBytes;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = cdf::align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t nn = (size_t)n * n;
+    const size_t kp = kpad_of(nb);
+    const size_t oW = factor_only ? 0 : take(nn * sizeof(float));
+    const size_t oWd = factor_only ? 0 : take(nn * sizeof(double));
+    const size_t oAf = (chol && !factor_only) ? take(nn * sizeof(double)) : 0;
+    const size_t oP = take((size_t)n * nb * sizeof(double));
+    const size_t oQA = take(kp * n * esize(fmt));
+    const size_t oQB = take(kp * n * esize(fmt));
+    const int nt = (n + QT - 1) / QT + 1;
+    const size_t oea = take(nt * sizeof(int)), oeb = take(nt * sizeof(int));
+    const size_t oipt = take((size_t)nb * sizeof(int)), oipiv = take((size_t)n * sizeof(int));
+    const size_t oR = take((size_t)n * nrhs * sizeof(double));
+    const size_t ored = take(((size_t)n + 4 * (size_t)nrhs + 8) * sizeof(double));
+    cdf_status_t st = cdf::ws_reserve(h, off);
+    if (st != CDF_OK) return st;
+    char *base = static_cast<char *>(h->ws);
+    w.W = factor_only ? nullptr : reinterpret_cast<float *>(base + oW);
+    w.Wd = factor_only ? nullptr : reinterpret_cast<double *>(base + oWd);
+    w.Afull = (chol && !factor_only) ? reinterpret_cast<double *>(base + oAf) : nullptr;
+    w.P = reinterpret_cast<double *>(base + oP);
+    w.QA = base + oQA;
+    w.QB = base + oQB;
+    w.ea = reinterpret_cast<int *>(base + oea);
+    w.eb = reinterpret_cast<int *>(base + oeb);
+    w.ipt = reinterpret_cast<int *>(base + oipt);
+    w.ipiv = reinterpret_cast<int *>(base + oipiv);
+    w.R = reinterpret_cast<double *>(base + oR);
+    w.red = reinterpret_cast<double *>(base + ored);
+    return CDF_OK;
+}
+
+inline int mixed_nb(cdf_handle_t h) {
+    const int v = h->params[CDF_PARAM_MIXED_NB];
+    return v > 0 ? v : 256;
+}
+
+// Blocked right-looking LU of the binary32 copy W (see the file comment);
+// absolute 1-based pivots go to ipiv.
+hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *ipiv, MixedWs &w, int nb, int *info) {
+    hipStream_t s = h->stream;
+    const int kp = kpad_of(nb);
+    for (int k = 0; k < n; k += nb) {
+        const int kb = nb < n - k ? nb : n - k;
+        const int m = n - k, rest = n - k - kb;
+        CDF_HIP_RET(cdf::convert_s2d(s, m, kb, W + k + (size_t)k * ldw, ldw, w.P, m, false));
+        CDF_HIP_RET(cdf::lu_panel(h, m, kb, w.P, m, w.ipt, info, 0, kb, k));
+        hipLaunchKernelGGL(add_offset_kernel, dim3((kb + 255) / 256), dim3(256), 0, s, w.ipt, ipiv + k, kb, k);
+        CDF_HIP_RET(hipGetLastError());
+        CDF_HIP_RET(cdf::convert_d2s(s, m, kb, w.P, m, W + k + (size_t)k * ldw, ldw, false));
+        CDF_HIP_RET(cdf::slaswp(s, 0, k, W + k, ldw, w.ipt, 0, kb, m));
+        CDF_HIP_RET(cdf::slaswp(s, k + kb, n, W + k, ldw, w.ipt, 0, kb, m));
+        if (rest > 0) {
+            float *w12 = W + k + (size_t)(k + kb) * ldw;
+            float *w21 = W + (k + kb) + (size_t)k * ldw;
+            float *w22 = W + (k + kb) + (size_t)(k + kb) * ldw;
+            CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_LLNU, kb, rest, w.P, m, w12, ldw));
+            CDF_HIP_RET(cdf::quantize(s, fmt, rest, kb, w21, ldw, QT, kb, w.QA, kp, w.ea, true));
+            CDF_HIP_RET(cdf::quantize(s, fmt, kb, rest, w12, ldw, kb, QT, w.QB, kp, w.eb, false));
+            CDF_HIP_RET(cdf::lowp_update(s, fmt, rest, rest, kb, w.QA, kp, w.ea, w.QB, kp, w.eb, w22, ldw, false,
+                                         nullptr));
+        }
+    }
+    return hipSuccess;
+}
+
+// Blocked right-looking lower Cholesky of the binary32 copy W.
+hipError_t mixed_potrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, MixedWs &w, int nb, int *info) {
+    hipStream_t s = h->stream;
+    const int kp = kpad_of(nb);
+    for (int k = 0; k < n; k += nb) {
+        const int kb = nb < n - k ? nb : n - k;
+        const int rest = n - k - kb;
+        float *w11 = W + k + (size_t)k * ldw;
+        CDF_HIP_RET(cdf::convert_s2d(s, kb, kb, w11, ldw, w.P, kb, true));
+        CDF_HIP_RET(cdf::potrf_blocked(h, kb, w.P, kb, info, k, 128));
+        CDF_HIP_RET(cdf::convert_d2s(s, kb, kb, w.P, kb, w11, ldw, true));
+        if (rest > 0) {
+            float *w21 = W + (k + kb) + (size_t)k * ldw;
+            float *w22 = W + (k + kb) + (size_t)(k + kb) * ldw;
+            CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_RLTN, kb, rest, w.P, kb, w21, ldw, info));
+            CDF_HIP_RET(cdf::quantize(s, fmt, rest, kb, w21, ldw, QT, kb, w.QA, kp, w.ea, true));
+            CDF_HIP_RET(cdf::lowp_update(s, fmt, rest, rest, kb, w.QA, kp, w.ea, w.QA, kp, w.ea, w22, ldw, true,
+                                         info));
+        }
+    }
+    return hipSuccess;
+}
+
+double hpl_from_norms(const std::vector<double> &v, int nrhs, double anorm, int n) {
+    const double eps = std::ldexp(1.0, -53);
+    double worst = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+        const double r = v[3 * c], x = v[3 * c + 1], b = v[3 * c + 2];
+        const double den = eps * (anorm * x + b) * n;
+        const double q = den > 0 ? r / den : (r > 0 ? INFINITY : 0.0);
+        worst = q > worst ? q : worst;
+    }
+    return worst;
+}
+
+cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, const double *A, int lda,
+                         const double *B, int ldb, double *X, int ldx, int max_iter, int *iters, double *resid,
+                         int *info) {
+    hipStream_t s = h->stream;
+    const int nb = mixed_nb(h);
+    MixedWs w;
+    cdf_status_t st = mixed_layout(h, n, nrhs, nb, fmt == 0 ? FMT_BF16 : fmt, chol, w);
+    if (st != CDF_OK) return st;
+    CDF_HIP_TRY(cdf::fill_int(s, info, 1, 0));
+    // binary64 ||A||_inf and the matrix the residual is computed with
+    const double *Ares = A;
+    int ldres = lda;
+    if (chol) {
+        CDF_HIP_TRY(cdf::copy_cols(s, n, n, A, lda, w.Afull, n));
+        hipLaunchKernelGGL(symmetrize_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, n, w.Afull, n);
+        CDF_HIP_TRY(hipGetLastError());
+        Ares = w.Afull;
+        ldres = n;
+    }
+    double *rs = w.red + 4 * nrhs + 8;
+    hipLaunchKernelGGL(zero_d_kernel, dim3((n + 4 * nrhs + 8 + 255) / 256), dim3(256), 0, s, w.red, n + 4 * nrhs + 8);
+    const int slab = 256;
+    hipLaunchKernelGGL(rowsum_abs_kernel, dim3((n + 255) / 256, (n + slab - 1) / slab), dim3(256), 0, s, n, Ares, ldres,
+                       rs, slab);
+    hipLaunchKernelGGL(vec_absmax_kernel, dim3(256), dim3(256), 0, s, n, rs, w.red);
+    CDF_HIP_TRY(hipGetLastError());
+    // factorization of the working copy
+    if (fmt == 0) {
+        CDF_HIP_TRY(cdf::copy_cols(s, n, n, A, lda, w.Wd, n));
+        if (chol) CDF_HIP_TRY(cdf::potrf_blocked(h, n, w.Wd, n, info, 0, 128));
+        else {
+            const int lnb = h->params[CDF_PARAM_LU_NB] > 0 ? h->params[CDF_PARAM_LU_NB] : 256;
+            for (int k = 0; k < n; k += lnb) {
+                const int kb = lnb < n - k ? lnb : n - k, rest = n - k - kb;
+                CDF_HIP_TRY(cdf::lu_panel(h, n, n, w.Wd, n, w.ipiv, info, k, kb, 0));
+                if (rest > 0) {
+                    double *a11 = w.Wd + k + (size_t)k * n, *a12 = w.Wd + k + (size_t)(k + kb) * n;
+                    double *a21 = w.Wd + (k + kb) + (size_t)k * n, *a22 = w.Wd + (k + kb) + (size_t)(k + kb) * n;
+                    CDF_HIP_TRY(cdf::trsm_small(s, cdf::TRSM_LLNU, kb, rest, a11, n, a12, n));
+                    CDF_HIP_TRY(cdf::dgemm(s, 0, 0, rest, rest, kb, -1.0, a21, n, a12, n, 1.0, a22, n, false));
+                }
+            }
+        }
+    } else {
+        CDF_HIP_TRY(cdf::convert_d2s(s, n, n, A, lda, w.W, n, chol));
+        if (chol) CDF_HIP_TRY(mixed_potrf(h, fmt, n, w.W, n, w, nb, info));
+        else CDF_HIP_TRY(mixed_getrf(h, fmt, n, w.W, n, w.ipiv, w, nb, info));
+        CDF_HIP_TRY(cdf::convert_s2d(s, n, n, w.W, n, w.Wd, n, chol));
+    }
+    int hinfo = 0;
+    double anorm = 0.0;
+    CDF_HIP_TRY(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
+    CDF_HIP_TRY(hipMemcpyAsync(&anorm, w.red, sizeof(double), hipMemcpyDeviceToHost, s));
+    CDF_HIP_TRY(hipStreamSynchronize(s));
+    *iters = 0;
+    *resid = INFINITY;
+    if (hinfo != 0) return CDF_ERR_NOT_CONVERGED;
+    auto solve = [&](double *Y, int ldy) -> hipError_t {
+        if (chol) {
+            CDF_HIP_RET(cdf::trsm_blocked(s, cdf::TRSM_LLNN, n, nrhs, w.Wd, n, Y, ldy));
+            return cdf::trsm_blocked(s, cdf::TRSM_LLTN, n, nrhs, w.Wd, n, Y, ldy);
+        }
+        CDF_HIP_RET(cdf::laswp(s, 0, nrhs, Y, ldy, w.ipiv, 0, n, n));
+        CDF_HIP_RET(cdf::trsm_blocked(s, cdf::TRSM_LLNU, n, nrhs, w.Wd, n, Y, ldy));
+        return cdf::trsm_blocked(s, cdf::TRSM_LUNN, n, nrhs, w.Wd, n, Y, ldy);
+    };
+    CDF_HIP_TRY(cdf::copy_cols(s, n, nrhs, B, ldb, X, ldx));
+    CDF_HIP_TRY(solve(X, ldx));
+    std::vector<double> hist, norms(3 * nrhs);
+    double *nrm = w.red + 1;
+    for (int it = 0;; ++it) {
+        // r = b - A x (binary64, original A)
+        CDF_HIP_TRY(cdf::copy_cols(s, n, nrhs, B, ldb, w.R, n));
+        CDF_HIP_TRY(cdf::dgemm(s, 0, 0, n, nrhs, n, -1.0, Ares, ldres, X, ldx, 1.0, w.R, n, false));
+        hipLaunchKernelGGL(zero_d_kernel, dim3(1), dim3(256), 0, s, nrm, 3 * nrhs);
+        for (int c = 0; c < nrhs; ++c) {
+            hipLaunchKernelGGL(vec_absmax_kernel, dim3(64), dim3(256), 0, s, n, w.R + (size_t)c * n, nrm + 3 * c);
+            hipLaunchKernelGGL(vec_absmax_kernel, dim3(64), dim3(256), 0, s, n, X + (size_t)c * ldx, nrm + 3 * c + 1);
+            hipLaunchKernelGGL(vec_absmax_kernel, dim3(64), dim3(256), 0, s, n, B + (size_t)c * ldb, nrm + 3 * c + 2);
+        }
+        CDF_HIP_TRY(hipGetLastError());
+        CDF_HIP_TRY(hipMemcpyAsync(norms.data(), nrm, 3 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        CDF_HIP_TRY(hipStreamSynchronize(s));
+        const double res = hpl_from_norms(norms, nrhs, anorm, n);
+        hist.push_back(res);
+        *iters = it;
+        *resid = res;
+        if (res <= 16.0) return CDF_OK;
+        const size_t q = hist.size();
+        if (it >= max_iter || (q > 3 && res > 0.5 * hist[q - 4])) return CDF_ERR_NOT_CONVERGED;
+        CDF_HIP_TRY(solve(w.R, n));
+        CDF_HIP_TRY(cdf::axpy_cols(s, n, nrhs, w.R, n, X, ldx));
+    }
+}
+
+cdf_status_t check_mixed_args(cdf_handle_t h, cdf_update_prec_t p, int n, int nrhs, const double *A, int lda,
+                              const double *B, int ldb, double *X, int ldx, int max_iter, int *iters, double *resid,
+                              int *info) {
+    h->bad_arg = 0;
+    auto bad = [&](int pos) { h->bad_arg = pos; return CDF_ERR_INVALID_ARG; };
+    if ((int)p < 0 || (int)p > 3) return bad(2);
+    if (n < 0) return bad(3);
+    if (nrhs < 0) return bad(4);
+    if (lda < (n > 1 ? n : 1)) return bad(6);
+    if (ldb < (n > 1 ? n : 1)) return bad(8);
+    if (ldx < (n > 1 ? n : 1)) return bad(10);
+    if (max_iter < 0) return bad(11);
+    if (!iters) return bad(12);
+    if (!resid) return bad(13);
+    if (!info) return bad(14);
+    if (n > 0 && !A) return bad(5);
+    if (n > 0 && nrhs > 0 && !B) return bad(7);
+    if (n > 0 && nrhs > 0 && !X) return bad(9);
+    return CDF_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
-cdf_status_t cdf_dgesv_mixed(cdf_handle_t h, cdf_update_prec_t, int, int, const double *, int, const double *,
-                             int, double *, int, int, int *, double *, int *) {
-    return h ? CDF_ERR_UNSUPPORTED : CDF_ERR_INVALID_ARG;
+cdf_status_t cdf_dgesv_mixed(cdf_handle_t h, cdf_update_prec_t p, int n, int nrhs, const double *A, int lda,
+                             const double *B, int ldb, double *X, int ldx, int max_iter, int *iters,
+                             double *scaled_resid, int *info) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    cdf_status_t st = check_mixed_args(h, p, n, nrhs, A, lda, B, ldb, X, ldx, max_iter, iters, scaled_resid, info);
+    if (st != CDF_OK) return st;
+    if (n == 0 || nrhs == 0) {
+        *iters = 0;
+        *scaled_resid = 0.0;
+        CDF_HIP_TRY(cdf::fill_int(h->stream, info, 1, 0));
+        return CDF_OK;
+    }
+    return mixed_solve(h, (int)p, false, n, nrhs, A, lda, B, ldb, X, ldx, max_iter, iters, scaled_resid, info);
 }
-cdf_status_t cdf_dposv_mixed(cdf_handle_t h, cdf_update_prec_t, int, int, const double *, int, const double *,
-                             int, double *, int, int, int *, double *, int *) {
-    return h ? CDF_ERR_UNSUPPORTED : CDF_ERR_INVALID_ARG;
+
+cdf_status_t cdf_dposv_mixed(cdf_handle_t h, cdf_update_prec_t p, int n, int nrhs, const double *A, int lda,
+                             const double *B, int ldb, double *X, int ldx, int max_iter, int *iters,
+                             double *scaled_resid, int *info) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    cdf_status_t st = check_mixed_args(h, p, n, nrhs, A, lda, B, ldb, X, ldx, max_iter, iters, scaled_resid, info);
+    if (st != CDF_OK) return st;
+    if (n == 0 || nrhs == 0) {
+        *iters = 0;
+        *scaled_resid = 0.0;
+        CDF_HIP_TRY(cdf::fill_int(h->stream, info, 1, 0));
+        return CDF_OK;
+    }
+    return mixed_solve(h, (int)p, true, n, nrhs, A, lda, B, ldb, X, ldx, max_iter, iters, scaled_resid, info);
 }
-cdf_status_t cdf_quantize(cdf_handle_t h, cdf_update_prec_t, int, int, const float *, int, int, int, void *, int,
-                          int *) {
-    return h ? CDF_ERR_UNSUPPORTED : CDF_ERR_INVALID_ARG;
+
+cdf_status_t cdf_sgetrf_mixed(cdf_handle_t h, cdf_update_prec_t p, int n, const double *A, int lda, float *W, int ldw,
+                              int *ipiv, int *info) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    auto bad = [&](int pos) { h->bad_arg = pos; return CDF_ERR_INVALID_ARG; };
+    if ((int)p < 1 || (int)p > 3) return bad(2);
+    if (n < 0) return bad(3);
+    if (lda < (n > 1 ? n : 1)) return bad(5);
+    if (ldw < (n > 1 ? n : 1)) return bad(7);
+    if (!info) return bad(9);
+    if (n == 0) { CDF_HIP_TRY(cdf::fill_int(h->stream, info, 1, 0)); return CDF_OK; }
+    if (!A) return bad(4);
+    if (!W) return bad(6);
+    if (!ipiv) return bad(8);
+    MixedWs w;
+    const int nb = mixed_nb(h);
+    cdf_status_t st = mixed_layout(h, n, 1, nb, (int)p, false, w, true);
+    if (st != CDF_OK) return st;
+    CDF_HIP_TRY(cdf::fill_int(h->stream, info, 1, 0));
+    CDF_HIP_TRY(cdf::convert_d2s(h->stream, n, n, A, lda, W, ldw, false));
+    CDF_HIP_TRY(mixed_getrf(h, (int)p, n, W, ldw, ipiv, w, nb, info));
+    return CDF_OK;
 }
-cdf_status_t cdf_lowp_update(cdf_handle_t h, cdf_update_prec_t, int, int, int, const void *, int, const int *,
-                             const void *, int, const int *, float *, int) {
-    return h ? CDF_ERR_UNSUPPORTED : CDF_ERR_INVALID_ARG;
+
+cdf_status_t cdf_spotrf_mixed(cdf_handle_t h, cdf_update_prec_t p, char uplo, int n, const double *A, int lda,
+                              float *W, int ldw, int *info) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    auto bad = [&](int pos) { h->bad_arg = pos; return CDF_ERR_INVALID_ARG; };
+    if ((int)p < 1 || (int)p > 3) return bad(2);
+    if (uplo != 'L' && uplo != 'l') {
+        if (uplo == 'U' || uplo == 'u') return CDF_ERR_UNSUPPORTED;
+        return bad(3);
+    }
+    if (n < 0) return bad(4);
+    if (lda < (n > 1 ? n : 1)) return bad(6);
+    if (ldw < (n > 1 ? n : 1)) return bad(8);
+    if (!info) return bad(9);
+    if (n == 0) { CDF_HIP_TRY(cdf::fill_int(h->stream, info, 1, 0)); return CDF_OK; }
+    if (!A) return bad(5);
+    if (!W) return bad(7);
+    MixedWs w;
+    const int nb = mixed_nb(h);
+    cdf_status_t st = mixed_layout(h, n, 1, nb, (int)p, true, w, true);
+    if (st != CDF_OK) return st;
+    CDF_HIP_TRY(cdf::fill_int(h->stream, info, 1, 0));
+    CDF_HIP_TRY(cdf::convert_d2s(h->stream, n, n, A, lda, W, ldw, true));
+    CDF_HIP_TRY(mixed_potrf(h, (int)p, n, W, ldw, w, nb, info));
+    return CDF_OK;
 }
-int cdf_update_tile(cdf_update_prec_t) { return 128; }
+
+cdf_status_t cdf_quantize(cdf_handle_t h, cdf_update_prec_t p, int m, int n, const float *X, int ldx, int tm, int tn,
+                          void *Q, int ldq, int *exps) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    auto bad = [&](int pos) { h->bad_arg = pos; return CDF_ERR_INVALID_ARG; };
+    if ((int)p < 1 || (int)p > 3) return bad(2);
+    if (m < 0) return bad(3);
+    if (n < 0) return bad(4);
+    if (ldx < (m > 1 ? m : 1)) return bad(6);
+    if (tm <= 0) return bad(7);
+    if (tn <= 0) return bad(8);
+    if (ldq < (m > 1 ? m : 1)) return bad(10);
+    if (m == 0 || n == 0) return CDF_OK;
+    if (!X) return bad(5);
+    if (!Q) return bad(9);
+    if (!exps) return bad(11);
+    CDF_HIP_TRY(cdf::quantize(h->stream, (int)p, m, n, X, ldx, tm, tn, Q, ldq, exps, false));
+    return CDF_OK;
+}
+
+cdf_status_t cdf_lowp_update(cdf_handle_t h, cdf_update_prec_t p, int m, int n, int k, const void *QA, int lda,
+                             const int *ea, const void *QB, int ldb, const int *eb, float *C, int ldc) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    auto bad = [&](int pos) { h->bad_arg = pos; return CDF_ERR_INVALID_ARG; };
+    if ((int)p < 1 || (int)p > 3) return bad(2);
+    if (m < 0) return bad(3);
+    if (n < 0) return bad(4);
+    if (k < 0) return bad(5);
+    if (lda < kpad_of(k) || lda % KSTEP) return bad(7);
+    if (ldb < kpad_of(k) || ldb % KSTEP) return bad(10);
+    if (ldc < (m > 1 ? m : 1)) return bad(13);
+    if (m == 0 || n == 0 || k == 0) return CDF_OK;
+    if (!QA) return bad(6);
+    if (!ea) return bad(8);
+    if (!QB) return bad(9);
+    if (!eb) return bad(11);
+    if (!C) return bad(12);
+    CDF_HIP_TRY(cdf::lowp_update(h->stream, (int)p, m, n, k, QA, lda, ea, QB, ldb, eb, C, ldc, false, nullptr));
+    return CDF_OK;
+}
+
+int cdf_update_tile(cdf_update_prec_t) { return QT; }
 
 }  // extern "C"

@@ -16,9 +16,9 @@ constexpr int LPAD = LNC + 1;
 constexpr int RNR = 64;          // rows per workgroup (right solve)
 constexpr int MAXNB = 256;
 
-template <int KIND>
+template <int KIND, typename TB>
 __global__ __launch_bounds__(NT) void trsm_left_kernel(int nb, int ncols, const double *__restrict__ T,
-                                                       int ldt, double *__restrict__ B, int ldb,
+                                                       int ldt, TB *__restrict__ B, int ldb,
                                                        const int *stop) {
     if (stop != nullptr && *stop != 0) return;
     extern __shared__ double X[];  // X[r * LPAD + c]
@@ -27,7 +27,7 @@ __global__ __launch_bounds__(NT) void trsm_left_kernel(int nb, int ncols, const 
     const int c0 = blockIdx.x * LNC;
     for (int e = t; e < nb * LNC; e += NT) {
         const int r = e % nb, cc = e / nb;
-        X[r * LPAD + cc] = (c0 + cc < ncols) ? B[(size_t)r + (size_t)(c0 + cc) * ldb] : 0.0;
+        X[r * LPAD + cc] = (c0 + cc < ncols) ? (double)B[(size_t)r + (size_t)(c0 + cc) * ldb] : 0.0;
     }
     __syncthreads();
     constexpr bool forward = (KIND == cdf::TRSM_LLNU || KIND == cdf::TRSM_LLNN);
@@ -53,14 +53,15 @@ __global__ __launch_bounds__(NT) void trsm_left_kernel(int nb, int ncols, const 
     }
     for (int e = t; e < nb * LNC; e += NT) {
         const int r = e % nb, cc = e / nb;
-        if (c0 + cc < ncols) B[(size_t)r + (size_t)(c0 + cc) * ldb] = X[r * LPAD + cc];
+        if (c0 + cc < ncols) B[(size_t)r + (size_t)(c0 + cc) * ldb] = (TB)X[r * LPAD + cc];
     }
 }
 
 // B (nrows x nb) <- B L^-T with L lower, non-unit: column j of the result is
 // (B(:, j) - sum_{c<j} X(:, c) L(j, c)) / L(j, j), done right-looking.
+template <typename TB>
 __global__ __launch_bounds__(NT) void trsm_rltn_kernel(int nb, int nrows, const double *__restrict__ T,
-                                                       int ldt, double *__restrict__ B, int ldb,
+                                                       int ldt, TB *__restrict__ B, int ldb,
                                                        const int *stop) {
     if (stop != nullptr && *stop != 0) return;
     extern __shared__ double X[];  // X[c * RNR + r]
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(NT) void trsm_rltn_kernel(int nb, int nrows, const 
     const int r0 = blockIdx.x * RNR;
     const bool live = r0 + r < nrows;
     for (int cc = cg; cc < nb; cc += 4)
-        X[cc * RNR + r] = live ? B[(size_t)(r0 + r) + (size_t)cc * ldb] : 0.0;
+        X[cc * RNR + r] = live ? (double)B[(size_t)(r0 + r) + (size_t)cc * ldb] : 0.0;
     __syncthreads();
     for (int j = 0; j < nb; ++j) {
         if (cg == (j & 3)) X[j * RNR + r] = X[j * RNR + r] / T[(size_t)j + (size_t)j * ldt];
@@ -80,36 +81,37 @@ __global__ __launch_bounds__(NT) void trsm_rltn_kernel(int nb, int nrows, const 
         __syncthreads();
     }
     if (live)
-        for (int cc = cg; cc < nb; cc += 4) B[(size_t)(r0 + r) + (size_t)cc * ldb] = X[cc * RNR + r];
+        for (int cc = cg; cc < nb; cc += 4) B[(size_t)(r0 + r) + (size_t)cc * ldb] = (TB)X[cc * RNR + r];
 }
 
-template <int KIND>
-hipError_t launch_left(hipStream_t s, int nb, int ncols, const double *T, int ldt, double *B, int ldb,
+template <int KIND, typename TB>
+hipError_t launch_left(hipStream_t s, int nb, int ncols, const double *T, int ldt, TB *B, int ldb,
                        const int *stop) {
     static bool attr = false;
     const size_t lds = (size_t)nb * LPAD * sizeof(double);
     if (!attr) {
-        CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&trsm_left_kernel<KIND>),
+        CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&trsm_left_kernel<KIND, TB>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize,
                                         MAXNB * LPAD * sizeof(double)));
         attr = true;
     }
-    hipLaunchKernelGGL((trsm_left_kernel<KIND>), dim3((ncols + LNC - 1) / LNC), dim3(NT), lds, s, nb, ncols,
+    hipLaunchKernelGGL((trsm_left_kernel<KIND, TB>), dim3((ncols + LNC - 1) / LNC), dim3(NT), lds, s, nb, ncols,
                        T, ldt, B, ldb, stop);
     return hipGetLastError();
 }
 
-hipError_t launch_right(hipStream_t s, int nb, int nrows, const double *T, int ldt, double *B, int ldb,
+template <typename TB>
+hipError_t launch_right(hipStream_t s, int nb, int nrows, const double *T, int ldt, TB *B, int ldb,
                         const int *stop) {
     static bool attr = false;
     const size_t lds = (size_t)nb * RNR * sizeof(double);
     if (!attr) {
-        CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&trsm_rltn_kernel),
+        CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&trsm_rltn_kernel<TB>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize,
                                         MAXNB * RNR * sizeof(double)));
         attr = true;
     }
-    hipLaunchKernelGGL(trsm_rltn_kernel, dim3((nrows + RNR - 1) / RNR), dim3(NT), lds, s, nb, nrows, T, ldt,
+    hipLaunchKernelGGL((trsm_rltn_kernel<TB>), dim3((nrows + RNR - 1) / RNR), dim3(NT), lds, s, nb, nrows, T, ldt,
                        B, ldb, stop);
     return hipGetLastError();
 }
@@ -118,18 +120,29 @@ hipError_t launch_right(hipStream_t s, int nb, int nrows, const double *T, int l
 
 namespace cdf {
 
-hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
-                      double *B, int ldb, const int *stop) {
+template <typename TB>
+hipError_t trsm_small_impl(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt, TB *B,
+                           int ldb, const int *stop) {
     if (nb <= 0 || ncols <= 0) return hipSuccess;
     if (nb > MAXNB) return hipErrorInvalidValue;
     switch (kind) {
-        case TRSM_LLNU: return launch_left<TRSM_LLNU>(s, nb, ncols, T, ldt, B, ldb, stop);
-        case TRSM_LLNN: return launch_left<TRSM_LLNN>(s, nb, ncols, T, ldt, B, ldb, stop);
-        case TRSM_LLTN: return launch_left<TRSM_LLTN>(s, nb, ncols, T, ldt, B, ldb, stop);
-        case TRSM_LUNN: return launch_left<TRSM_LUNN>(s, nb, ncols, T, ldt, B, ldb, stop);
-        case TRSM_RLTN: return launch_right(s, nb, ncols, T, ldt, B, ldb, stop);
+        case TRSM_LLNU: return launch_left<TRSM_LLNU, TB>(s, nb, ncols, T, ldt, B, ldb, stop);
+        case TRSM_LLNN: return launch_left<TRSM_LLNN, TB>(s, nb, ncols, T, ldt, B, ldb, stop);
+        case TRSM_LLTN: return launch_left<TRSM_LLTN, TB>(s, nb, ncols, T, ldt, B, ldb, stop);
+        case TRSM_LUNN: return launch_left<TRSM_LUNN, TB>(s, nb, ncols, T, ldt, B, ldb, stop);
+        case TRSM_RLTN: return launch_right<TB>(s, nb, ncols, T, ldt, B, ldb, stop);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
+                      double *B, int ldb, const int *stop) {
+    return trsm_small_impl<double>(s, kind, nb, ncols, T, ldt, B, ldb, stop);
+}
+
+hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
+                      float *B, int ldb, const int *stop) {
+    return trsm_small_impl<float>(s, kind, nb, ncols, T, ldt, B, ldb, stop);
 }
 
 // Blocked solve with an n x n triangle: 128-wide diagonal solves, the rest
