@@ -78,7 +78,9 @@ typedef enum {
     CDF_PARAM_CHOL_NB = 1,       /* Cholesky outer block width (multiple of 32) */
     CDF_PARAM_LU_LEAF_ROWS = 2,  /* rows per thread in the LU panel leaf (1 or 2) */
     CDF_PARAM_MIXED_NB = 3,      /* block width of the mixed-precision factorizations (multiple of 32) */
-    CDF_PARAM_COUNT = 4
+    CDF_PARAM_VBATCH_NB = 4,     /* batched panel width: 0 = 32 where it fits in LDS, 16 = always 16 */
+    CDF_PARAM_VBATCH_WG_PER_CU = 5, /* batched persistent workgroups per CU (1 or 2; 0 = 1) */
+    CDF_PARAM_COUNT = 6
 } cdf_param_t;
 CDF_API cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value);
 CDF_API int cdf_get_param(cdf_handle_t h, cdf_param_t p);

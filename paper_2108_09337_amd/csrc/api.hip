@@ -218,6 +218,8 @@ cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value) {
     if (p == CDF_PARAM_CHOL_NB && value > 128) return bad(h, 3);
     if (p == CDF_PARAM_LU_LEAF_ROWS && !(value == 0 || value == 1 || value == 2)) return bad(h, 3);
     if (p == CDF_PARAM_MIXED_NB && value != 0 && (value % 32 != 0 || value > 256)) return bad(h, 3);
+    if (p == CDF_PARAM_VBATCH_NB && !(value == 0 || value == 16)) return bad(h, 3);
+    if (p == CDF_PARAM_VBATCH_WG_PER_CU && value > 2) return bad(h, 3);
     h->params[p] = value;
     return CDF_OK;
 }

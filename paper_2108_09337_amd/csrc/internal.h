@@ -16,7 +16,7 @@ struct cdf_handle_s {
     size_t ws_limit = 0;         // 0 = no cap
     int *sync = nullptr;         // zeroed counters for grid-wide barriers
     int bad_arg = 0;
-    int params[CDF_PARAM_COUNT] = {0, 0, 0, 0};
+    int params[CDF_PARAM_COUNT] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace cdf {

@@ -1,15 +1,466 @@
-// Batched small factorizations (placeholder entry points).
+// Batched small factorizations of uneven sizes in one persistent launch.
+//
+// The plan sorts the problems by estimated cost, largest first (longest-
+// processing-time order), and captures one launch of the persistent kernel
+// (preceded by a kernel that clears the work counter) in a HIP graph.  Each
+// workgroup repeatedly takes the next problem from the device counter and
+// factors it alone, blocked right-looking as in Sec. 7 with a panel of NB
+// columns held in LDS:
+//   LU       : panel with partial pivoting (argmax by wave shuffles), row
+//              interchanges on the other columns, U12 = L11^-1 A12 in
+//              registers, trailing update A22 -= L21 U12 from LDS;
+//   Cholesky : panel = potrf of the diagonal block and L21 in one pass
+//              (Sec. 6.2 statements on the panel), trailing lower update.
+// Every workgroup exits once the counter passes the batch size.
 #include "internal.h"
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <vector>
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int UC = 64;          // U12 columns staged in LDS per chunk
+constexpr size_t LDS_BYTES = 144 * 1024;
+
+struct VArgs {                   // pointer arrays, rewritten before each replay
+    void *const *A;
+    const int *lda;
+    int *const *ipiv;
+    int *info;
+};
+
+struct VPlanDev {
+    int batch;
+    const int *n;
+    const int *kind;
+    const int *order;
+    int *counter;
+    VArgs *args;
+};
+
+template <typename T>
+__device__ inline T tabs(T x) { return x < T(0) ? -x : x; }
+
+// Panel width for an n x n problem: 32 if n x 32 fits in 96 KB, else 16.
+template <typename T>
+__host__ __device__ inline int panel_nb(int n, int nb_pref) {
+    if (nb_pref == 16) return 16;
+    return (size_t)n * 32 * sizeof(T) <= 96 * 1024 ? 32 : 16;
+}
+
+// Row interchanges of one panel (pivots pv[0..kb), relative to row k0,
+// 0-based) on columns [c0, c1) of A: (dst, src) pairs built by one thread,
+// then all reads before all writes, 64 columns at a time.
+template <typename T>
+__device__ void swap_rows(T *A, int lda, int k0, const int *pv, int kb, int c0, int c1, int *pos, int *cont,
+                          int *dst, int *src, int *s_np) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        int np = 0;
+        for (int j = 0; j < kb; ++j) {
+            const int p = pv[j];
+            if (p == j) continue;
+            int ij = -1, ip = -1;
+            for (int q = 0; q < np; ++q) {
+                if (pos[q] == j) ij = q;
+                if (pos[q] == p) ip = q;
+            }
+            if (ij < 0) { pos[np] = j; cont[np] = j; ij = np++; }
+            if (ip < 0) { pos[np] = p; cont[np] = p; ip = np++; }
+            const int tmp = cont[ij];
+            cont[ij] = cont[ip];
+            cont[ip] = tmp;
+        }
+        int q2 = 0;
+        for (int q = 0; q < np; ++q)
+            if (cont[q] != pos[q]) { dst[q2] = k0 + pos[q]; src[q2] = k0 + cont[q]; ++q2; }
+        *s_np = q2;
+    }
+    __syncthreads();
+    const int np = *s_np;
+    if (np > 0) {
+        for (int cb = c0; cb < c1; cb += 64) {
+            const int cols = min(64, c1 - cb);
+            const int total = np * cols;
+            T v[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int e = t + NT * r;
+                if (e < total) v[r] = A[(size_t)src[e % np] + (size_t)(cb + e / np) * lda];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int e = t + NT * r;
+                if (e < total) A[(size_t)dst[e % np] + (size_t)(cb + e / np) * lda] = v[r];
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void block_argmax(T v, int idx, T *rv, int *ri, int *out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off >= 1; off >>= 1) {
+        const T ov = __shfl_xor(v, off);
+        const int oi = __shfl_xor(idx, off);
+        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    }
+    if (lane == 0) { rv[wave] = v; ri[wave] = idx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T bv = rv[0];
+        int bi = ri[0];
+        for (int w = 1; w < NT / 64; ++w)
+            if (rv[w] > bv || (rv[w] == bv && ri[w] < bi)) { bv = rv[w]; bi = ri[w]; }
+        *out = bi;
+    }
+    __syncthreads();
+}
+
+// Trailing update C (rows x cols at C, ldc) -= L (rows x kb, LDS, ld ldl) *
+// U (kb x cols, LDS, ld ldu); lower: only entries with row >= col + diag.
+// Each thread accumulates 4 x 4 blocks of a 64 x 64 macro tile.
+template <typename T>
+__device__ void lds_update(T *C, int ldc, int rows, int cols, int kb, const T *L, int ldl, const T *U, int ldu,
+                           bool lower, int diag) {
+    const int t = threadIdx.x;
+    const int tx = t & 15, ty = t >> 4;
+    for (int r0 = 0; r0 < rows; r0 += 64)
+        for (int c0 = 0; c0 < cols; c0 += 64) {
+            if (lower && r0 + 63 + diag < c0) continue;
+            T acc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+            const int rr = r0 + 4 * tx, cc = c0 + 4 * ty;
+            for (int j = 0; j < kb; ++j) {
+                T l[4], u[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) l[a] = rr + a < rows ? L[(size_t)j * ldl + rr + a] : T(0);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) u[b] = cc + b < cols ? U[(size_t)j * ldu + cc + b] : T(0);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] = fma(l[a], u[b], acc[a][b]);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int r = rr + a, c = cc + b;
+                    if (r < rows && c < cols && (!lower || r + diag >= c)) C[(size_t)r + (size_t)c * ldc] -= acc[a][b];
+                }
+        }
+}
+
+template <typename T, int NB>
+__device__ void lu_one(int n, T *A, int lda, int *ipiv, int *info, char *smem) {
+    __shared__ T rv[NT / 64];
+    __shared__ int ri[NT / 64];
+    __shared__ int s_p, s_np;
+    __shared__ int pv[NB];
+    __shared__ int pos[2 * NB], cont[2 * NB], dst[2 * NB], src[2 * NB];
+    const int t = threadIdx.x;
+    T *P = reinterpret_cast<T *>(smem);                      // panel, m x kb, ld m
+    T *Uc = P + (size_t)n * NB;                              // U12 chunk, kb x UC, ld UC
+    int first_zero = 0;
+    for (int k0 = 0; k0 < n; k0 += NB) {
+        const int kb = min(NB, n - k0), m = n - k0;
+        for (int e = t; e < m * kb; e += NT) P[e] = A[(size_t)(k0 + e % m) + (size_t)(k0 + e / m) * lda];
+        __syncthreads();
+        for (int j = 0; j < kb; ++j) {
+            T bv = T(-1);
+            int bi = 0x7fffffff;
+            for (int r = j + t; r < m; r += NT) {
+                const T v = tabs(P[(size_t)j * m + r]);
+                if (v > bv) { bv = v; bi = r; }
+            }
+            block_argmax<T>(bv, bi, rv, ri, &s_p);
+            const int p = s_p == 0x7fffffff ? j : s_p;
+            if (t == 0) { pv[j] = p; ipiv[k0 + j] = k0 + p + 1; }
+            if (p != j)
+                for (int c = t; c < kb; c += NT) {
+                    const T tmp = P[(size_t)c * m + j];
+                    P[(size_t)c * m + j] = P[(size_t)c * m + p];
+                    P[(size_t)c * m + p] = tmp;
+                }
+            __syncthreads();
+            const T piv = P[(size_t)j * m + j];
+            if (piv == T(0)) {
+                if (!first_zero) first_zero = k0 + j + 1;
+                continue;
+            }
+            for (int r = j + 1 + t; r < m; r += NT) P[(size_t)j * m + r] /= piv;
+            __syncthreads();
+            for (int e = t; e < (m - j - 1) * (kb - j - 1); e += NT) {
+                const int r = j + 1 + e % (m - j - 1), c = j + 1 + e / (m - j - 1);
+                P[(size_t)c * m + r] = fma(-P[(size_t)j * m + r], P[(size_t)c * m + j], P[(size_t)c * m + r]);
+            }
+            __syncthreads();
+        }
+        for (int e = t; e < m * kb; e += NT) A[(size_t)(k0 + e % m) + (size_t)(k0 + e / m) * lda] = P[e];
+        __syncthreads();
+        swap_rows<T>(A, lda, k0, pv, kb, 0, k0, pos, cont, dst, src, &s_np);
+        swap_rows<T>(A, lda, k0, pv, kb, k0 + kb, n, pos, cont, dst, src, &s_np);
+        const int rest = n - k0 - kb;
+        for (int cb = 0; cb < rest; cb += UC) {
+            const int cols = min(UC, rest - cb);
+            // U12 chunk = L11^-1 A12 (unit lower), one column per thread, in registers
+            if (t < cols) {
+                T x[NB];
+                T *col = A + k0 + (size_t)(k0 + kb + cb + t) * lda;
+#pragma unroll
+                for (int i = 0; i < NB; ++i) x[i] = i < kb ? col[i] : T(0);
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int i = j + 1; i < NB; ++i)
+                        if (i < kb) x[i] = fma(-P[(size_t)j * m + i], x[j], x[i]);
+#pragma unroll
+                for (int i = 0; i < NB; ++i)
+                    if (i < kb) { col[i] = x[i]; Uc[(size_t)i * UC + t] = x[i]; }
+            }
+            __syncthreads();
+            lds_update<T>(A + (k0 + kb) + (size_t)(k0 + kb + cb) * lda, lda, rest, cols, kb, P + kb, m, Uc, UC, false,
+                          0);
+            __syncthreads();
+        }
+    }
+    if (t == 0) *info = first_zero;
+}
+
+template <typename T, int NB>
+__device__ void chol_one(int n, T *A, int lda, int *info, char *smem) {
+    __shared__ int s_fail;
+    const int t = threadIdx.x;
+    T *P = reinterpret_cast<T *>(smem);  // panel, m x kb, ld m (lower part used)
+    if (t == 0) s_fail = 0;
+    __syncthreads();
+    for (int k0 = 0; k0 < n; k0 += NB) {
+        const int kb = min(NB, n - k0), m = n - k0;
+        for (int e = t; e < m * kb; e += NT) {
+            const int r = e % m, c = e / m;
+            P[e] = r >= c ? A[(size_t)(k0 + r) + (size_t)(k0 + c) * lda] : T(0);
+        }
+        __syncthreads();
+        for (int j = 0; j < kb; ++j) {
+            if (t == 0) {
+                const T d = P[(size_t)j * m + j];
+                if (!(d > T(0))) s_fail = k0 + j + 1;
+                else P[(size_t)j * m + j] = sqrt(d);
+            }
+            __syncthreads();
+            if (s_fail) break;
+            const T ljj = P[(size_t)j * m + j];
+            for (int r = j + 1 + t; r < m; r += NT) P[(size_t)j * m + r] /= ljj;
+            __syncthreads();
+            for (int e = t; e < (m - j - 1) * (kb - j - 1); e += NT) {
+                const int r = j + 1 + e % (m - j - 1), c = j + 1 + e / (m - j - 1);
+                if (r >= c) P[(size_t)c * m + r] = fma(-P[(size_t)j * m + r], P[(size_t)j * m + c], P[(size_t)c * m + r]);
+            }
+            __syncthreads();
+        }
+        for (int e = t; e < m * kb; e += NT) {
+            const int r = e % m, c = e / m;
+            if (r >= c) A[(size_t)(k0 + r) + (size_t)(k0 + c) * lda] = P[e];
+        }
+        __syncthreads();
+        if (s_fail) break;
+        const int rest = n - k0 - kb;
+        // lower(A22) -= L21 L21^T with L21 = rows [kb, m) of the panel
+        if (rest > 0) lds_update<T>(A + (k0 + kb) + (size_t)(k0 + kb) * lda, lda, rest, rest, kb, P + kb, m, P + kb, m,
+                                    true, 0);
+        __syncthreads();
+    }
+    if (t == 0) *info = s_fail;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void vbatch_kernel(const VPlanDev *__restrict__ pd, int nb_pref) {
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int s_idx;
+    const int batch = pd->batch;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = atomicAdd(pd->counter, 1);
+        __syncthreads();
+        const int idx = s_idx;
+        __syncthreads();
+        if (idx >= batch) break;
+        const int p = pd->order[idx];
+        const int n = pd->n[p];
+        T *A = static_cast<T *>(pd->args->A[p]);
+        const int lda = pd->args->lda[p];
+        int *info = pd->args->info + p;
+        if (pd->kind[p] == 0) {
+            int *ipiv = pd->args->ipiv[p];
+            if (panel_nb<T>(n, nb_pref) == 32) lu_one<T, 32>(n, A, lda, ipiv, info, smem);
+            else lu_one<T, 16>(n, A, lda, ipiv, info, smem);
+        } else {
+            if (panel_nb<T>(n, nb_pref) == 32) chol_one<T, 32>(n, A, lda, info, smem);
+            else chol_one<T, 16>(n, A, lda, info, smem);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void reset_counter_kernel(int *c) { *c = 0; }
+
+__global__ void set_args_kernel(VArgs *a, void *const *A, const int *lda, int *const *ipiv, int *info) {
+    a->A = A;
+    a->lda = lda;
+    a->ipiv = ipiv;
+    a->info = info;
+}
+
+}  // namespace
+
+struct cdf_vbatch_plan_s {
+    int device = 0;
+    int batch = 0;
+    cdf_dtype_t dt = CDF_F64;
+    int grid = 0;
+    int nb_pref = 0;
+    void *dev = nullptr;  // VPlanDev + arrays + counter + VArgs
+    VPlanDev *pd = nullptr;
+    VArgs *args = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
-cdf_status_t cdf_vbatch_plan_create(cdf_handle_t h, int, const int *, const int *, cdf_dtype_t,
-                                    cdf_vbatch_plan_t *) {
-    return h ? CDF_ERR_UNSUPPORTED : CDF_ERR_INVALID_ARG;
+cdf_status_t cdf_vbatch_plan_create(cdf_handle_t h, int batch, const int *n_host, const int *kind_host, cdf_dtype_t dt,
+                                    cdf_vbatch_plan_t *plan) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    auto bad = [&](int pos) { h->bad_arg = pos; return CDF_ERR_INVALID_ARG; };
+    if (batch < 0) return bad(2);
+    if (batch > 0 && !n_host) return bad(3);
+    if (batch > 0 && !kind_host) return bad(4);
+    if (dt != CDF_F64 && dt != CDF_F32) return bad(5);
+    if (!plan) return bad(6);
+    *plan = nullptr;
+    for (int i = 0; i < batch; ++i) {
+        if (n_host[i] < 1 || n_host[i] > 1024) return bad(3);
+        if (kind_host[i] != 0 && kind_host[i] != 1) return bad(4);
+    }
+    cdf_vbatch_plan_s *p = new (std::nothrow) cdf_vbatch_plan_s();
+    if (!p) return CDF_ERR_ALLOC;
+    p->device = h->device;
+    p->batch = batch;
+    p->dt = dt;
+    p->nb_pref = h->params[CDF_PARAM_VBATCH_NB];
+    const int wpc = h->params[CDF_PARAM_VBATCH_WG_PER_CU] > 0 ? h->params[CDF_PARAM_VBATCH_WG_PER_CU] : 1;
+    p->grid = std::max(1, std::min(batch, h->num_cus * wpc));
+    // longest-processing-time order: estimated flops, largest first (stable)
+    std::vector<int> order(batch);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const double ca = (double)n_host[a] * n_host[a] * n_host[a] * (kind_host[a] == 0 ? 2.0 : 1.0);
+        const double cb = (double)n_host[b] * n_host[b] * n_host[b] * (kind_host[b] == 0 ? 2.0 : 1.0);
+        return ca > cb;
+    });
+    const size_t nb4 = cdf::align_up((size_t)std::max(batch, 1) * sizeof(int), 256);
+    const size_t bytes = cdf::align_up(sizeof(VPlanDev), 256) + 3 * nb4 + 256 + cdf::align_up(sizeof(VArgs), 256);
+    if (hipMalloc(&p->dev, bytes) != hipSuccess) { delete p; return CDF_ERR_ALLOC; }
+    char *base = static_cast<char *>(p->dev);
+    VPlanDev hpd;
+    hpd.batch = batch;
+    int *dn = reinterpret_cast<int *>(base + cdf::align_up(sizeof(VPlanDev), 256));
+    int *dk = reinterpret_cast<int *>(reinterpret_cast<char *>(dn) + nb4);
+    int *dord = reinterpret_cast<int *>(reinterpret_cast<char *>(dk) + nb4);
+    int *dcnt = reinterpret_cast<int *>(reinterpret_cast<char *>(dord) + nb4);
+    VArgs *dargs = reinterpret_cast<VArgs *>(reinterpret_cast<char *>(dcnt) + 256);
+    hpd.n = dn;
+    hpd.kind = dk;
+    hpd.order = dord;
+    hpd.counter = dcnt;
+    hpd.args = dargs;
+    p->pd = reinterpret_cast<VPlanDev *>(base);
+    p->args = dargs;
+    bool ok = hipMemcpy(base, &hpd, sizeof(hpd), hipMemcpyHostToDevice) == hipSuccess;
+    if (batch > 0) {
+        ok = ok && hipMemcpy(dn, n_host, batch * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(dk, kind_host, batch * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(dord, order.data(), batch * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+    }
+    const void *fn = dt == CDF_F64 ? reinterpret_cast<const void *>(&vbatch_kernel<double>)
+                                   : reinterpret_cast<const void *>(&vbatch_kernel<float>);
+    // LDS: the largest panel (n x nb) plus one U12 chunk (nb x UC)
+    size_t lds = 1024;
+    const size_t es = dt == CDF_F64 ? sizeof(double) : sizeof(float);
+    for (int i = 0; i < batch; ++i) {
+        const int nbp = dt == CDF_F64 ? panel_nb<double>(n_host[i], p->nb_pref) : panel_nb<float>(n_host[i], p->nb_pref);
+        lds = std::max(lds, ((size_t)n_host[i] * nbp + (size_t)nbp * UC) * es);
+    }
+    lds = cdf::align_up(lds, 256);
+    ok = ok && lds <= LDS_BYTES;
+    ok = ok && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_BYTES) == hipSuccess;
+    // capture: counter reset + persistent launch
+    hipStream_t cs = nullptr;
+    ok = ok && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+    if (ok && batch > 0) {
+        ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, cs, dcnt);
+            VPlanDev *pdp = p->pd;
+            int nbp = p->nb_pref;
+            if (dt == CDF_F64)
+                hipLaunchKernelGGL((vbatch_kernel<double>), dim3(p->grid), dim3(NT), lds, cs, pdp, nbp);
+            else
+                hipLaunchKernelGGL((vbatch_kernel<float>), dim3(p->grid), dim3(NT), lds, cs, pdp, nbp);
+            ok = hipStreamEndCapture(cs, &p->graph) == hipSuccess;
+        }
+        ok = ok && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (!ok) {
+        (void)hipGetLastError();
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        (void)hipFree(p->dev);
+        delete p;
+        return CDF_ERR_HIP;
+    }
+    *plan = p;
+    return CDF_OK;
 }
-cdf_status_t cdf_vbatch_run(cdf_handle_t h, cdf_vbatch_plan_t, void *const *, const int *, int *const *, int *) {
-    return h ? CDF_ERR_UNSUPPORTED : CDF_ERR_INVALID_ARG;
+
+cdf_status_t cdf_vbatch_run(cdf_handle_t h, cdf_vbatch_plan_t plan, void *const *A_array, const int *lda_array,
+                            int *const *ipiv_array, int *info_array) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    auto bad = [&](int pos) { h->bad_arg = pos; return CDF_ERR_INVALID_ARG; };
+    if (!plan) return bad(2);
+    if (plan->batch == 0) return CDF_OK;
+    if (!A_array) return bad(3);
+    if (!lda_array) return bad(4);
+    if (!ipiv_array) return bad(5);
+    if (!info_array) return bad(6);
+    if (plan->device != h->device) return bad(2);
+    hipLaunchKernelGGL(set_args_kernel, dim3(1), dim3(1), 0, h->stream, plan->args, A_array, lda_array, ipiv_array,
+                       info_array);
+    CDF_HIP_TRY(hipGetLastError());
+    CDF_HIP_TRY(hipGraphLaunch(plan->exec, h->stream));
+    return CDF_OK;
 }
-cdf_status_t cdf_vbatch_plan_destroy(cdf_vbatch_plan_t) { return CDF_ERR_UNSUPPORTED; }
+
+cdf_status_t cdf_vbatch_plan_destroy(cdf_vbatch_plan_t plan) {
+    if (!plan) return CDF_ERR_INVALID_ARG;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    (void)hipDeviceSynchronize();
+    if (plan->dev) (void)hipFree(plan->dev);
+    delete plan;
+    return CDF_OK;
+}
 
 }  // extern "C"
