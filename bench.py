@@ -1,13 +1,23 @@
-"""Benchmark of the FP64 LU and Cholesky factorizations on one MI355X.
+"""Benchmark of the dense LU / Cholesky hot path on one MI355X.
 
-One step = FP64 LU with partial pivoting (dgetrf) of an N x N matrix with
-uniform[-1, 1] entries + FP64 Cholesky (dpotrf) of an N x N SPD matrix
-B B^T / N + I, both resident in HBM before the timed region (one fresh copy
-per step, made before timing).  value = (2N^3/3 + N^3/3) / time, TFLOP/s.
+Headline (``value``): one step = FP64 LU with partial pivoting (dgetrf) of an
+N x N matrix with uniform[-1, 1] entries + FP64 Cholesky (dpotrf) of an N x N
+SPD matrix B B^T / N + I (N = 32768 by default), inputs resident in HBM before
+the timed region (one fresh copy per step, made before timing);
+value = (2N^3/3 + N^3/3) / time in TFLOP/s.
 
-Prints one JSON line (rank 0) with the roofline of the dominant kernel (the
-FP64 Schur-complement update GEMM, timed with HIP events on the stream it is
-launched on) and the CPU oracle's throughput on a bounded sample.
+Also reported (``detail``):
+  * mixed: time-to-solution of A x = b (diagonally dominant, N = 65536,
+    nrhs = 1) with the BF16 / FP16 update + FP64 refinement to an HPL scaled
+    residual <= 16, against the FP64 path (FP64 LU + solve + the same
+    residual check) on the same matrix; speedup = FP64 time / mixed time;
+  * batched: 4096 LU/Cholesky problems, N log-uniform in [16, 512], one
+    graph replay, FP64 and FP32, aggregate TFLOP/s.
+
+``roofline``: the FP64 Schur-complement update GEMM (the dominant kernel),
+replayed with the trailing-update shapes of one LU and timed with HIP events
+on the stream it is launched on.  ``cpu_baseline``: the CPU oracle on the
+first elimination steps of the same N x N inputs.
 """
 import argparse
 import json
@@ -22,8 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "LU/Cholesky TFLOP/s vs FP64 MFMA peak; mixed-prec+IR speedup at residual<=16"
-FP64_PEAK_TFLOPS = 78.6
-HBM_PEAK_GBS = 8000.0
+FP64_PEAK = 78.6
+FP32_PEAK = 157.3
 
 
 def parse():
@@ -32,9 +42,14 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--n", type=int, default=32768)
-    p.add_argument("--cpu-steps", type=int, default=24, help="elimination steps in the oracle sample")
+    p.add_argument("--mixed-n", type=int, default=65536)
+    p.add_argument("--batch", type=int, default=4096)
+    p.add_argument("--cpu-steps", type=int, default=64, help="elimination steps in the oracle sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-chol", action="store_true")
+    p.add_argument("--no-mixed", action="store_true")
+    p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--no-tune-cache", action="store_true", help="ignore the autotuner cache")
     return p.parse_args()
 
 
@@ -57,27 +72,17 @@ def spd_on_device(n, torch, cdf, workloads):
     return out
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
-    import torch
+def events(torch, k):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
 
-    import paper_2108_09337_amd as cdf
-    import workloads
 
-    torch.cuda.set_device(0)
-    n = args.n
-    K, W = args.steps, args.warmup
-    h = cdf.handle()
-    lu_nb = h.get_param("lu_nb") or 256
-    chol_nb = h.get_param("chol_nb") or 128
-
-    log(f"generating inputs n={n}")
+def fp64_section(args, torch, cdf, workloads, h, tuned):
+    n, K, W = args.n, args.steps, args.warmup
+    log(f"FP64: generating inputs n={n}")
     a_host = workloads.lu_uniform(n)
     A0 = cdf.to_device(a_host)
     lu_copies = [A0.clone() for _ in range(K + W)]
+    S0 = None
     chol_copies = []
     if not args.no_chol:
         S0 = spd_on_device(n, torch, cdf, workloads)
@@ -85,6 +90,8 @@ def main():
     ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
     info_lu = torch.zeros(1, dtype=torch.int32, device="cuda")
     info_ch = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lu_params = tuned(h, "getrf", n)
+    ch_params = tuned(h, "potrf", n)
     torch.cuda.synchronize()
 
     def step(i, ev=None):
@@ -102,7 +109,7 @@ def main():
         log(f"warmup step {i}")
         step(i)
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    evs = [events(torch, 3) for _ in range(K)]
     log(f"timing {K} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -112,23 +119,19 @@ def main():
     t1 = time.perf_counter()
     assert int(info_lu.item()) == 0 and (not chol_copies or int(info_ch.item()) == 0)
     ms = (t1 - t0) * 1e3 / K
-    t_lu = np.mean([e[0].elapsed_time(e[1]) for e in evs]) * 1e-3
-    t_ch = np.mean([e[1].elapsed_time(e[2]) for e in evs]) * 1e-3
+    t_lu = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e-3
+    t_ch = float(np.mean([e[1].elapsed_time(e[2]) for e in evs])) * 1e-3
     flops_lu = 2.0 * n ** 3 / 3.0
     flops_ch = n ** 3 / 3.0 if chol_copies else 0.0
     value = (flops_lu + flops_ch) / (ms * 1e-3) / 1e12
     log(f"ms/step {ms:.1f}  LU {flops_lu / t_lu / 1e12:.2f} TF  Chol {flops_ch / max(t_ch, 1e-12) / 1e12:.2f} TF")
 
-    # Dominant kernel: the FP64 Schur-complement update GEMM, replayed with the
-    # shapes of one LU's trailing updates on a spent copy, timed with events.
+    # dominant kernel: the FP64 update GEMM with one LU's trailing-update shapes
+    lu_nb = h.get_param("lu_nb") or 256
     C = lu_copies[W]
-    shapes = []
-    for k in range(0, n, lu_nb):
-        kb = min(lu_nb, n - k)
-        rest = n - k - kb
-        if rest > 0:
-            shapes.append((k, kb, rest))
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    shapes = [(k, min(lu_nb, n - k), n - k - min(lu_nb, n - k)) for k in range(0, n, lu_nb)]
+    shapes = [s for s in shapes if s[2] > 0]
+    e0, e1 = events(torch, 2)
     torch.cuda.synchronize()
     e0.record()
     for k, kb, rest in shapes:
@@ -137,46 +140,153 @@ def main():
     torch.cuda.synchronize()
     gemm_s = e0.elapsed_time(e1) * 1e-3
     gemm_flops = sum(2.0 * rest * rest * kb for _, kb, rest in shapes)
-    avg_launch = gemm_s / len(shapes)
-    achieved = gemm_flops / len(shapes) / avg_launch / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": "dgemm_kernel (FP64 Schur-complement update, C -= A B)",
-                "launches": len(shapes), "avg_launch_us": round(avg_launch * 1e6, 2),
+    avg = gemm_s / len(shapes)
+    achieved = gemm_flops / len(shapes) / avg / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK, 4), "traffic": None,
+                "kernel": "dgemm_kernel<0,0,false> (FP64 Schur-complement update C -= A B)",
+                "launches": len(shapes), "avg_launch_us": round(avg * 1e6, 2),
                 "flops_per_launch": gemm_flops / len(shapes)}
+    out = {"value": value, "ms": ms, "t_lu": t_lu, "t_ch": t_ch, "flops_lu": flops_lu, "flops_ch": flops_ch,
+           "roofline": roofline, "lu_nb": lu_nb, "chol_nb": h.get_param("chol_nb") or 128,
+           "params": {"getrf": lu_params, "potrf": ch_params}}
+    for k in list(lu_params) + list(ch_params):
+        h.set_param(k, 0)
+    del lu_copies, chol_copies, C
+    torch.cuda.empty_cache()
+    return out, a_host, S0
 
+
+def mixed_section(args, torch, cdf, workloads, h):
+    n = args.mixed_n
+    log(f"mixed: generating diagonally dominant n={n}")
+    A = workloads.diag_dominant_torch(n)
+    b = workloads.rhs_uniform_torch(n)
+    X = torch.empty(n, dtype=torch.float64, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    res = {"n": n, "nrhs": 1}
+    for prec in ("fp64", "bf16", "fp16"):
+        cdf.dgesv_mixed(prec, A, b, X, info, max_iter=30)  # warm-up (also allocates the workspace)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = cdf.dgesv_mixed(prec, A, b, X, info, max_iter=30)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res[prec] = {"seconds": round(t, 4), "iters": r["iters"], "scaled_resid": round(r["scaled_resid"], 4),
+                     "converged": r["converged"], "info": int(info.item())}
+        log(f"mixed {prec}: {t:.3f} s, iters {r['iters']}, resid {r['scaled_resid']:.3f}")
+    for prec in ("bf16", "fp16"):
+        res[prec]["speedup_vs_fp64"] = round(res["fp64"]["seconds"] / res[prec]["seconds"], 3)
+    del A, X
+    torch.cuda.empty_cache()
+    return res
+
+
+def batched_section(args, torch, cdf, workloads, h, tuned):
+    count = args.batch
+    sizes = workloads.batch_sizes(count)
+    kinds = workloads.batch_kinds(count)
+    flops = float(sum(2.0 * n ** 3 / 3 if k == 0 else n ** 3 / 3.0 for n, k in zip(sizes.astype(float), kinds)))
+    mats = [workloads.batch_problem(i, int(n), int(k)) for i, (n, k) in enumerate(zip(sizes, kinds))]
+    offs = np.concatenate([[0], np.cumsum([m.size for m in mats])])
+    host = np.concatenate([m.ravel(order="F") for m in mats])
+    out = {"count": count, "flops": flops}
+    for dtn, dt, tdt, peak in (("f64", cdf.F64, torch.float64, FP64_PEAK), ("f32", cdf.F32, torch.float32, FP32_PEAK)):
+        src = torch.from_numpy(host).to(device="cuda", dtype=tdt)
+        buf = torch.empty_like(src)
+        es = buf.element_size()
+        a_ptrs = torch.tensor([buf.data_ptr() + int(o) * es for o in offs[:-1]], dtype=torch.int64, device="cuda")
+        ldas = torch.tensor(sizes, dtype=torch.int32, device="cuda")
+        nmax = int(sizes.max())
+        piv = torch.zeros((count, nmax), dtype=torch.int32, device="cuda")
+        p_ptrs = torch.tensor([piv.data_ptr() + i * nmax * 4 for i in range(count)], dtype=torch.int64,
+                              device="cuda")
+        info = torch.zeros(count, dtype=torch.int32, device="cuda")
+        params = tuned(h, "vbatch", nmax, dtn)
+        plan = cdf.VBatchPlan(sizes, kinds, dt, h)
+        for k in params:
+            h.set_param(k, 0)
+        times = []
+        for rep in range(6):
+            buf.copy_(src)
+            e0, e1 = events(torch, 2)
+            e0.record()
+            plan.run(a_ptrs, ldas, p_ptrs, info)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep:
+                times.append(e0.elapsed_time(e1) * 1e-3)
+        assert int(info.abs().sum().item()) == 0
+        t = float(np.median(times))
+        out[dtn] = {"seconds": round(t, 6), "tflops": round(flops / t / 1e12, 3),
+                    "frac_peak": round(flops / t / 1e12 / peak, 4), "params": params}
+        log(f"batched {dtn}: {t * 1e3:.3f} ms, {flops / t / 1e12:.2f} TF")
+        plan.close()
+        del src, buf
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2108_09337_amd as cdf
+    import workloads
+    from paper_2108_09337_amd import tune
+
+    torch.cuda.set_device(0)
+    h = cdf.handle()
+    cache = {} if args.no_tune_cache else tune.load_cache()
+
+    def tuned(hh, op, n, dtype="f64"):
+        return tune.apply(hh, op, n, dtype, cache) if cache else {}
+
+    fp, a_host, S0 = fp64_section(args, torch, cdf, workloads, h, tuned)
+    detail = {"lu_tflops": round(fp["flops_lu"] / fp["t_lu"] / 1e12, 3),
+              "chol_tflops": round(fp["flops_ch"] / fp["t_ch"] / 1e12, 3) if fp["flops_ch"] else None,
+              "lu_s": round(fp["t_lu"], 4), "chol_s": round(fp["t_ch"], 4),
+              "frac_fp64_peak": round(fp["value"] / FP64_PEAK, 4), "tuned_params": fp["params"]}
     cpu = None
     if not args.no_cpu:
         import oracle
         s = args.cpu_steps
-        log(f"oracle sample: first {s} elimination steps of the n={n} LU and Cholesky")
+        log(f"oracle sample: first {s} elimination steps of the n={args.n} LU and Cholesky")
         t = time.perf_counter()
         oracle.dgetrf(a_host, ksteps=s)
         t_cl = time.perf_counter() - t
-        f = oracle.lu_step_flops(n, s)
-        if chol_copies:
+        f = oracle.lu_step_flops(args.n, s)
+        if S0 is not None:
             s_host = cdf.to_host(S0)
             t = time.perf_counter()
             oracle.dpotrf(s_host, ksteps=s)
-            t_cc = time.perf_counter() - t
-            f += oracle.chol_step_flops(n, s)
-            t_cl += t_cc
+            t_cl += time.perf_counter() - t
+            f += oracle.chol_step_flops(args.n, s)
+            del s_host
         cpu = {"value": round(f / t_cl / 1e12, 6), "unit": "TFLOP/s", "cores": oracle.get_threads(),
                "kind": "oracle",
-               "sample": f"first {s} elimination steps of the n={n} LU (and Cholesky) on the same inputs, "
-                         f"{t_cl:.1f} s"}
+               "sample": f"first {s} elimination steps of the n={args.n} LU and Cholesky factorizations of the "
+                         f"benchmark's own inputs ({f:.3e} flop in {t_cl:.1f} s)"}
+    del a_host, S0
+    torch.cuda.empty_cache()
+    if not args.no_mixed:
+        detail["mixed"] = mixed_section(args, torch, cdf, workloads, h)
+    if not args.no_batched:
+        detail["batched"] = batched_section(args, torch, cdf, workloads, h, tuned)
 
+    n = args.n
     out = {
-        "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": K, "warmup": W,
-        "ms_per_step": round(ms, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"FP64 LU (uniform[-1,1]) + FP64 Cholesky (B B^T/N + I), N={n}, one matrix each per step", "n": n, "lu_nb": lu_nb, "chol_nb": chol_nb},
-        "roofline": roofline,
+        "metric": METRIC, "value": round(fp["value"], 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(fp["ms"], 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"FP64 LU with partial pivoting (uniform[-1,1]) + FP64 Cholesky (B B^T/N + I), "
+                               f"N={n}, one matrix each per step", "n": n, "lu_nb": fp["lu_nb"],
+                   "chol_nb": fp["chol_nb"]},
+        "roofline": fp["roofline"],
         "cpu_baseline": cpu,
-        "detail": {"lu_tflops": round(flops_lu / t_lu / 1e12, 3),
-                   "chol_tflops": round(flops_ch / t_ch / 1e12, 3) if chol_copies else None,
-                   "lu_s": round(t_lu, 4), "chol_s": round(t_ch, 4) if chol_copies else None,
-                   "frac_fp64_peak": round(value / FP64_PEAK_TFLOPS, 4)},
+        "detail": detail,
     }
     print(json.dumps(out), flush=True)
 

@@ -99,6 +99,31 @@ def batch_problem(i: int, n: int, kind: int, seed: int = SEED_MATRIX) -> np.ndar
     return lu_uniform(n, seed=s) if kind == 0 else spd_bbt(n, seed=s)
 
 
+def diag_dominant_torch(n: int, seed: int = SEED_MATRIX, device: str = "cuda"):
+    """diag_dominant() drawn on the GPU with torch's seeded generator (same
+    distribution, different stream), column-major view; for sizes where a
+    host draw would dominate the run time."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    a = torch.empty((n, n), dtype=torch.float64, device=device)  # a[j, i] = entry (i, j)
+    a.uniform_(-0.5, 0.5, generator=g)
+    rows = torch.zeros(n, dtype=torch.float64, device=device)
+    for j0 in range(0, n, 2048):        # row sums of the column-major matrix, in column slabs
+        rows += a[j0:j0 + 2048].abs().sum(dim=0)
+    a.diagonal().copy_(rows)
+    return a.t()
+
+
+def rhs_uniform_torch(n: int, nrhs: int = 1, seed: int = SEED_RHS, device: str = "cuda"):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    b = torch.empty((nrhs, n), dtype=torch.float64, device=device)
+    b.uniform_(-1.0, 1.0, generator=g)
+    return b.t() if nrhs > 1 else b[0]
+
+
 def sha256(a: np.ndarray) -> str:
     """SHA-256 of the array's column-major bytes (records which bits a run used)."""
     return hashlib.sha256(np.asfortranarray(a).tobytes(order="F")).hexdigest()
