@@ -31,6 +31,7 @@ inline int chol_nb(cdf_handle_t h) {
 
 // Slots for the LU leaf's grid exchange: 2 parities x (G x 34) + 2 x 32 doubles.
 constexpr size_t kLeafSlotBytes = (2 * 256 * 34 + 64) * sizeof(double) * 4;
+constexpr size_t kLuWsBytes = kLeafSlotBytes + 256 * sizeof(int) + (1 + 2 * 512) * sizeof(int) + 4096;
 
 }  // namespace
 
@@ -42,11 +43,10 @@ namespace cdf {
 // interchanges to every other column of the region, so the region stays
 // consistently permuted.  Pivots are written relative to the region's row 0;
 // info values are offset by info_off.
-hipError_t lu_panel(cdf_handle_t h, int m, int ncols, double *A, int lda, int *ipiv, int *info, int c0, int w,
-                    int info_off) {
-    hipStream_t s = h->stream;
+hipError_t lu_panel(cdf_handle_t h, hipStream_t s, int m, int ncols, double *A, int lda, int *ipiv, int *info,
+                    int c0, int w, int info_off) {
     if (w <= 32) {
-        CDF_HIP_RET(lu_leaf(h, m - c0, w, A + c0 + (size_t)c0 * lda, lda, ipiv + c0, c0, info, info_off + c0,
+        CDF_HIP_RET(lu_leaf(h, s, m - c0, w, A + c0 + (size_t)c0 * lda, lda, ipiv + c0, c0, info, info_off + c0,
                             h->params[CDF_PARAM_LU_LEAF_ROWS]));
         CDF_HIP_RET(laswp(s, 0, c0, A, lda, ipiv, c0, c0 + w, m));
         CDF_HIP_RET(laswp(s, c0 + w, ncols, A, lda, ipiv, c0, c0 + w, m));
@@ -54,14 +54,14 @@ hipError_t lu_panel(cdf_handle_t h, int m, int ncols, double *A, int lda, int *i
     }
     const int n1 = ((w / 2 + 31) / 32) * 32;
     const int n2 = w - n1;
-    CDF_HIP_RET(lu_panel(h, m, ncols, A, lda, ipiv, info, c0, n1, info_off));
+    CDF_HIP_RET(lu_panel(h, s, m, ncols, A, lda, ipiv, info, c0, n1, info_off));
     double *a11 = A + c0 + (size_t)c0 * lda;
     double *a12 = A + c0 + (size_t)(c0 + n1) * lda;
     double *a21 = A + (c0 + n1) + (size_t)c0 * lda;
     double *a22 = A + (c0 + n1) + (size_t)(c0 + n1) * lda;
-    CDF_HIP_RET(trsm_small(s, TRSM_LLNU, n1, n2, a11, lda, a12, lda));
+    CDF_HIP_RET(trsm_blocked(s, TRSM_LLNU, n1, n2, a11, lda, a12, lda, 64));
     CDF_HIP_RET(dgemm(s, 0, 0, m - c0 - n1, n2, n1, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false));
-    return lu_panel(h, m, ncols, A, lda, ipiv, info, c0 + n1, n2, info_off);
+    return lu_panel(h, s, m, ncols, A, lda, ipiv, info, c0 + n1, n2, info_off);
 }
 
 // Blocked right-looking lower Cholesky of the n x n matrix A: potrf of each
@@ -89,34 +89,138 @@ hipError_t potrf_blocked(cdf_handle_t h, int n, double *A, int lda, int *info, i
 
 namespace {
 
+hipError_t ensure_aux(cdf_handle_t h) {
+    if (!h->aux) CDF_HIP_RET(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    for (auto &e : h->ev)
+        if (!e) CDF_HIP_RET(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return hipSuccess;
+}
+
+struct LuWs {
+    int *ipt;    // region-relative pivots of the current panel
+    int *pairs;  // its interchange pairs
+};
+
+// Panel [k, k+kb) over rows [k, n) as a region: pivots relative to row k in
+// ws.ipt, absolute (1-based) in ipiv[k..k+kb), pairs built for the region.
+hipError_t factor_panel(cdf_handle_t h, hipStream_t s, int n, double *A, int lda, int *ipiv, int *info, int k,
+                        int kb, LuWs &ws) {
+    double *R = A + k + (size_t)k * lda;
+    CDF_HIP_RET(cdf::lu_panel(h, s, n - k, kb, R, lda, ws.ipt, info, 0, kb, k));
+    CDF_HIP_RET(cdf::offset_pivots(s, ws.ipt, ipiv + k, kb, k));
+    return cdf::build_pairs(s, ws.ipt, 0, kb, n - k, ws.pairs);
+}
+
+// Blocked right-looking LU with look-ahead of depth one: while the trailing
+// update of panel k runs on the handle's stream, panel k+1 (whose columns
+// were updated first) is factored on a second stream; its interchanges are
+// applied to the other columns once both are done.
 hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info) {
-    hipStream_t s = h->stream;
-    CDF_HIP_RET(cdf::fill_int(s, info, 1, 0));
+    hipStream_t s0 = h->stream;
+    CDF_HIP_RET(ensure_aux(h));
+    hipStream_t s1 = h->aux;
+    CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
     const int nb = lu_nb(h);
+    LuWs ws;
+    char *base = static_cast<char *>(h->ws) + kLeafSlotBytes;
+    ws.ipt = reinterpret_cast<int *>(base);
+    ws.pairs = reinterpret_cast<int *>(base + 256 * sizeof(int));
+    const int kb0 = nb < n ? nb : n;
+    CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, 0, kb0, ws));
+    CDF_HIP_RET(cdf::apply_pairs(s0, kb0, n, A, lda, ws.pairs));
     for (int k = 0; k < n; k += nb) {
         const int kb = nb < n - k ? nb : n - k;
-        CDF_HIP_RET(cdf::lu_panel(h, n, n, A, lda, ipiv, info, k, kb, 0));
+        const int k1 = k + kb;
+        if (k1 >= n) break;
+        const int kb1 = nb < n - k1 ? nb : n - k1;
+        const int rest = n - k1;
+        double *l11 = A + k + (size_t)k * lda;
+        double *a21 = A + k1 + (size_t)k * lda;
+        // next panel's columns first
+        CDF_HIP_RET(cdf::trsm_blocked(s0, cdf::TRSM_LLNU, kb, kb1, l11, lda, A + k + (size_t)k1 * lda, lda, 64));
+        CDF_HIP_RET(cdf::dgemm(s0, 0, 0, rest, kb1, kb, -1.0, a21, lda, A + k + (size_t)k1 * lda, lda, 1.0,
+                               A + k1 + (size_t)k1 * lda, lda, false));
+        if (rest > kb1) {
+            CDF_HIP_RET(hipEventRecord(h->ev[0], s0));
+            CDF_HIP_RET(hipStreamWaitEvent(s1, h->ev[0], 0));
+            CDF_HIP_RET(factor_panel(h, s1, n, A, lda, ipiv, info, k1, kb1, ws));
+            CDF_HIP_RET(hipEventRecord(h->ev[1], s1));
+            const int c2 = k1 + kb1;
+            CDF_HIP_RET(cdf::trsm_blocked(s0, cdf::TRSM_LLNU, kb, n - c2, l11, lda, A + k + (size_t)c2 * lda, lda, 64));
+            CDF_HIP_RET(cdf::dgemm(s0, 0, 0, rest, n - c2, kb, -1.0, a21, lda, A + k + (size_t)c2 * lda, lda, 1.0,
+                                   A + k1 + (size_t)c2 * lda, lda, false));
+            CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[1], 0));
+        } else {
+            CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, k1, kb1, ws));
+        }
+        CDF_HIP_RET(cdf::apply_pairs(s0, 0, k1, A + k1, lda, ws.pairs));
+        CDF_HIP_RET(cdf::apply_pairs(s0, k1 + kb1, n, A + k1, lda, ws.pairs));
+    }
+    return hipSuccess;
+}
+
+// Blocked right-looking lower Cholesky with look-ahead of depth one: the
+// next block column is updated first, then its diagonal block (potrf) and
+// L21 (trsm) run on the second stream while the rest of the trailing lower
+// triangle is updated on the handle's stream.  Only the lower triangle is
+// touched; every launch after a failed pivot is a no-op (stop = info).
+hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
+    hipStream_t s0 = h->stream;
+    CDF_HIP_RET(ensure_aux(h));
+    hipStream_t s1 = h->aux;
+    CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
+    const int nb = chol_nb(h);
+    auto panel = [&](hipStream_t s, int k, int kb) -> hipError_t {
+        double *a11 = A + k + (size_t)k * lda;
+        CDF_HIP_RET(cdf::potrf_diag(s, kb, a11, lda, info, k));
         const int rest = n - k - kb;
-        if (rest > 0) {
-            double *a11 = A + k + (size_t)k * lda;
-            double *a12 = A + k + (size_t)(k + kb) * lda;
-            double *a21 = A + (k + kb) + (size_t)k * lda;
-            double *a22 = A + (k + kb) + (size_t)(k + kb) * lda;
-            CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_LLNU, kb, rest, a11, lda, a12, lda));
-            CDF_HIP_RET(cdf::dgemm(s, 0, 0, rest, rest, kb, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false));
+        if (rest > 0) CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_RLTN, kb, rest, a11, lda, a11 + kb, lda, info));
+        return hipSuccess;
+    };
+    CDF_HIP_RET(panel(s0, 0, nb < n ? nb : n));
+    for (int k = 0; k < n; k += nb) {
+        const int kb = nb < n - k ? nb : n - k;
+        const int k1 = k + kb;
+        if (k1 >= n) break;
+        const int kb1 = nb < n - k1 ? nb : n - k1;
+        const int rest = n - k1;
+        double *l21 = A + k1 + (size_t)k * lda;                 // rest x kb
+        double *d1 = A + k1 + (size_t)k1 * lda;                 // next diagonal block
+        // next block column: its diagonal block (lower only) and the rows below it
+        CDF_HIP_RET(cdf::dgemm(s0, 0, 1, kb1, kb1, kb, -1.0, l21, lda, l21, lda, 1.0, d1, lda, true, info));
+        if (rest > kb1)
+            CDF_HIP_RET(cdf::dgemm(s0, 0, 1, rest - kb1, kb1, kb, -1.0, l21 + kb1, lda, l21, lda, 1.0, d1 + kb1, lda,
+                                   false, info));
+        if (rest > kb1) {
+            CDF_HIP_RET(hipEventRecord(h->ev[0], s0));
+            CDF_HIP_RET(hipStreamWaitEvent(s1, h->ev[0], 0));
+            CDF_HIP_RET(panel(s1, k1, kb1));
+            CDF_HIP_RET(hipEventRecord(h->ev[1], s1));
+            const int c2 = k1 + kb1;
+            CDF_HIP_RET(cdf::dgemm(s0, 0, 1, n - c2, n - c2, kb, -1.0, l21 + kb1, lda, l21 + kb1, lda, 1.0,
+                                   A + c2 + (size_t)c2 * lda, lda, true, info));
+            CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[1], 0));
+        } else {
+            CDF_HIP_RET(panel(s0, k1, kb1));
         }
     }
     return hipSuccess;
 }
 
-hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
-    CDF_HIP_RET(cdf::fill_int(h->stream, info, 1, 0));
-    return cdf::potrf_blocked(h, n, A, lda, info, 0, chol_nb(h));
-}
-
 }  // namespace
 
 namespace cdf {
+
+__global__ void offset_kernel(const int *__restrict__ a, int *__restrict__ b, int count, int off) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) b[i] = a[i] + off;
+}
+
+hipError_t offset_pivots(hipStream_t s, const int *ipiv_in, int *ipiv_out, int count, int off) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(offset_kernel, dim3((count + 255) / 256), dim3(256), 0, s, ipiv_in, ipiv_out, count, off);
+    return hipGetLastError();
+}
 
 hipError_t fill_int(hipStream_t s, int *p, int count, int v) {
     if (count <= 0) return hipSuccess;
@@ -176,6 +280,9 @@ cdf_status_t cdf_destroy(cdf_handle_t h) {
     (void)hipStreamSynchronize(h->stream);
     if (h->ws) (void)hipFree(h->ws);
     if (h->sync) (void)hipFree(h->sync);
+    if (h->aux) { (void)hipStreamSynchronize(h->aux); (void)hipStreamDestroy(h->aux); }
+    for (auto &e : h->ev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
     return CDF_OK;
 }
@@ -241,7 +348,7 @@ cdf_status_t cdf_dgetrf(cdf_handle_t h, int n, double *A, int lda, int *ipiv, in
         CDF_HIP_TRY(cdf::fill_int(h->stream, info, 1, 0));
         return CDF_OK;
     }
-    cdf_status_t st = cdf::ws_reserve(h, kLeafSlotBytes);
+    cdf_status_t st = cdf::ws_reserve(h, kLuWsBytes);
     if (st != CDF_OK) return st;
     CDF_HIP_TRY(getrf_impl(h, n, A, lda, ipiv, info));
     return CDF_OK;
@@ -265,6 +372,11 @@ cdf_status_t cdf_dgetrs(cdf_handle_t h, char trans, int n, int nrhs, const doubl
     if (!B) return bad(h, 8);
     hipStream_t s = h->stream;
     CDF_HIP_TRY(cdf::laswp(s, 0, nrhs, B, ldb, ipiv, 0, n, n));
+    if (nrhs <= 4) {
+        CDF_HIP_TRY(cdf::trsv_blocked(s, cdf::TRSM_LLNU, n, nrhs, A, lda, B, ldb));
+        CDF_HIP_TRY(cdf::trsv_blocked(s, cdf::TRSM_LUNN, n, nrhs, A, lda, B, ldb));
+        return CDF_OK;
+    }
     CDF_HIP_TRY(cdf::trsm_blocked(s, cdf::TRSM_LLNU, n, nrhs, A, lda, B, ldb));
     CDF_HIP_TRY(cdf::trsm_blocked(s, cdf::TRSM_LUNN, n, nrhs, A, lda, B, ldb));
     return CDF_OK;
@@ -305,6 +417,11 @@ cdf_status_t cdf_dpotrs(cdf_handle_t h, char uplo, int n, int nrhs, const double
     if (!A) return bad(h, 5);
     if (!B) return bad(h, 7);
     hipStream_t s = h->stream;
+    if (nrhs <= 4) {
+        CDF_HIP_TRY(cdf::trsv_blocked(s, cdf::TRSM_LLNN, n, nrhs, A, lda, B, ldb));
+        CDF_HIP_TRY(cdf::trsv_blocked(s, cdf::TRSM_LLTN, n, nrhs, A, lda, B, ldb));
+        return CDF_OK;
+    }
     CDF_HIP_TRY(cdf::trsm_blocked(s, cdf::TRSM_LLNN, n, nrhs, A, lda, B, ldb));
     CDF_HIP_TRY(cdf::trsm_blocked(s, cdf::TRSM_LLTN, n, nrhs, A, lda, B, ldb));
     return CDF_OK;

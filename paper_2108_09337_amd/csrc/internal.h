@@ -16,6 +16,8 @@ struct cdf_handle_s {
     size_t ws_limit = 0;         // 0 = no cap
     int *sync = nullptr;         // zeroed counters for grid-wide barriers
     int bad_arg = 0;
+    hipStream_t aux = nullptr;   // second stream for look-ahead (default priority)
+    hipEvent_t ev[2] = {nullptr, nullptr};
     int params[CDF_PARAM_COUNT] = {0, 0, 0, 0, 0, 0};
 };
 
@@ -40,14 +42,24 @@ hipError_t dgemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alph
 // LU panel leaf: factor the m x n (n <= 32) column block at A with partial
 // pivoting; writes absolute 1-based pivots ipiv[0..n) (row offset `row0`
 // added), first zero pivot into *info (as info_base + j + 1) if *info == 0.
-hipError_t lu_leaf(cdf_handle_t h, int m, int n, double *A, int lda, int *ipiv, int row0,
-                   int *info, int info_base, int rows_per_thread);
+hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, int lda, int *ipiv,
+                   int row0, int *info, int info_base, int rows_per_thread);
 
 // Recursive LU panel of columns [c0, c0+w) of the m x ncols region A (rows
-// [c0, m)); interchanges are applied to all other columns of the region;
-// pivots are relative to the region's row 0; info offset by info_off.
-hipError_t lu_panel(cdf_handle_t h, int m, int ncols, double *A, int lda, int *ipiv, int *info, int c0,
-                    int w, int info_off);
+// [c0, m)) on stream s; interchanges are applied to all other columns of the
+// region; pivots are relative to the region's row 0; info offset by info_off.
+hipError_t lu_panel(cdf_handle_t h, hipStream_t s, int m, int ncols, double *A, int lda, int *ipiv, int *info,
+                    int c0, int w, int info_off);
+
+// Panel-wide interchanges: build (dst, src) pairs of ipiv[k1..k2) (<= 256,
+// region-relative, 1-based) once into `pairs` (pairs_ints() ints), then
+// apply them to any column range.
+size_t pairs_ints();
+hipError_t build_pairs(hipStream_t s, const int *ipiv, int k1, int k2, int nrows, int *pairs);
+hipError_t apply_pairs(hipStream_t s, int c0, int c1, double *A, int lda, const int *pairs);
+hipError_t apply_pairs(hipStream_t s, int c0, int c1, float *A, int lda, const int *pairs);
+// ipiv_out[i] = ipiv_in[i] + off for i < count.
+hipError_t offset_pivots(hipStream_t s, const int *ipiv_in, int *ipiv_out, int count, int off);
 // Blocked lower Cholesky of an n x n matrix (block width nb <= 128).
 hipError_t potrf_blocked(cdf_handle_t h, int n, double *A, int lda, int *info, int info_off, int nb);
 
@@ -75,10 +87,14 @@ hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const dou
 hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
                       float *B, int ldb, const int *stop = nullptr);
 
-// Full triangular solve with a large n x n factor (blocked: small diagonal
-// solves + GEMM updates).
+// Full triangular solve with a large n x n factor (blocked: bs-wide diagonal
+// solves + GEMM updates; bs <= 256).
 hipError_t trsm_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const double *T, int ldt,
-                        double *B, int ldb);
+                        double *B, int ldb, int bs = 128);
+// Solve with few right-hand sides (ncols <= 4): 64-row diagonal blocks solved
+// by one wave in registers, off-diagonal blocks applied GEMV-style.
+hipError_t trsv_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const double *T, int ldt, double *B,
+                        int ldb);
 
 // Cholesky of one diagonal block (n <= 128) held in LDS; stops at the first
 // non-positive pivot, writing info_base + j + 1 into *info if *info == 0.

@@ -294,12 +294,101 @@ hipError_t laswp_impl(hipStream_t s, int c0, int c1, T *A, int lda, const int *i
     return hipSuccess;
 }
 
+
+// ------------------------------------------------- panel-wide interchanges
+
+constexpr int PMAX = 256;            // interchanges per panel
+constexpr int PPAIRS = 2 * PMAX;
+constexpr int PSLOT = PPAIRS / 64;   // positions per lane
+
+// (dst, src) pairs of the interchanges ipiv[k1..k2) (k2 - k1 <= 256,
+// relative to row 0 of the region, 1-based; entries outside [k+1, nrows]
+// ignored), simulated by one thread on LDS: positions [k1, k2) in a direct
+// array, the other rows touched in an open-addressing hash table.
+// pairs[0] = count, pairs[1 + q] = dst row, pairs[1 + PPAIRS + q] = src row.
+__global__ __launch_bounds__(256) void pairs_kernel(const int *__restrict__ ipiv, int k1, int k2, int nrows,
+                                                    int *__restrict__ pairs) {
+    constexpr int HS = 1024;
+    __shared__ int blk[PMAX];
+    __shared__ int piv[PMAX];
+    __shared__ int hkey[HS], hval[HS];
+    __shared__ int cnt;
+    const int t = threadIdx.x;
+    const int nk = k2 - k1;
+    for (int i = t; i < HS; i += 256) hkey[i] = -1;
+    if (t < nk) {
+        blk[t] = k1 + t;
+        int p = ipiv[k1 + t] - 1;
+        piv[t] = (p < k1 + t || p >= nrows) ? k1 + t : p;
+    }
+    if (t == 0) cnt = 0;
+    __syncthreads();
+    if (t == 0) {
+        for (int j = 0; j < nk; ++j) {
+            const int k = k1 + j, p = piv[j];
+            if (p == k) continue;
+            const int ck = blk[j];
+            if (p < k2) {
+                blk[j] = blk[p - k1];
+                blk[p - k1] = ck;
+            } else {
+                unsigned hsh = ((unsigned)p * 2654435761u) >> 22;  // 10 bits
+                while (hkey[hsh] != -1 && hkey[hsh] != p) hsh = (hsh + 1) & (HS - 1);
+                if (hkey[hsh] == -1) { hkey[hsh] = p; hval[hsh] = p; }
+                blk[j] = hval[hsh];
+                hval[hsh] = ck;
+            }
+        }
+    }
+    __syncthreads();
+    if (t < nk && blk[t] != k1 + t) {
+        const int o = atomicAdd(&cnt, 1);
+        pairs[1 + o] = k1 + t;
+        pairs[1 + PPAIRS + o] = blk[t];
+    }
+    for (int i = t; i < HS; i += 256)
+        if (hkey[i] != -1 && hval[i] != hkey[i]) {
+            const int o = atomicAdd(&cnt, 1);
+            pairs[1 + o] = hkey[i];
+            pairs[1 + PPAIRS + o] = hval[i];
+        }
+    __syncthreads();
+    if (t == 0) pairs[0] = cnt;
+}
+
+// Applies prebuilt pairs to columns [0, ncols) of A (rows offset by the
+// region base already folded into A): 8 columns per workgroup, every moved
+// row read before any is written.
+template <typename T>
+__global__ __launch_bounds__(256) void apply_pairs_kernel(int ncols, T *__restrict__ A, int lda,
+                                                          const int *__restrict__ pairs) {
+    constexpr int CW = 8, PER = PPAIRS * CW / 256;
+    const int np = pairs[0];
+    if (np == 0) return;
+    const int cbase = blockIdx.x * CW;
+    const int total = np * CW;
+    T v[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int e = threadIdx.x + 256 * r;
+        const int q = e % np, c = cbase + e / np;
+        if (e < total && c < ncols) v[r] = A[(size_t)pairs[1 + PPAIRS + q] + (size_t)c * lda];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int e = threadIdx.x + 256 * r;
+        const int q = e % np, c = cbase + e / np;
+        if (e < total && c < ncols) A[(size_t)pairs[1 + q] + (size_t)c * lda] = v[r];
+    }
+}
+
 }  // namespace
 
 namespace cdf {
 
-hipError_t lu_leaf(cdf_handle_t h, int m, int n, double *A, int lda, int *ipiv, int row0, int *info,
-                   int info_base, int rows_per_thread) {
+hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, int lda, int *ipiv, int row0,
+                   int *info, int info_base, int rows_per_thread) {
     if (m <= 0 || n <= 0) return hipSuccess;
     if (n > LW || n > m) return hipErrorInvalidValue;
     static bool attr = false;
@@ -321,8 +410,33 @@ hipError_t lu_leaf(cdf_handle_t h, int m, int n, double *A, int lda, int *ipiv, 
     const void *fn = R == 1 ? reinterpret_cast<const void *>(&lu_leaf_kernel<1>)
                             : reinterpret_cast<const void *>(&lu_leaf_kernel<2>);
     const size_t lds = (size_t)LW * LT * R * sizeof(double);
-    if (G == 1) return hipLaunchKernel(fn, dim3(1), dim3(LT), args, lds, h->stream);
-    return hipLaunchCooperativeKernel(fn, dim3(G), dim3(LT), args, (unsigned)lds, h->stream);
+    // A plain launch: G <= number of CUs and each CU fits a leaf workgroup, so
+    // all G become resident at the latest when the (finite) kernels that may
+    // run beside it on other streams have drained; the grid barrier then
+    // completes.  (A cooperative launch would forbid that overlap.)
+    return hipLaunchKernel(fn, dim3(G), dim3(LT), args, lds, stream);
+}
+
+size_t pairs_ints() { return 1 + 2 * PPAIRS; }
+
+hipError_t build_pairs(hipStream_t s, const int *ipiv, int k1, int k2, int nrows, int *pairs) {
+    if (k2 - k1 > PMAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pairs_kernel, dim3(1), dim3(256), 0, s, ipiv, k1, k2, nrows, pairs);
+    return hipGetLastError();
+}
+
+hipError_t apply_pairs(hipStream_t s, int c0, int c1, double *A, int lda, const int *pairs) {
+    if (c1 <= c0) return hipSuccess;
+    hipLaunchKernelGGL((apply_pairs_kernel<double>), dim3((c1 - c0 + 7) / 8), dim3(256), 0, s, c1 - c0,
+                       A + (size_t)c0 * lda, lda, pairs);
+    return hipGetLastError();
+}
+
+hipError_t apply_pairs(hipStream_t s, int c0, int c1, float *A, int lda, const int *pairs) {
+    if (c1 <= c0) return hipSuccess;
+    hipLaunchKernelGGL((apply_pairs_kernel<float>), dim3((c1 - c0 + 7) / 8), dim3(256), 0, s, c1 - c0,
+                       A + (size_t)c0 * lda, lda, pairs);
+    return hipGetLastError();
 }
 
 hipError_t laswp(hipStream_t s, int c0, int c1, double *A, int lda, const int *ipiv, int k1, int k2,

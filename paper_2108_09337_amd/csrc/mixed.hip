@@ -210,11 +210,23 @@ __global__ __launch_bounds__(NT) void lowp_gemm_kernel(int m, int n, int kpad, c
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int lrow = lane & 15, lk = lane >> 4;
+    // C enters the accumulators scaled by 2^(ea+eb) and negated (exact power
+    // of two), so the K loop accumulates -C 2^s + sum(qa qb) and the epilogue
+    // only stores -acc 2^-s.
+    const int sc = ea[tm] + eb[tn];
     v4f acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + wn * 64 + j * 16 + lrow;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 64 + i * 16 + lk * 4 + v;
+                acc[i][j][v] = (row < m && col < n && (!LOWER || row >= col))
+                                   ? -ldexpf(C[(size_t)row + (size_t)col * ldc], sc) : 0.f;
+            }
+        }
     size_t aoff[4], boff[4];
     bool aok[4], bok[4];
 #pragma unroll
@@ -247,7 +259,6 @@ __global__ __launch_bounds__(NT) void lowp_gemm_kernel(int m, int n, int kpad, c
 #pragma unroll
         for (int i = 0; i < 4; ++i) { a[i] = an[i]; b[i] = bn[i]; }
     }
-    const int sc = -(ea[tm] + eb[tn]);
     // 16x16 f32 output block: register v of a lane holds row 4*(lane/16)+v, column lane%16.
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -257,10 +268,8 @@ __global__ __launch_bounds__(NT) void lowp_gemm_kernel(int m, int n, int kpad, c
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = m0 + wm * 64 + i * 16 + lk * 4 + v;
-                if (row < m && col < n && (!LOWER || row >= col)) {
-                    float *p = C + (size_t)row + (size_t)col * ldc;
-                    *p = *p - ldexpf(acc[i][j][v], sc);
-                }
+                if (row < m && col < n && (!LOWER || row >= col))
+                    C[(size_t)row + (size_t)col * ldc] = -ldexpf(acc[i][j][v], -sc);
             }
         }
 }
@@ -317,6 +326,38 @@ __global__ void vec_absmax_kernel(int n, const double *__restrict__ x, double *_
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
         atomic_max_pos(out, r);
     }
+}
+
+// R = B - A X for nrhs <= 4 (binary64): 64 rows per workgroup, one row per
+// lane, the 4 waves take interleaved column slabs; partial sums are combined
+// in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void residual_gemv_kernel(int n, int nrhs, const double *__restrict__ A, int lda,
+                                                            const double *__restrict__ X, int ldx,
+                                                            const double *__restrict__ B, int ldb,
+                                                            double *__restrict__ R, int ldr) {
+    __shared__ double part[4][4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = blockIdx.x * 64 + lane;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (r < n) {
+        for (int j0 = wave * 64; j0 < n; j0 += 256) {
+            const int j1 = min(j0 + 64, n);
+            for (int j = j0; j < j1; ++j) {
+                const double a = A[(size_t)r + (size_t)j * lda];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (c < nrhs) acc[c] = fma(a, X[(size_t)j + (size_t)c * ldx], acc[c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) part[wave][c][lane] = acc[c];
+    __syncthreads();
+    if (wave == 0 && r < n)
+        for (int c = 0; c < nrhs; ++c) {
+            const double ax = ((part[0][c][lane] + part[1][c][lane]) + part[2][c][lane]) + part[3][c][lane];
+            R[(size_t)r + (size_t)c * ldr] = B[(size_t)r + (size_t)c * ldb] - ax;
+        }
 }
 
 __global__ void zero_d_kernel(double *p, int count) {
@@ -422,6 +463,7 @@ struct MixedWs {
     double *Wd = nullptr;      // binary64 copy of the finished factor (for the solves)
     double *Afull = nullptr;   // symmetric extension of A (Cholesky residual)
     double *P = nullptr;       // binary64 panel, n x nb
+    double *U = nullptr;       // binary64 staging of U12, nb x n
     void *QA = nullptr, *QB = nullptr;
     int *ea = nullptr, *eb = nullptr, *ipt = nullptr, *ipiv = nullptr;
     double *R = nullptr, *red = nullptr;
@@ -443,6 +485,7 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     const size_t oWd = factor_only ? 0 : take(nn * sizeof(double));
     const size_t oAf = (chol && !factor_only) ? take(nn * sizeof(double)) : 0;
     const size_t oP = take((size_t)n * nb * sizeof(double));
+    const size_t oU = take((size_t)n * nb * sizeof(double));
     const size_t oQA = take(kp * n * esize(fmt));
     const size_t oQB = take(kp * n * esize(fmt));
     const int nt = (n + QT - 1) / QT + 1;
@@ -457,6 +500,7 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     w.Wd = factor_only ? nullptr : reinterpret_cast<double *>(base + oWd);
     w.Afull = (chol && !factor_only) ? reinterpret_cast<double *>(base + oAf) : nullptr;
     w.P = reinterpret_cast<double *>(base + oP);
+    w.U = reinterpret_cast<double *>(base + oU);
     w.QA = base + oQA;
     w.QB = base + oQB;
     w.ea = reinterpret_cast<int *>(base + oea);
@@ -482,7 +526,7 @@ hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *i
         const int kb = nb < n - k ? nb : n - k;
         const int m = n - k, rest = n - k - kb;
         CDF_HIP_RET(cdf::convert_s2d(s, m, kb, W + k + (size_t)k * ldw, ldw, w.P, m, false));
-        CDF_HIP_RET(cdf::lu_panel(h, m, kb, w.P, m, w.ipt, info, 0, kb, k));
+        CDF_HIP_RET(cdf::lu_panel(h, s, m, kb, w.P, m, w.ipt, info, 0, kb, k));
         hipLaunchKernelGGL(add_offset_kernel, dim3((kb + 255) / 256), dim3(256), 0, s, w.ipt, ipiv + k, kb, k);
         CDF_HIP_RET(hipGetLastError());
         CDF_HIP_RET(cdf::convert_d2s(s, m, kb, w.P, m, W + k + (size_t)k * ldw, ldw, false));
@@ -492,7 +536,9 @@ hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *i
             float *w12 = W + k + (size_t)(k + kb) * ldw;
             float *w21 = W + (k + kb) + (size_t)k * ldw;
             float *w22 = W + (k + kb) + (size_t)(k + kb) * ldw;
-            CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_LLNU, kb, rest, w.P, m, w12, ldw));
+            CDF_HIP_RET(cdf::convert_s2d(s, kb, rest, w12, ldw, w.U, kb, false));
+            CDF_HIP_RET(cdf::trsm_blocked(s, cdf::TRSM_LLNU, kb, rest, w.P, m, w.U, kb, 64));
+            CDF_HIP_RET(cdf::convert_d2s(s, kb, rest, w.U, kb, w12, ldw, false));
             CDF_HIP_RET(cdf::quantize(s, fmt, rest, kb, w21, ldw, QT, kb, w.QA, kp, w.ea, true));
             CDF_HIP_RET(cdf::quantize(s, fmt, kb, rest, w12, ldw, kb, QT, w.QB, kp, w.eb, false));
             CDF_HIP_RET(cdf::lowp_update(s, fmt, rest, rest, kb, w.QA, kp, w.ea, w.QB, kp, w.eb, w22, ldw, false,
@@ -571,7 +617,7 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
             const int lnb = h->params[CDF_PARAM_LU_NB] > 0 ? h->params[CDF_PARAM_LU_NB] : 256;
             for (int k = 0; k < n; k += lnb) {
                 const int kb = lnb < n - k ? lnb : n - k, rest = n - k - kb;
-                CDF_HIP_TRY(cdf::lu_panel(h, n, n, w.Wd, n, w.ipiv, info, k, kb, 0));
+                CDF_HIP_TRY(cdf::lu_panel(h, s, n, n, w.Wd, n, w.ipiv, info, k, kb, 0));
                 if (rest > 0) {
                     double *a11 = w.Wd + k + (size_t)k * n, *a12 = w.Wd + k + (size_t)(k + kb) * n;
                     double *a21 = w.Wd + (k + kb) + (size_t)k * n, *a22 = w.Wd + (k + kb) + (size_t)(k + kb) * n;
@@ -594,14 +640,18 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
     *iters = 0;
     *resid = INFINITY;
     if (hinfo != 0) return CDF_ERR_NOT_CONVERGED;
+    auto tri = [&](cdf::TrsmKind kind, double *Y, int ldy) -> hipError_t {
+        return nrhs <= 4 ? cdf::trsv_blocked(s, kind, n, nrhs, w.Wd, n, Y, ldy)
+                         : cdf::trsm_blocked(s, kind, n, nrhs, w.Wd, n, Y, ldy);
+    };
     auto solve = [&](double *Y, int ldy) -> hipError_t {
         if (chol) {
-            CDF_HIP_RET(cdf::trsm_blocked(s, cdf::TRSM_LLNN, n, nrhs, w.Wd, n, Y, ldy));
-            return cdf::trsm_blocked(s, cdf::TRSM_LLTN, n, nrhs, w.Wd, n, Y, ldy);
+            CDF_HIP_RET(tri(cdf::TRSM_LLNN, Y, ldy));
+            return tri(cdf::TRSM_LLTN, Y, ldy);
         }
         CDF_HIP_RET(cdf::laswp(s, 0, nrhs, Y, ldy, w.ipiv, 0, n, n));
-        CDF_HIP_RET(cdf::trsm_blocked(s, cdf::TRSM_LLNU, n, nrhs, w.Wd, n, Y, ldy));
-        return cdf::trsm_blocked(s, cdf::TRSM_LUNN, n, nrhs, w.Wd, n, Y, ldy);
+        CDF_HIP_RET(tri(cdf::TRSM_LLNU, Y, ldy));
+        return tri(cdf::TRSM_LUNN, Y, ldy);
     };
     CDF_HIP_TRY(cdf::copy_cols(s, n, nrhs, B, ldb, X, ldx));
     CDF_HIP_TRY(solve(X, ldx));
@@ -609,8 +659,14 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
     double *nrm = w.red + 1;
     for (int it = 0;; ++it) {
         // r = b - A x (binary64, original A)
-        CDF_HIP_TRY(cdf::copy_cols(s, n, nrhs, B, ldb, w.R, n));
-        CDF_HIP_TRY(cdf::dgemm(s, 0, 0, n, nrhs, n, -1.0, Ares, ldres, X, ldx, 1.0, w.R, n, false));
+        if (nrhs <= 4) {
+            hipLaunchKernelGGL(residual_gemv_kernel, dim3((n + 63) / 64), dim3(256), 0, s, n, nrhs, Ares, ldres, X, ldx,
+                               B, ldb, w.R, n);
+            CDF_HIP_TRY(hipGetLastError());
+        } else {
+            CDF_HIP_TRY(cdf::copy_cols(s, n, nrhs, B, ldb, w.R, n));
+            CDF_HIP_TRY(cdf::dgemm(s, 0, 0, n, nrhs, n, -1.0, Ares, ldres, X, ldx, 1.0, w.R, n, false));
+        }
         hipLaunchKernelGGL(zero_d_kernel, dim3(1), dim3(256), 0, s, nrm, 3 * nrhs);
         for (int c = 0; c < nrhs; ++c) {
             hipLaunchKernelGGL(vec_absmax_kernel, dim3(64), dim3(256), 0, s, n, w.R + (size_t)c * n, nrm + 3 * c);

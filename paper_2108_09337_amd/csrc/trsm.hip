@@ -116,9 +116,135 @@ hipError_t launch_right(hipStream_t s, int nb, int nrows, const double *T, int l
     return hipGetLastError();
 }
 
+// Few right-hand sides: one wave per column; lane i holds row i of the
+// 64-row diagonal block, the block of T sits in LDS; the solved value of row
+// j is broadcast with a shuffle.
+template <int KIND>
+__global__ __launch_bounds__(256) void trsv_diag_kernel(int kb, int nrhs, const double *__restrict__ T, int ldt,
+                                                        double *__restrict__ B, int ldb) {
+    __shared__ double Ts[64 * 65];
+    const int t = threadIdx.x, lane = t & 63, c = t >> 6;
+    for (int e = t; e < kb * kb; e += 256) {
+        const int i = e % kb, j = e / kb;
+        Ts[i + j * 65] = T[(size_t)i + (size_t)j * ldt];
+    }
+    __syncthreads();
+    if (c >= nrhs) return;
+    double x = lane < kb ? B[(size_t)lane + (size_t)c * ldb] : 0.0;
+    if (KIND == cdf::TRSM_LLNU || KIND == cdf::TRSM_LLNN) {
+        for (int j = 0; j < kb; ++j) {
+            if (KIND == cdf::TRSM_LLNN && lane == j) x = x / Ts[j + j * 65];
+            const double xj = __shfl(x, j);
+            if (lane > j && lane < kb) x = fma(-Ts[lane + j * 65], xj, x);
+        }
+    } else {
+        for (int j = kb - 1; j >= 0; --j) {
+            if (lane == j) x = x / Ts[j + j * 65];
+            const double xj = __shfl(x, j);
+            if (lane < j) x = fma(KIND == cdf::TRSM_LUNN ? -Ts[lane + j * 65] : -Ts[j + lane * 65], xj, x);
+        }
+    }
+    if (lane < kb) B[(size_t)lane + (size_t)c * ldb] = x;
+}
+
+// Y(rows x nrhs) -= T(rows x kb) X(kb x nrhs); one row per thread.
+__global__ __launch_bounds__(256) void gemv_n_kernel(int rows, int kb, int nrhs, const double *__restrict__ T, int ldt,
+                                                     const double *__restrict__ X, int ldx, double *__restrict__ Y,
+                                                     int ldy) {
+    __shared__ double xs[4][64];
+    const int t = threadIdx.x;
+    if (t < kb * nrhs) xs[t / kb][t % kb] = X[(size_t)(t % kb) + (size_t)(t / kb) * ldx];
+    __syncthreads();
+    const int r = blockIdx.x * 256 + t;
+    if (r >= rows) return;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < kb; ++j) {
+        const double tv = T[(size_t)r + (size_t)j * ldt];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < nrhs) acc[c] = fma(tv, xs[c][j], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        if (c < nrhs) Y[(size_t)r + (size_t)c * ldy] -= acc[c];
+}
+
+// Y(cols x nrhs) -= T(kb x cols)^T X(kb x nrhs); one output row (a column of T) per thread.
+__global__ __launch_bounds__(256) void gemv_t_kernel(int cols, int kb, int nrhs, const double *__restrict__ T, int ldt,
+                                                     const double *__restrict__ X, int ldx, double *__restrict__ Y,
+                                                     int ldy) {
+    __shared__ double xs[4][64];
+    const int t = threadIdx.x;
+    if (t < kb * nrhs) xs[t / kb][t % kb] = X[(size_t)(t % kb) + (size_t)(t / kb) * ldx];
+    __syncthreads();
+    const int r = blockIdx.x * 256 + t;
+    if (r >= cols) return;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double *col = T + (size_t)r * ldt;
+    for (int i = 0; i < kb; ++i) {
+        const double tv = col[i];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < nrhs) acc[c] = fma(tv, xs[c][i], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        if (c < nrhs) Y[(size_t)r + (size_t)c * ldy] -= acc[c];
+}
+
+template <int KIND>
+hipError_t launch_diag(hipStream_t s, int kb, int nrhs, const double *T, int ldt, double *B, int ldb) {
+    hipLaunchKernelGGL((trsv_diag_kernel<KIND>), dim3(1), dim3(256), 0, s, kb, nrhs, T, ldt, B, ldb);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 namespace cdf {
+
+hipError_t trsv_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const double *T, int ldt, double *B,
+                        int ldb) {
+    constexpr int BS = 64;
+    if (n <= 0 || ncols <= 0) return hipSuccess;
+    if (ncols > 4) return hipErrorInvalidValue;
+    auto diag = [&](int k, int kb) -> hipError_t {
+        const double *Tk = T + k + (size_t)k * ldt;
+        switch (kind) {
+            case TRSM_LLNU: return launch_diag<TRSM_LLNU>(s, kb, ncols, Tk, ldt, B + k, ldb);
+            case TRSM_LLNN: return launch_diag<TRSM_LLNN>(s, kb, ncols, Tk, ldt, B + k, ldb);
+            case TRSM_LUNN: return launch_diag<TRSM_LUNN>(s, kb, ncols, Tk, ldt, B + k, ldb);
+            case TRSM_LLTN: return launch_diag<TRSM_LLTN>(s, kb, ncols, Tk, ldt, B + k, ldb);
+            default: return hipErrorInvalidValue;
+        }
+    };
+    if (kind == TRSM_LLNU || kind == TRSM_LLNN) {
+        for (int k = 0; k < n; k += BS) {
+            const int kb = min(BS, n - k), rest = n - k - kb;
+            CDF_HIP_RET(diag(k, kb));
+            if (rest > 0) {
+                hipLaunchKernelGGL(gemv_n_kernel, dim3((rest + 255) / 256), dim3(256), 0, s, rest, kb, ncols,
+                                   T + (k + kb) + (size_t)k * ldt, ldt, B + k, ldb, B + k + kb, ldb);
+                CDF_HIP_RET(hipGetLastError());
+            }
+        }
+        return hipSuccess;
+    }
+    const int last = ((n - 1) / BS) * BS;
+    for (int k = last; k >= 0; k -= BS) {
+        const int kb = min(BS, n - k);
+        CDF_HIP_RET(diag(k, kb));
+        if (k > 0) {
+            if (kind == TRSM_LUNN)
+                hipLaunchKernelGGL(gemv_n_kernel, dim3((k + 255) / 256), dim3(256), 0, s, k, kb, ncols,
+                                   T + (size_t)k * ldt, ldt, B + k, ldb, B, ldb);
+            else
+                hipLaunchKernelGGL(gemv_t_kernel, dim3((k + 255) / 256), dim3(256), 0, s, k, kb, ncols, T + k, ldt,
+                                   B + k, ldb, B, ldb);
+            CDF_HIP_RET(hipGetLastError());
+        }
+    }
+    return hipSuccess;
+}
 
 template <typename TB>
 hipError_t trsm_small_impl(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt, TB *B,
@@ -148,8 +274,8 @@ hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const dou
 // Blocked solve with an n x n triangle: 128-wide diagonal solves, the rest
 // of the right-hand block updated with the FP64 GEMM.
 hipError_t trsm_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const double *T, int ldt,
-                        double *B, int ldb) {
-    constexpr int BS = 128;
+                        double *B, int ldb, int BS) {
+    if (BS <= 0 || BS > MAXNB) return hipErrorInvalidValue;
     if (n <= 0 || ncols <= 0) return hipSuccess;
     if (kind == TRSM_LLNU || kind == TRSM_LLNN) {
         for (int k = 0; k < n; k += BS) {
