@@ -30,8 +30,7 @@ inline int chol_nb(cdf_handle_t h) {
 }
 
 // Slots for the LU leaf's grid exchange: 2 parities x (G x 34) + 2 x 32 doubles.
-constexpr size_t kLeafSlotBytes = (2 * 256 * 34 + 64) * sizeof(double) * 4;
-constexpr size_t kLuWsBytes = kLeafSlotBytes + 256 * sizeof(int) + (1 + 2 * 512) * sizeof(int) + 4096;
+constexpr size_t kLuWsBytes = cdf::kLeafWsBytes + 256 * sizeof(int) + (1 + 2 * 512) * sizeof(int) + 4096;
 
 }  // namespace
 
@@ -122,7 +121,7 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
     CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
     const int nb = lu_nb(h);
     LuWs ws;
-    char *base = static_cast<char *>(h->ws) + kLeafSlotBytes;
+    char *base = static_cast<char *>(h->ws) + cdf::kLeafWsBytes;
     ws.ipt = reinterpret_cast<int *>(base);
     ws.pairs = reinterpret_cast<int *>(base + 256 * sizeof(int));
     const int kb0 = nb < n ? nb : n;
@@ -245,6 +244,7 @@ cdf_status_t ws_reserve(cdf_handle_t h, size_t bytes) {
     }
     h->ws = p;
     h->ws_bytes = want;
+    h->leaf_epoch = 0;  // fresh memory: the leaf re-zeroes its tag area before use
     return CDF_OK;
 }
 
@@ -261,16 +261,6 @@ cdf_status_t cdf_create(cdf_handle_t *h) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
         p->num_cus = cus;
-    if (hipMalloc(reinterpret_cast<void **>(&p->sync), cdf::kSyncInts * sizeof(int)) != hipSuccess) {
-        delete p;
-        return CDF_ERR_ALLOC;
-    }
-    if (hipMemset(p->sync, 0, cdf::kSyncInts * sizeof(int)) != hipSuccess ||
-        hipDeviceSynchronize() != hipSuccess) {
-        (void)hipFree(p->sync);
-        delete p;
-        return CDF_ERR_HIP;
-    }
     *h = p;
     return CDF_OK;
 }
@@ -279,7 +269,6 @@ cdf_status_t cdf_destroy(cdf_handle_t h) {
     if (!h) return CDF_ERR_INVALID_ARG;
     (void)hipStreamSynchronize(h->stream);
     if (h->ws) (void)hipFree(h->ws);
-    if (h->sync) (void)hipFree(h->sync);
     if (h->aux) { (void)hipStreamSynchronize(h->aux); (void)hipStreamDestroy(h->aux); }
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);

@@ -14,7 +14,7 @@ struct cdf_handle_s {
     void *ws = nullptr;          // lazily grown workspace
     size_t ws_bytes = 0;
     size_t ws_limit = 0;         // 0 = no cap
-    int *sync = nullptr;         // zeroed counters for grid-wide barriers
+    unsigned leaf_epoch = 0;     // next epoch of the panel leaf's exchange tags
     int bad_arg = 0;
     hipStream_t aux = nullptr;   // second stream for look-ahead (default priority)
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -23,7 +23,8 @@ struct cdf_handle_s {
 
 namespace cdf {
 
-constexpr int kSyncInts = 64;    // ints in handle->sync
+// Bytes at the head of the workspace reserved for the panel leaf's exchange.
+constexpr size_t kLeafWsBytes = 256 * 1024;
 
 // Grows the handle's workspace to at least `bytes` (synchronizing the stream
 // before a reallocation).  Returns CDF_ERR_ALLOC on failure or above the cap.

@@ -3,18 +3,25 @@
 // and row interchanges.
 //
 // Leaf kernel: factors an m x n (n <= 32) column block.  The rows are spread
-// over G workgroups (one per CU), each workgroup keeping its 256*R rows of
-// the block in LDS (column-major, so a column scan is contiguous).  Every
-// column costs one grid-wide exchange:
+// over G workgroups (at most one per CU), each keeping its 256*R rows of the
+// block in LDS (column-major, so a column scan is contiguous).  Every column
+// costs one grid-wide exchange, done without atomics or cache-wide fences:
 //   1. each workgroup finds its best candidate (largest |a|, lowest row on
-//      ties) with wave shuffles and LDS, and publishes it with the
-//      candidate's whole row (and, if it owns it, the current row j);
-//   2. grid barrier;
-//   3. every workgroup reduces the G candidates identically, swaps rows j and
-//      p locally, scales column j by the pivot (division) and applies the
-//      rank-1 update to the remaining columns of the block.
-// Published slots are double-buffered by column parity, so one barrier per
-// column suffices.  With G = 1 the exchange stays in LDS.
+//      ties) with wave shuffles and LDS, writes the candidate's whole row
+//      (and, if it owns it, the current row j) to its slot, waits for those
+//      stores to complete and then writes three tag words: the candidate's
+//      |a| split in two 32-bit halves and its row index, each paired with a
+//      32-bit epoch unique to this launch and column;
+//   2. every workgroup polls the G tag triples with device-coherent loads
+//      until all carry the current epoch (each 64-bit word is written
+//      whole, so a word with the current epoch holds the current half), and
+//      reduces them identically;
+//   3. it reads the winning row, then each thread swaps, scales (division)
+//      and rank-1 updates its own rows.
+// Slots are double-buffered by column parity: a workgroup can only overwrite
+// the slots of column j once every workgroup has published column j + 1,
+// which each does after it finished reading column j.  With G = 1 the
+// exchange stays in LDS.
 #include "internal.h"
 
 #include <climits>
@@ -23,53 +30,66 @@ namespace {
 
 constexpr int LW = 32;   // leaf width (columns)
 constexpr int LT = 256;  // threads per workgroup
-constexpr int SL = LW + 2;  // slot stride in doubles: |a|, row index, row[LW]
+constexpr int GMAX = 256;
+typedef unsigned long long u64;
+
+// Workspace layout of the exchange (at the head of the handle's workspace).
+constexpr size_t kTagWords = 4;  // per slot: |a| high half, |a| low half, row index, padding
+constexpr size_t kTagBytes = 2 * GMAX * kTagWords * sizeof(u64);
+constexpr size_t kRowBytes = 2 * GMAX * LW * sizeof(double);
+static_assert(kTagBytes + kRowBytes + 2 * LW * sizeof(double) <= cdf::kLeafWsBytes, "leaf workspace");
 
 __device__ inline void better(double &bv, int &bi, double ov, int oi) {
     if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
 }
 
-__device__ inline void grid_barrier(int *count, int target) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        atomicAdd(count, 1);
-        while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
-            __builtin_amdgcn_s_sleep(1);
-        __threadfence();
-    }
-    __syncthreads();
+__device__ inline void put_dev(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double get_dev(const double *p) {
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void put_tag(u64 *p, u64 v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline u64 get_tag(const u64 *p) {
+    return __hip_atomic_load(const_cast<u64 *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int R>
 __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__restrict__ A, int lda,
                                                      int *__restrict__ ipiv, int row0,
                                                      int *__restrict__ info, int info_base,
-                                                     double *__restrict__ slots, int *__restrict__ sync) {
+                                                     u64 *__restrict__ tags, double *__restrict__ rows,
+                                                     unsigned epoch0) {
     constexpr int RT = LT * R;  // rows per workgroup
     extern __shared__ double X[];  // X[c * RT + local row]
     __shared__ double prow[LW];
     __shared__ double oldj[LW];
-    __shared__ double wv[LT / 64];
-    __shared__ int wi[LT / 64];
-    __shared__ int ww[LT / 64];
-    __shared__ int s_p;
-    __shared__ int s_w;
+    __shared__ double wv[LT / 64], xv[LT / 64];
+    __shared__ int wi[LT / 64], xi[LT / 64], xw[LT / 64];
 
     const int G = gridDim.x;
     const int g = blockIdx.x;
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int rbase = g * RT;
+    double *rowj = rows + (size_t)2 * GMAX * LW;
 
-    if (t < LW) { prow[t] = 0.0; oldj[t] = 0.0; }
-    for (int c = 0; c < n; ++c)
+    // load the block: 8 columns in flight per thread at a time
+    for (int c0 = 0; c0 < n; c0 += 8) {
+        double tmp[8][R];
 #pragma unroll
-        for (int s = 0; s < R; ++s) {
-            const int r = rbase + s * LT + t;
-            X[c * RT + s * LT + t] = r < m ? A[(size_t)r + (size_t)c * lda] : 0.0;
-        }
-    double *rowj = slots + (size_t)2 * G * SL;
+        for (int cc = 0; cc < 8; ++cc)
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+                const int r = rbase + s * LT + t, c = c0 + cc;
+                tmp[cc][s] = (r < m && c < n) ? A[(size_t)r + (size_t)c * lda] : 0.0;
+            }
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc)
+#pragma unroll
+            for (int s = 0; s < R; ++s)
+                if (c0 + cc < n) X[(c0 + cc) * RT + s * LT + t] = tmp[cc][s];
+    }
     __syncthreads();
 
     for (int j = 0; j < n; ++j) {
@@ -90,84 +110,92 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
         }
         if (lane == 0) { wv[wave] = bv; wi[wave] = bi; }
         __syncthreads();
-        if (t == 0) {
-            double v = wv[0];
-            int i = wi[0];
+        double v = wv[0];
+        int p = wi[0];
 #pragma unroll
-            for (int w = 1; w < LT / 64; ++w) better(v, i, wv[w], wi[w]);
-            s_p = i;
-            wv[0] = v;
-        }
-        __syncthreads();
-        int p;
-        if (G == 1) {
-            p = s_p == INT_MAX ? j : s_p;  // no ordered candidate (NaN column): no interchange
-            if (t < n) {
-                prow[t] = X[t * RT + p];
-                oldj[t] = X[t * RT + j];
+        for (int w = 1; w < LT / 64; ++w) better(v, p, wv[w], wi[w]);
+        int win = 0;
+        if (G > 1) {
+            const u64 e = (u64)(epoch0 + (unsigned)j) << 32;
+            if (wave == 0) {
+                // publish: rows first, then (after they completed) the tags
+                if (p != INT_MAX && t < n) put_dev(rows + ((size_t)par * GMAX + g) * LW + t, X[t * RT + (p - rbase)]);
+                if (j >= rbase && j < rbase + RT && t < n) put_dev(rowj + (size_t)par * LW + t, X[t * RT + (j - rbase)]);
+                __builtin_amdgcn_s_waitcnt(0);
+                if (t < 3) {
+                    const u64 bits = (u64)__double_as_longlong(v);
+                    const u64 half = t == 0 ? bits >> 32 : (t == 1 ? bits & 0xffffffffull : (u64)(unsigned)p);
+                    put_tag(tags + ((size_t)par * GMAX + g) * kTagWords + t, e | half);
+                }
             }
-            __syncthreads();
-        } else {
-            const int lp = s_p;
-            double *slot = slots + ((size_t)par * G + g) * SL;
-            if (t == 0) { slot[0] = wv[0]; slot[1] = (double)lp; }
-            if (lp != INT_MAX && t < n) slot[2 + t] = X[t * RT + (lp - rbase)];
-            if (j >= rbase && j < rbase + RT && t < n) rowj[(size_t)par * LW + t] = X[t * RT + (j - rbase)];
-            grid_barrier(sync, (j + 1) * G);
-            // 3. reduce the G candidates (identically in every workgroup)
-            double v = -1.0;
-            int i = INT_MAX, w = 0;
-            if (t < G) {
-                const double *o = slots + ((size_t)par * G + t) * SL;
-                v = o[0];
-                i = (int)o[1];
-                w = t;
+            // 2. poll every workgroup's tags (one slot per lane)
+            const int q = wave * 64 + lane;
+            const bool act = q < G;
+            const u64 *tq = tags + ((size_t)par * GMAX + (act ? q : 0)) * kTagWords;
+            u64 w0 = 0, w1 = 0, w2 = 0;
+            bool ok;
+            do {
+                if (act) { w0 = get_tag(tq); w1 = get_tag(tq + 1); w2 = get_tag(tq + 2); }
+                ok = !act || ((w0 & ~0xffffffffull) == e && (w1 & ~0xffffffffull) == e && (w2 & ~0xffffffffull) == e);
+            } while (!__all(ok));
+            double cv = -1.0;
+            int ci = INT_MAX, cw = 0;
+            if (act) {
+                cv = __longlong_as_double((long long)((w0 << 32) | (w1 & 0xffffffffull)));
+                ci = (int)(unsigned)(w2 & 0xffffffffull);
+                cw = q;
             }
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
-                const double ov = __shfl_xor(v, off);
-                const int oi = __shfl_xor(i, off);
-                const int ow = __shfl_xor(w, off);
-                if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; w = ow; }
+                const double ov = __shfl_xor(cv, off);
+                const int oi = __shfl_xor(ci, off);
+                const int ow = __shfl_xor(cw, off);
+                if (ov > cv || (ov == cv && oi < ci)) { cv = ov; ci = oi; cw = ow; }
             }
-            if (lane == 0) { wv[wave] = v; wi[wave] = i; ww[wave] = w; }
+            if (lane == 0) { xv[wave] = cv; xi[wave] = ci; xw[wave] = cw; }
             __syncthreads();
-            if (t == 0) {
-                double bv2 = wv[0];
-                int bi2 = wi[0], bw2 = ww[0];
-                for (int q = 1; q < LT / 64; ++q)
-                    if (wv[q] > bv2 || (wv[q] == bv2 && wi[q] < bi2)) { bv2 = wv[q]; bi2 = wi[q]; bw2 = ww[q]; }
-                s_p = bi2;
-                s_w = bw2;
-            }
-            __syncthreads();
-            p = s_p == INT_MAX ? j : s_p;
+            v = xv[0];
+            p = xi[0];
+            win = xw[0];
+#pragma unroll
+            for (int w = 1; w < LT / 64; ++w)
+                if (xv[w] > v || (xv[w] == v && xi[w] < p)) { v = xv[w]; p = xi[w]; win = xw[w]; }
+            // 3. winning row and current row j
             if (t < n) {
-                oldj[t] = rowj[(size_t)par * LW + t];
-                prow[t] = s_p == INT_MAX ? oldj[t] : slots[((size_t)par * G + s_w) * SL + 2 + t];
+                const double oj = get_dev(rowj + (size_t)par * LW + t);
+                const double pw = get_dev(rows + ((size_t)par * GMAX + win) * LW + t);
+                oldj[t] = oj;
+                prow[t] = p == INT_MAX ? oj : pw;
             }
-            __syncthreads();
+        } else if (t < n) {
+            oldj[t] = X[t * RT + j];
+            prow[t] = p == INT_MAX ? X[t * RT + j] : X[t * RT + p];
         }
-        // swap rows j and p (local copies of both rows are in prow / oldj)
-        if (t < n) {
-            if (p != j && p >= rbase && p < rbase + RT) X[t * RT + (p - rbase)] = oldj[t];
-            if (j >= rbase && j < rbase + RT) X[t * RT + (j - rbase)] = prow[t];
-        }
+        if (p == INT_MAX) p = j;  // no ordered candidate (NaN column): no interchange
+        __syncthreads();
         const double piv = prow[j];
         if (g == 0 && t == 0) {
             ipiv[j] = row0 + p + 1;
             if (piv == 0.0 && *info == 0) *info = info_base + j + 1;
         }
-        __syncthreads();
-        if (piv != 0.0) {
+        // swap rows j and p, scale and update; every thread owns its rows
 #pragma unroll
-            for (int s = 0; s < R; ++s) {
-                const int r = rbase + s * LT + t;
-                if (r < m && r > j) {
-                    const int rl = s * LT + t;
-                    const double l = X[j * RT + rl] / piv;
+        for (int s = 0; s < R; ++s) {
+            const int r = rbase + s * LT + t;
+            const int rl = s * LT + t;
+            if (r == j) {
+                for (int c = 0; c < n; ++c) X[c * RT + rl] = prow[c];
+            } else if (r > j && r < m) {
+                const bool moved = (r == p);
+                if (moved)
+                    for (int c = 0; c < j; ++c) X[c * RT + rl] = oldj[c];
+                const double aj = moved ? oldj[j] : X[j * RT + rl];
+                if (piv != 0.0) {
+                    const double l = aj / piv;
                     X[j * RT + rl] = l;
-                    for (int c = j + 1; c < n; ++c) X[c * RT + rl] = fma(-l, prow[c], X[c * RT + rl]);
+                    for (int c = j + 1; c < n; ++c) X[c * RT + rl] = fma(-l, prow[c], moved ? oldj[c] : X[c * RT + rl]);
+                } else if (moved) {
+                    for (int c = j; c < n; ++c) X[c * RT + rl] = oldj[c];
                 }
             }
         }
@@ -180,17 +208,6 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
             const int r = rbase + s * LT + t;
             if (r < m) A[(size_t)r + (size_t)c * lda] = X[c * RT + s * LT + t];
         }
-
-    if (G > 1) {
-        __syncthreads();
-        if (t == 0) {
-            const int old = atomicAdd(sync + 1, 1);
-            if (old == G - 1) {
-                atomicExch(sync, 0);
-                atomicExch(sync + 1, 0);
-            }
-        }
-    }
 }
 
 // ---------------------------------------------------------------- interchanges
@@ -403,16 +420,25 @@ hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, 
     if (R != 1 && R != 2) R = (m + LT - 1) / LT > h->num_cus / 2 ? 2 : 1;
     int G = (m + LT * R - 1) / (LT * R);
     if (G > h->num_cus && R == 1) { R = 2; G = (m + LT * R - 1) / (LT * R); }
-    if (G > h->num_cus) return hipErrorInvalidValue;
-    double *slots = static_cast<double *>(h->ws);  // caller reserved (2*G*SL + 2*LW) doubles
-    int *sync = h->sync;
-    void *args[] = {&m, &n, &A, &lda, &ipiv, &row0, &info, &info_base, &slots, &sync};
+    if (G > h->num_cus || G > GMAX) return hipErrorInvalidValue;
+    // Epochs are unique per launch and column; the tag area starts zeroed
+    // (ws_reserve) and epochs below 64 are never issued, so no stale word
+    // can carry a current epoch.
+    if (h->leaf_epoch < 64u || h->leaf_epoch > 0xffffff00u) {
+        CDF_HIP_RET(fill_int(stream, static_cast<int *>(h->ws), (int)(kTagBytes / sizeof(int)), 0));
+        h->leaf_epoch = 64u;
+    }
+    unsigned e0 = h->leaf_epoch;
+    h->leaf_epoch += 64u;
+    u64 *tags = static_cast<u64 *>(h->ws);
+    double *rows = reinterpret_cast<double *>(static_cast<char *>(h->ws) + kTagBytes);
+    void *args[] = {&m, &n, &A, &lda, &ipiv, &row0, &info, &info_base, &tags, &rows, &e0};
     const void *fn = R == 1 ? reinterpret_cast<const void *>(&lu_leaf_kernel<1>)
                             : reinterpret_cast<const void *>(&lu_leaf_kernel<2>);
     const size_t lds = (size_t)LW * LT * R * sizeof(double);
     // A plain launch: G <= number of CUs and each CU fits a leaf workgroup, so
     // all G become resident at the latest when the (finite) kernels that may
-    // run beside it on other streams have drained; the grid barrier then
+    // run beside it on other streams have drained; the exchange then
     // completes.  (A cooperative launch would forbid that overlap.)
     return hipLaunchKernel(fn, dim3(G), dim3(LT), args, lds, stream);
 }

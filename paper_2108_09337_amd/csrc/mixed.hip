@@ -469,11 +469,10 @@ struct MixedWs {
     double *R = nullptr, *red = nullptr;
 };
 
-constexpr size_t kSlotBytes = (2 * 256 * 34 + 64) * sizeof(double) * 4;  // LU leaf exchange (workspace head)
 
 cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool chol, MixedWs &w,
                           bool factor_only = false) {
-    size_t off = kSlotBytes;
+    size_t off = cdf::kLeafWsBytes;  // LU leaf exchange at the workspace head
     auto take = [&](size_t bytes) {
         const size_t o = off;
         off = cdf::align_up(off + bytes, 256);
