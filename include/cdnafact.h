@@ -202,13 +202,14 @@ CDF_API cdf_status_t cdf_quantize(cdf_handle_t h, cdf_update_prec_t p, int m, in
 /*
  * Low-precision Schur-complement update C <- C - dq(A) dq(B) with binary32
  * accumulation (Sec. 7, routine A11, in the update precision), where dq
- * multiplies each code's value by 2^-e of its tile.  Operands are given
- * K-contiguous, as cdf_quantize writes them with tm = k and tn = T
- * (T = cdf_update_tile(p)):
- *   QA    codes of A^T (k x m, leading dimension lda); ea[i] is the exponent
- *         of rows [T*i, T*i+T) of A
- *   QB    codes of B (k x n, leading dimension ldb); eb[j] is the exponent of
- *         columns [T*j, T*j+T) of B
+ * multiplies each code's value by 2^-e of its tile.  For each T x T tile the
+ * product of the codes is accumulated in binary32 from zero, then
+ * C - 2^-(ea+eb) * sum is rounded once.  Operands are given K-contiguous,
+ * as cdf_quantize writes them with tm = k and tn = T (T = cdf_update_tile(p)):
+ *   QA    codes of A^T (k x m, leading dimension lda), 16-byte aligned;
+ *         ea[i] is the exponent of rows [T*i, T*i+T) of A
+ *   QB    codes of B (k x n, leading dimension ldb), 16-byte aligned; eb[j]
+ *         is the exponent of columns [T*j, T*j+T) of B
  *   lda, ldb multiples of 32 and >= 32*ceil(k/32); codes of rows [k, lda) are zero
  *   C     device float m x n (ldc >= m)
  */

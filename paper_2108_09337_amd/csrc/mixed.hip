@@ -20,6 +20,7 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
 enum { FMT_BF16 = 1, FMT_FP16 = 2, FMT_E4M3 = 3 };
 constexpr int QT = 128;    // quantization tile = update tile
@@ -150,28 +151,22 @@ struct Frag;
 template <>
 struct Frag<FMT_BF16> {
     typedef v8bf T;
-    __device__ static T load(const void *p, size_t off) {
-        return *reinterpret_cast<const T *>(static_cast<const unsigned short *>(p) + off);
-    }
-    __device__ static T zero() { return T{}; }
+    static constexpr int ES = 2;
+    __device__ static T lds(const unsigned char *p) { return *reinterpret_cast<const T *>(p); }
     __device__ static v4f mma(T a, T b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };
 template <>
 struct Frag<FMT_FP16> {
     typedef v8h T;
-    __device__ static T load(const void *p, size_t off) {
-        return *reinterpret_cast<const T *>(static_cast<const unsigned short *>(p) + off);
-    }
-    __device__ static T zero() { return T{}; }
+    static constexpr int ES = 2;
+    __device__ static T lds(const unsigned char *p) { return *reinterpret_cast<const T *>(p); }
     __device__ static v4f mma(T a, T b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
 };
 template <>
 struct Frag<FMT_E4M3> {
     typedef long T;
-    __device__ static T load(const void *p, size_t off) {
-        return *reinterpret_cast<const long *>(static_cast<const unsigned char *>(p) + off);
-    }
-    __device__ static T zero() { return 0; }
+    static constexpr int ES = 1;
+    __device__ static T lds(const unsigned char *p) { return *reinterpret_cast<const long *>(p); }
     __device__ static v4f mma(T a, T b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0); }
 };
 
@@ -181,16 +176,27 @@ __device__ inline int xcd_remap(int bid, int nwg) {
     return (bid & 7) * (full >> 3) + (bid >> 3);
 }
 
-// C (binary32) -= dq(QA) dq(QB): 128 x 128 tile per workgroup, 64 x 64 per
-// wave as 4 x 4 blocks of the 16x16x32 MFMA; operand fragments (8 K-adjacent
-// elements per lane) are loaded straight from L2 into registers.
+// C (binary32) -= dq(QA) dq(QB): a 128 x 128 tile per workgroup, 64 x 64 per
+// wave as 4 x 4 blocks of the 16x16x32 MFMA.  The update streams C once
+// (read + write, 8 bytes per element against 2k flops), so it is bound by
+// HBM: C is read with 16-byte loads at the start into registers of its own,
+// so that its latency overlaps the whole K loop, and written once at the
+// end as C - 2^-(ea+eb) * acc.  Operands go through LDS in chunks of 128
+// bytes of K per row (double-buffered, rows padded by 16 bytes so the
+// fragment reads of 16 consecutive rows hit distinct banks).
 template <int FMT, bool LOWER>
-__global__ __launch_bounds__(NT) void lowp_gemm_kernel(int m, int n, int kpad, const void *__restrict__ QA, int lda,
-                                                       const int *__restrict__ ea, const void *__restrict__ QB,
-                                                       int ldb, const int *__restrict__ eb, float *__restrict__ C,
-                                                       int ldc, int tiles_m, int tiles_n, const int *stop) {
+__global__ __launch_bounds__(NT, 2) void lowp_gemm_kernel(int m, int n, int kpad, const void *__restrict__ QA, int lda,
+                                                          const int *__restrict__ ea, const void *__restrict__ QB,
+                                                          int ldb, const int *__restrict__ eb, float *__restrict__ C,
+                                                          int ldc, int tiles_m, int tiles_n, const int *stop) {
     if (stop != nullptr && *stop != 0) return;
     using F = Frag<FMT>;
+    constexpr int ES = F::ES;    // bytes per code
+    constexpr int CB = 128;      // bytes of K per row and chunk
+    constexpr int KC = CB / ES;  // K per chunk
+    constexpr int RS = CB + 16;  // LDS row stride (bytes)
+    __shared__ __attribute__((aligned(16))) unsigned char As[2][QT * RS];
+    __shared__ __attribute__((aligned(16))) unsigned char Bs[2][QT * RS];
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     int tm, tn;
     if (LOWER) {
@@ -207,69 +213,96 @@ __global__ __launch_bounds__(NT) void lowp_gemm_kernel(int m, int n, int kpad, c
         tn = in / gm;
     }
     const int m0 = tm * QT, n0 = tn * QT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int lrow = lane & 15, lk = lane >> 4;
-    // C enters the accumulators scaled by 2^(ea+eb) and negated (exact power
-    // of two), so the K loop accumulates -C 2^s + sum(qa qb) and the epilogue
-    // only stores -acc 2^-s.
     const int sc = ea[tm] + eb[tn];
-    v4f acc[4][4];
+    const bool vec = ((reinterpret_cast<uintptr_t>(C) & 15) == 0) && (ldc & 3) == 0;
+
+    // 16x16 f32 output block: register v of a lane holds row 4*(lane/16)+v, column lane%16.
+    v4f acc[4][4], cr[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
+            acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
             const int col = n0 + wn * 64 + j * 16 + lrow;
+            const int row0 = m0 + wm * 64 + i * 16 + lk * 4;
+            if (vec && row0 + 3 < m && col < n && (!LOWER || row0 >= col)) {
+                cr[i][j] = *reinterpret_cast<const v4f *>(C + (size_t)row0 + (size_t)col * ldc);
+            } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm * 64 + i * 16 + lk * 4 + v;
-                acc[i][j][v] = (row < m && col < n && (!LOWER || row >= col))
-                                   ? -ldexpf(C[(size_t)row + (size_t)col * ldc], sc) : 0.f;
+                for (int v = 0; v < 4; ++v) {
+                    const int row = row0 + v;
+                    cr[i][j][v] = (row < m && col < n && (!LOWER || row >= col)) ? C[(size_t)row + (size_t)col * ldc] : 0.f;
+                }
             }
         }
-    size_t aoff[4], boff[4];
-    bool aok[4], bok[4];
+
+    // operand pieces of 16 bytes: piece e = t + NT q covers row e / 8, bytes (e % 8) * 16 of the chunk
+    const unsigned char *qa = static_cast<const unsigned char *>(QA);
+    const unsigned char *qb = static_cast<const unsigned char *>(QB);
+    v4u ra[4], rb[4];
+    auto gload = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = m0 + wm * 64 + i * 16 + lrow;
-        aok[i] = row < m;
-        aoff[i] = (size_t)(aok[i] ? row : 0) * lda + 8 * lk;
-        const int col = n0 + wn * 64 + i * 16 + lrow;
-        bok[i] = col < n;
-        boff[i] = (size_t)(bok[i] ? col : 0) * ldb + 8 * lk;
-    }
-    typename F::T a[4], b[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        a[i] = aok[i] ? F::load(QA, aoff[i]) : F::zero();
-        b[i] = bok[i] ? F::load(QB, boff[i]) : F::zero();
-    }
-    for (int k0 = 0; k0 < kpad; k0 += KSTEP) {
-        typename F::T an[4], bn[4];
-        const bool more = k0 + KSTEP < kpad;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            an[i] = (more && aok[i]) ? F::load(QA, aoff[i] + k0 + KSTEP) : F::zero();
-            bn[i] = (more && bok[i]) ? F::load(QB, boff[i] + k0 + KSTEP) : F::zero();
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + NT * q, r = e >> 3, off = (e & 7) * 16;
+            const int kk = k0 + off / ES;
+            const v4u z = v4u{0u, 0u, 0u, 0u};
+            ra[q] = (m0 + r < m && kk < kpad) ? *reinterpret_cast<const v4u *>(qa + ((size_t)(m0 + r) * lda + kk) * ES) : z;
+            rb[q] = (n0 + r < n && kk < kpad) ? *reinterpret_cast<const v4u *>(qb + ((size_t)(n0 + r) * ldb + kk) * ES) : z;
         }
+    };
+    auto sstore = [&](int b) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + NT * q, r = e >> 3, off = (e & 7) * 16;
+            *reinterpret_cast<v4u *>(&As[b][r * RS + off]) = ra[q];
+            *reinterpret_cast<v4u *>(&Bs[b][r * RS + off]) = rb[q];
+        }
+    };
+    const int nc = (kpad + KC - 1) / KC;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int c = 0; c < nc; ++c) {
+        const int b = c & 1;
+        if (c + 1 < nc) gload((c + 1) * KC);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = F::mma(a[i], b[j], acc[i][j]);
+        for (int ks = 0; ks < KC / KSTEP; ++ks) {
+            if (c * KC + ks * KSTEP >= kpad) break;
+            typename F::T af[4], bf[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) { a[i] = an[i]; b[i] = bn[i]; }
+            for (int i = 0; i < 4; ++i) {
+                af[i] = F::lds(&As[b][(wm * 64 + i * 16 + lrow) * RS + (ks * KSTEP + lk * 8) * ES]);
+                bf[i] = F::lds(&Bs[b][(wn * 64 + i * 16 + lrow) * RS + (ks * KSTEP + lk * 8) * ES]);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = F::mma(af[i], bf[j], acc[i][j]);
+        }
+        if (c + 1 < nc) sstore(b ^ 1);
+        __syncthreads();
     }
-    // 16x16 f32 output block: register v of a lane holds row 4*(lane/16)+v, column lane%16.
+
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int col = n0 + wn * 64 + j * 16 + lrow;
+            const int row0 = m0 + wm * 64 + i * 16 + lk * 4;
+            v4f out;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm * 64 + i * 16 + lk * 4 + v;
-                if (row < m && col < n && (!LOWER || row >= col))
-                    C[(size_t)row + (size_t)col * ldc] = -ldexpf(acc[i][j][v], -sc);
+            for (int v = 0; v < 4; ++v) out[v] = cr[i][j][v] - ldexpf(acc[i][j][v], -sc);
+            if (vec && row0 + 3 < m && col < n && (!LOWER || row0 >= col)) {
+                *reinterpret_cast<v4f *>(C + (size_t)row0 + (size_t)col * ldc) = out;
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = row0 + v;
+                    if (row < m && col < n && (!LOWER || row >= col)) C[(size_t)row + (size_t)col * ldc] = out[v];
+                }
             }
         }
 }
@@ -826,9 +859,9 @@ cdf_status_t cdf_lowp_update(cdf_handle_t h, cdf_update_prec_t p, int m, int n, 
     if (ldb < kpad_of(k) || ldb % KSTEP) return bad(10);
     if (ldc < (m > 1 ? m : 1)) return bad(13);
     if (m == 0 || n == 0 || k == 0) return CDF_OK;
-    if (!QA) return bad(6);
+    if (!QA || (reinterpret_cast<uintptr_t>(QA) & 15)) return bad(6);
     if (!ea) return bad(8);
-    if (!QB) return bad(9);
+    if (!QB || (reinterpret_cast<uintptr_t>(QB) & 15)) return bad(9);
     if (!eb) return bad(11);
     if (!C) return bad(12);
     CDF_HIP_TRY(cdf::lowp_update(h->stream, (int)p, m, n, k, QA, lda, ea, QB, ldb, eb, C, ldc, false, nullptr));

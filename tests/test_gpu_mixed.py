@@ -105,7 +105,7 @@ def _lowp_gpu(fmt, a, b, c, h=None):
 
 
 @pytest.mark.parametrize("fmt", FMTS)
-@pytest.mark.parametrize("m,n,k", [(128, 128, 32), (300, 257, 100), (64, 600, 256)])
+@pytest.mark.parametrize("m,n,k", [(128, 128, 32), (300, 257, 100), (64, 600, 256), (522, 384, 1000)])
 def test_lowp_update_exact_on_representable(fmt, m, n, k):
     rng = np.random.default_rng(m + n + k)
     a = rng.integers(-8, 9, (m, k)).astype(np.float32)
