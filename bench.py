@@ -50,6 +50,8 @@ def parse():
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--no-tune-cache", action="store_true", help="ignore the autotuner cache")
+    p.add_argument("--calibrate-bytes", type=int, default=0,
+                   help="first run a plain elementwise kernel reading and writing this many bytes (PMC scale)")
     return p.parse_args()
 
 
@@ -70,6 +72,50 @@ def spd_on_device(n, torch, cdf, workloads):
     del s
     torch.cuda.empty_cache()
     return out
+
+
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "dgemm_nn_lu_fp64_hbm_traffic.md")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2108_09337_amd", "csrc", "gemm_f64.hip")
+
+
+def gemm_source_sha():
+    import hashlib
+    with open(GEMM_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_per_launch(n, lu_nb):
+    """Calibrated HBM bytes per launch of the update GEMM, from the committed
+    rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE runs of this benchmark),
+    or None when there is none for this N / block size or the kernel source
+    has changed since the counters were taken."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].strip().split(": ", 1)
+                vals[k.strip("` ")] = v.strip("` ")
+    try:
+        if int(vals["n"]) != n or int(vals["lu_nb"]) != lu_nb or vals["gemm_source_sha256"] != gemm_source_sha():
+            return None
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy(torch, nbytes):
+    """A plain elementwise kernel of known traffic (reads and writes nbytes
+    each), so that PMC runs of this command carry their own scale for
+    FETCH_SIZE / WRITE_SIZE."""
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+    torch.cuda.empty_cache()
 
 
 def events(torch, k):
@@ -112,11 +158,14 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
     evs = [events(torch, 3) for _ in range(K)]
     log(f"timing {K} steps")
     torch.cuda.synchronize()
+    cdf.profile_begin(h)  # HIP events around every update-GEMM launch, on the stream it runs on
     t0 = time.perf_counter()
     for i in range(K):
         step(W + i, evs[i])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    prof_nn = cdf.profile_end("nn", h)
+    prof_syrk = cdf.profile_end("syrk", h)
     assert int(info_lu.item()) == 0 and (not chol_copies or int(info_ch.item()) == 0)
     ms = (t1 - t0) * 1e3 / K
     t_lu = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e-3
@@ -126,33 +175,25 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
     value = (flops_lu + flops_ch) / (ms * 1e-3) / 1e12
     log(f"ms/step {ms:.1f}  LU {flops_lu / t_lu / 1e12:.2f} TF  Chol {flops_ch / max(t_ch, 1e-12) / 1e12:.2f} TF")
 
-    # dominant kernel: the FP64 update GEMM with one LU's trailing-update shapes
+    # dominant kernel: the FP64 update GEMM, every launch of it inside the timed LU steps
     lu_nb = h.get_param("lu_nb") or 256
-    C = lu_copies[W]
-    shapes = [(k, min(lu_nb, n - k), n - k - min(lu_nb, n - k)) for k in range(0, n, lu_nb)]
-    shapes = [s for s in shapes if s[2] > 0]
-    e0, e1 = events(torch, 2)
-    torch.cuda.synchronize()
-    e0.record()
-    for k, kb, rest in shapes:
-        cdf.dgemm_update(C[k + kb:, k:k + kb], C[k:k + kb, k + kb:], C[k + kb:, k + kb:])
-    e1.record()
-    torch.cuda.synchronize()
-    gemm_s = e0.elapsed_time(e1) * 1e-3
-    gemm_flops = sum(2.0 * rest * rest * kb for _, kb, rest in shapes)
-    avg = gemm_s / len(shapes)
-    achieved = gemm_flops / len(shapes) / avg / 1e12
+    launches = max(prof_nn["launches"], 1)
+    avg = prof_nn["total_ms"] * 1e-3 / launches
+    fpl = prof_nn["flops"] / launches
+    achieved = fpl / avg / 1e12 if avg > 0 else 0.0
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK, 4), "traffic": None,
-                "kernel": "dgemm_kernel<0,0,false> (FP64 Schur-complement update C -= A B)",
-                "launches": len(shapes), "avg_launch_us": round(avg * 1e6, 2),
-                "flops_per_launch": gemm_flops / len(shapes)}
+                "frac": round(achieved / FP64_PEAK, 4), "traffic": traffic_per_launch(n, lu_nb),
+                "kernel": "dgemm_kernel<0,0,false> (FP64 update C -= A B)",
+                "launches": prof_nn["launches"], "avg_launch_us": round(avg * 1e6, 2),
+                "flops_per_launch": round(fpl, 1),
+                "syrk": {"launches": prof_syrk["launches"],
+                         "tflops": round(prof_syrk["flops"] / max(prof_syrk["total_ms"], 1e-9) * 1e-9, 3)}}
     out = {"value": value, "ms": ms, "t_lu": t_lu, "t_ch": t_ch, "flops_lu": flops_lu, "flops_ch": flops_ch,
            "roofline": roofline, "lu_nb": lu_nb, "chol_nb": h.get_param("chol_nb") or 128,
            "params": {"getrf": lu_params, "potrf": ch_params}}
     for k in list(lu_params) + list(ch_params):
         h.set_param(k, 0)
-    del lu_copies, chol_copies, C
+    del lu_copies, chol_copies
     torch.cuda.empty_cache()
     return out, a_host, S0
 
@@ -244,6 +285,8 @@ def main():
     def tuned(hh, op, n, dtype="f64"):
         return tune.apply(hh, op, n, dtype, cache) if cache else {}
 
+    if args.calibrate_bytes:
+        calibrate_copy(torch, args.calibrate_bytes)
     fp, a_host, S0 = fp64_section(args, torch, cdf, workloads, h, tuned)
     detail = {"lu_tflops": round(fp["flops_lu"] / fp["t_lu"] / 1e12, 3),
               "chol_tflops": round(fp["flops_ch"] / fp["t_ch"] / 1e12, 3) if fp["flops_ch"] else None,

@@ -74,10 +74,11 @@ CDF_API const char *cdf_status_string(cdf_status_t s);
 
 /* Tunable parameters (block sizes chosen per call when left at 0 = auto). */
 typedef enum {
-    CDF_PARAM_LU_NB = 0,         /* LU outer panel width (multiple of 32) */
-    CDF_PARAM_CHOL_NB = 1,       /* Cholesky outer block width (multiple of 32) */
+    CDF_PARAM_LU_NB = 0,         /* LU outer panel width (multiple of 32, <= 512) */
+    CDF_PARAM_CHOL_NB = 1,       /* Cholesky outer block width (multiple of 32, <= 128) */
     CDF_PARAM_LU_LEAF_ROWS = 2,  /* rows per thread in the LU panel leaf (1 or 2) */
-    CDF_PARAM_MIXED_NB = 3,      /* block width of the mixed-precision factorizations (multiple of 32) */
+    CDF_PARAM_MIXED_NB = 3,      /* block width of the mixed-precision factorizations (multiple of 32,
+                                    <= 512; the Cholesky uses at most 256) */
     CDF_PARAM_VBATCH_NB = 4,     /* batched panel width: 0 = 32 where it fits in LDS, 16 = always 16 */
     CDF_PARAM_VBATCH_WG_PER_CU = 5, /* batched persistent workgroups per CU (1 or 2; 0 = 1) */
     CDF_PARAM_COUNT = 6
@@ -266,6 +267,27 @@ CDF_API cdf_status_t cdf_vbatch_plan_destroy(cdf_vbatch_plan_t plan);
  * Returns a negative value for an invalid kind or m_elems <= 0.  Host only.
  */
 CDF_API double cdf_io_lower_bound_elems(int kind, double n, double m_elems);
+
+/* ------------------------------------------------------- kernel timing */
+
+/*
+ * Kernel timing for roofline measurement (instrumentation, not part of the
+ * method).  Between cdf_profile_begin and cdf_profile_end, every launch of
+ * the FP64 update GEMM kernels (any handle, any stream, process-wide) is
+ * bracketed by two HIP events recorded on the stream it is launched on.
+ *   kernel   0: C -= A B (dgemm_kernel<0,0,false>, the LU trailing update)
+ *            1: A B^T, 2: A^T B, 3: A^T B^T, 4: lower-triangle A B^T (SYRK)
+ *   launches number of launches of that kernel (host)
+ *   total_ms sum of their event-measured durations in ms (host)
+ *   flops    sum of their algorithmic flops 2mnk (m(m+1)k for SYRK) (host)
+ * cdf_profile_end synchronizes the recorded events and stops recording;
+ * the records stay readable (one call per kernel kind) until the next
+ * cdf_profile_begin.  Without a cdf_profile_begin it returns zeros.  The
+ * handle argument is only checked for validity.
+ */
+CDF_API cdf_status_t cdf_profile_begin(cdf_handle_t h);
+CDF_API cdf_status_t cdf_profile_end(cdf_handle_t h, int kernel, long long *launches, double *total_ms,
+                                     double *flops);
 
 #ifdef __cplusplus
 }

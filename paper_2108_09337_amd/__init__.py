@@ -79,6 +79,8 @@ def lib() -> ctypes.CDLL:
         "cdf_vbatch_run": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "cdf_vbatch_plan_destroy": (_i, [_vp]),
         "cdf_io_lower_bound_elems": (ctypes.c_double, [_i, ctypes.c_double, ctypes.c_double]),
+        "cdf_profile_begin": (_i, [_vp]),
+        "cdf_profile_end": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_longlong), _c_double_p, _c_double_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -232,6 +234,26 @@ def dgemm_update(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, h: Handle | 
     n = _cols(C)
     _check("cdf_dgemm_update", lib().cdf_dgemm_update(h.bind_stream(), m, n, k, _p(A), _ld(A), _p(B), _ld(B),
                                                       _p(C), _ld(C)), h.ptr)
+
+
+GEMM_KERNELS = {"nn": 0, "nt": 1, "tn": 2, "tt": 3, "syrk": 4}
+
+
+def profile_begin(h: Handle | None = None) -> None:
+    """Start timing every FP64 update-GEMM launch (process-wide, HIP events on its stream)."""
+    h = h or handle()
+    _check("cdf_profile_begin", lib().cdf_profile_begin(h.ptr), h.ptr)
+
+
+def profile_end(kernel: str = "nn", h: Handle | None = None) -> dict:
+    """Stop timing; launches, summed event time (ms) and algorithmic flops of one GEMM kernel."""
+    h = h or handle()
+    n = ctypes.c_longlong(0)
+    ms = ctypes.c_double(0.0)
+    fl = ctypes.c_double(0.0)
+    _check("cdf_profile_end", lib().cdf_profile_end(h.ptr, GEMM_KERNELS[kernel], ctypes.byref(n), ctypes.byref(ms),
+                                                    ctypes.byref(fl)), h.ptr)
+    return {"launches": int(n.value), "total_ms": float(ms.value), "flops": float(fl.value)}
 
 
 # ---------------------------------------------------------------- mixed precision

@@ -29,8 +29,10 @@ inline int chol_nb(cdf_handle_t h) {
     return v > 0 ? v : 128;
 }
 
-// Slots for the LU leaf's grid exchange: 2 parities x (G x 34) + 2 x 32 doubles.
-constexpr size_t kLuWsBytes = cdf::kLeafWsBytes + 256 * sizeof(int) + (1 + 2 * 512) * sizeof(int) + 4096;
+// LU workspace: the leaf's exchange area, the current panel's pivots (<= 512)
+// and its interchange pairs.
+constexpr int kMaxLuNb = 512;
+constexpr size_t kLuWsBytes = cdf::kLeafWsBytes + kMaxLuNb * sizeof(int) + (1 + 4 * kMaxLuNb) * sizeof(int) + 4096;
 
 }  // namespace
 
@@ -123,7 +125,7 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
     LuWs ws;
     char *base = static_cast<char *>(h->ws) + cdf::kLeafWsBytes;
     ws.ipt = reinterpret_cast<int *>(base);
-    ws.pairs = reinterpret_cast<int *>(base + 256 * sizeof(int));
+    ws.pairs = reinterpret_cast<int *>(base + kMaxLuNb * sizeof(int));
     const int kb0 = nb < n ? nb : n;
     CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, 0, kb0, ws));
     CDF_HIP_RET(cdf::apply_pairs(s0, kb0, n, A, lda, ws.pairs));
@@ -276,6 +278,23 @@ cdf_status_t cdf_destroy(cdf_handle_t h) {
     return CDF_OK;
 }
 
+cdf_status_t cdf_profile_begin(cdf_handle_t h) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    cdf::prof_enable();
+    return CDF_OK;
+}
+
+cdf_status_t cdf_profile_end(cdf_handle_t h, int kernel, long long *launches, double *total_ms, double *flops) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    if (kernel < 0 || kernel > 4) { h->bad_arg = 2; return CDF_ERR_INVALID_ARG; }
+    if (!launches) { h->bad_arg = 3; return CDF_ERR_INVALID_ARG; }
+    if (!total_ms) { h->bad_arg = 4; return CDF_ERR_INVALID_ARG; }
+    if (!flops) { h->bad_arg = 5; return CDF_ERR_INVALID_ARG; }
+    CDF_HIP_TRY(cdf::prof_collect(kernel, launches, total_ms, flops));
+    return CDF_OK;
+}
+
 cdf_status_t cdf_set_stream(cdf_handle_t h, void *stream) {
     if (!h) return CDF_ERR_INVALID_ARG;
     h->stream = static_cast<hipStream_t>(stream);
@@ -309,11 +328,11 @@ cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value) {
     h->bad_arg = 0;
     if ((int)p < 0 || (int)p >= CDF_PARAM_COUNT) return bad(h, 2);
     if (value < 0) return bad(h, 3);
-    if ((p == CDF_PARAM_LU_NB || p == CDF_PARAM_CHOL_NB) && value != 0 && (value % 32 != 0 || value > 256))
+    if ((p == CDF_PARAM_LU_NB || p == CDF_PARAM_CHOL_NB || p == CDF_PARAM_MIXED_NB) && value != 0 &&
+        (value % 32 != 0 || value > kMaxLuNb))
         return bad(h, 3);
     if (p == CDF_PARAM_CHOL_NB && value > 128) return bad(h, 3);
     if (p == CDF_PARAM_LU_LEAF_ROWS && !(value == 0 || value == 1 || value == 2)) return bad(h, 3);
-    if (p == CDF_PARAM_MIXED_NB && value != 0 && (value % 32 != 0 || value > 256)) return bad(h, 3);
     if (p == CDF_PARAM_VBATCH_NB && !(value == 0 || value == 16)) return bad(h, 3);
     if (p == CDF_PARAM_VBATCH_WG_PER_CU && value > 2) return bad(h, 3);
     h->params[p] = value;

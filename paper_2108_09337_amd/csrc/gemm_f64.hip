@@ -15,6 +15,9 @@
 // 8 tile-rows so the A and B panels an XCD touches stay in its L2.
 #include "internal.h"
 
+#include <mutex>
+#include <vector>
+
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -188,14 +191,95 @@ hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double
     long long nwg = LOWER ? (long long)tiles_m * (tiles_m + 1) / 2 : (long long)tiles_m * tiles_n;
     if (nwg <= 0) return hipSuccess;
     if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int kind = LOWER ? 4 : TA * 2 + TB;
+    const double flops = LOWER ? (double)m * (m + 1) * k : 2.0 * m * n * k;
+    const int slot = cdf::prof_begin(s, kind, flops);
     hipLaunchKernelGGL((dgemm_kernel<TA, TB, LOWER>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k,
                        alpha, A, lda, B, ldb, beta, C, ldc, tiles_m, tiles_n, stop);
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    cdf::prof_end(s, slot);
+    return e;
 }
 
 }  // namespace
 
 namespace cdf {
+
+namespace {
+struct ProfRec {
+    hipEvent_t a, b;
+    int kind;
+    double flops;
+};
+struct ProfState {
+    std::mutex mu;
+    bool on = false;
+    std::vector<ProfRec> recs;  // recs[0, used) are live; events reused across sessions
+    size_t used = 0;
+};
+ProfState &prof_state() {
+    static ProfState st;
+    return st;
+}
+}  // namespace
+
+int prof_begin(hipStream_t s, int kind, double flops) {
+    ProfState &st = prof_state();
+    std::lock_guard<std::mutex> lk(st.mu);
+    if (!st.on) return -1;
+    if (st.used == st.recs.size()) {
+        ProfRec r{nullptr, nullptr, 0, 0.0};
+        if (hipEventCreate(&r.a) != hipSuccess) return -1;
+        if (hipEventCreate(&r.b) != hipSuccess) { (void)hipEventDestroy(r.a); return -1; }
+        st.recs.push_back(r);
+    }
+    ProfRec &r = st.recs[st.used];
+    r.kind = kind;
+    r.flops = flops;
+    if (hipEventRecord(r.a, s) != hipSuccess) return -1;
+    return (int)st.used++;
+}
+
+void prof_end(hipStream_t s, int slot) {
+    if (slot < 0) return;
+    ProfState &st = prof_state();
+    std::lock_guard<std::mutex> lk(st.mu);
+    if ((size_t)slot < st.used) (void)hipEventRecord(st.recs[slot].b, s);
+}
+
+void prof_enable() {
+    ProfState &st = prof_state();
+    std::lock_guard<std::mutex> lk(st.mu);
+    st.on = true;
+    st.used = 0;
+}
+
+hipError_t prof_collect(int kind, long long *launches, double *total_ms, double *flops) {
+    ProfState &st = prof_state();
+    std::lock_guard<std::mutex> lk(st.mu);
+    long long cnt = 0;
+    double ms = 0.0, fl = 0.0;
+    hipError_t err = hipSuccess;
+    {
+        for (size_t i = 0; i < st.used; ++i) {
+            const ProfRec &r = st.recs[i];
+            if (r.kind != kind) continue;
+            float t = 0.0f;
+            if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+                err = hipErrorUnknown;
+                continue;
+            }
+            ++cnt;
+            ms += t;
+            fl += r.flops;
+        }
+    }
+    st.on = false;  // records stay readable until the next prof_enable
+    *launches = cnt;
+    *total_ms = ms;
+    *flops = fl;
+    return err;
+}
 
 hipError_t dgemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha, const double *A,
                  int lda, const double *B, int ldb, double beta, double *C, int ldc, bool lower,

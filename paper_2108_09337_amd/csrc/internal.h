@@ -40,6 +40,14 @@ hipError_t dgemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alph
                  const double *A, int lda, const double *B, int ldb, double beta,
                  double *C, int ldc, bool lower, const int *stop = nullptr);
 
+// Kernel timing (process-wide): prof_begin records an event before a launch
+// and returns a slot (-1 when timing is off), prof_end records the closing
+// event; prof_collect sums launches / ms / flops of one kernel kind and stops.
+int prof_begin(hipStream_t s, int kind, double flops);
+void prof_end(hipStream_t s, int slot);
+void prof_enable();
+hipError_t prof_collect(int kind, long long *launches, double *total_ms, double *flops);
+
 // LU panel leaf: factor the m x n (n <= 32) column block at A with partial
 // pivoting; writes absolute 1-based pivots ipiv[0..n) (row offset `row0`
 // added), first zero pivot into *info (as info_base + j + 1) if *info == 0.

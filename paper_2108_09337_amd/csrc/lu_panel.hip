@@ -314,18 +314,17 @@ hipError_t laswp_impl(hipStream_t s, int c0, int c1, T *A, int lda, const int *i
 
 // ------------------------------------------------- panel-wide interchanges
 
-constexpr int PMAX = 256;            // interchanges per panel
+constexpr int PMAX = 512;            // interchanges per panel
 constexpr int PPAIRS = 2 * PMAX;
-constexpr int PSLOT = PPAIRS / 64;   // positions per lane
 
-// (dst, src) pairs of the interchanges ipiv[k1..k2) (k2 - k1 <= 256,
+// (dst, src) pairs of the interchanges ipiv[k1..k2) (k2 - k1 <= 512,
 // relative to row 0 of the region, 1-based; entries outside [k+1, nrows]
 // ignored), simulated by one thread on LDS: positions [k1, k2) in a direct
 // array, the other rows touched in an open-addressing hash table.
 // pairs[0] = count, pairs[1 + q] = dst row, pairs[1 + PPAIRS + q] = src row.
 __global__ __launch_bounds__(256) void pairs_kernel(const int *__restrict__ ipiv, int k1, int k2, int nrows,
                                                     int *__restrict__ pairs) {
-    constexpr int HS = 1024;
+    constexpr int HS = 2048;  // at most PMAX rows outside [k1, k2) are touched: load <= 1/4
     __shared__ int blk[PMAX];
     __shared__ int piv[PMAX];
     __shared__ int hkey[HS], hval[HS];
@@ -333,10 +332,10 @@ __global__ __launch_bounds__(256) void pairs_kernel(const int *__restrict__ ipiv
     const int t = threadIdx.x;
     const int nk = k2 - k1;
     for (int i = t; i < HS; i += 256) hkey[i] = -1;
-    if (t < nk) {
-        blk[t] = k1 + t;
-        int p = ipiv[k1 + t] - 1;
-        piv[t] = (p < k1 + t || p >= nrows) ? k1 + t : p;
+    for (int i = t; i < nk; i += 256) {
+        blk[i] = k1 + i;
+        const int p = ipiv[k1 + i] - 1;
+        piv[i] = (p < k1 + i || p >= nrows) ? k1 + i : p;
     }
     if (t == 0) cnt = 0;
     __syncthreads();
@@ -349,7 +348,7 @@ __global__ __launch_bounds__(256) void pairs_kernel(const int *__restrict__ ipiv
                 blk[j] = blk[p - k1];
                 blk[p - k1] = ck;
             } else {
-                unsigned hsh = ((unsigned)p * 2654435761u) >> 22;  // 10 bits
+                unsigned hsh = ((unsigned)p * 2654435761u) >> 21;  // 11 bits
                 while (hkey[hsh] != -1 && hkey[hsh] != p) hsh = (hsh + 1) & (HS - 1);
                 if (hkey[hsh] == -1) { hkey[hsh] = p; hval[hsh] = p; }
                 blk[j] = hval[hsh];
@@ -358,11 +357,12 @@ __global__ __launch_bounds__(256) void pairs_kernel(const int *__restrict__ ipiv
         }
     }
     __syncthreads();
-    if (t < nk && blk[t] != k1 + t) {
-        const int o = atomicAdd(&cnt, 1);
-        pairs[1 + o] = k1 + t;
-        pairs[1 + PPAIRS + o] = blk[t];
-    }
+    for (int i = t; i < nk; i += 256)
+        if (blk[i] != k1 + i) {
+            const int o = atomicAdd(&cnt, 1);
+            pairs[1 + o] = k1 + i;
+            pairs[1 + PPAIRS + o] = blk[i];
+        }
     for (int i = t; i < HS; i += 256)
         if (hkey[i] != -1 && hval[i] != hkey[i]) {
             const int o = atomicAdd(&cnt, 1);

@@ -581,8 +581,9 @@ hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *i
 }
 
 // Blocked right-looking lower Cholesky of the binary32 copy W.
-hipError_t mixed_potrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, MixedWs &w, int nb, int *info) {
+hipError_t mixed_potrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, MixedWs &w, int nb_in, int *info) {
     hipStream_t s = h->stream;
+    const int nb = nb_in < 256 ? nb_in : 256;  // the right-side solve takes triangles up to 256
     const int kp = kpad_of(nb);
     for (int k = 0; k < n; k += nb) {
         const int kb = nb < n - k ? nb : n - k;

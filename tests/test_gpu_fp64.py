@@ -77,7 +77,8 @@ def test_chol_hand_worked_bitwise(oracle_mod, name):
 
 
 @pytest.mark.parametrize("n,nb", [(1, 0), (2, 0), (3, 0), (31, 0), (32, 0), (33, 0), (100, 0), (255, 0),
-                                  (256, 0), (257, 0), (513, 0), (1024, 0), (1500, 0), (700, 64), (700, 96)])
+                                  (256, 0), (257, 0), (513, 0), (1024, 0), (1500, 0), (700, 64), (700, 96),
+                                  (1100, 384), (2100, 512)])
 def test_lu_parity_random(oracle_mod, n, nb):
     a = workloads.lu_uniform(n, seed=1000 + n)
     lu_or, ip_or, info_or = oracle_mod.dgetrf(a)

@@ -172,7 +172,7 @@ def _spotrf_mixed(fmt, a, nb=0):
 
 
 @pytest.mark.parametrize("fmt", FMTS)
-@pytest.mark.parametrize("n,nb", [(40, 32), (300, 64), (300, 0)])
+@pytest.mark.parametrize("n,nb", [(40, 32), (300, 64), (300, 0), (1100, 512)])
 def test_sgetrf_mixed_exact(fmt, n, nb):
     a, L, U = _exact_lu(n, np.random.default_rng(n + nb))
     w, ipiv, info = _sgetrf_mixed(fmt, a, nb)
@@ -182,7 +182,7 @@ def test_sgetrf_mixed_exact(fmt, n, nb):
 
 
 @pytest.mark.parametrize("fmt", FMTS)
-@pytest.mark.parametrize("n,nb", [(40, 32), (300, 64), (300, 0)])
+@pytest.mark.parametrize("n,nb", [(40, 32), (300, 64), (300, 0), (1100, 512)])
 def test_spotrf_mixed_exact(fmt, n, nb):
     rng = np.random.default_rng(7 + n)
     L = np.tril(rng.integers(-2, 3, (n, n)).astype(np.float64), -1)
