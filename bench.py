@@ -2,22 +2,30 @@
 
 Headline (``value``): one step = FP64 LU with partial pivoting (dgetrf) of an
 N x N matrix with uniform[-1, 1] entries + FP64 Cholesky (dpotrf) of an N x N
-SPD matrix B B^T / N + I (N = 32768 by default), inputs resident in HBM before
-the timed region (one fresh copy per step, made before timing);
-value = (2N^3/3 + N^3/3) / time in TFLOP/s.
+SPD matrix B B^T / N + I (N = 65536 by default, the largest size of the
+workload's size set; inputs drawn on the GPU with seeded generators and
+resident in HBM).  Each step factors scratch copies restored from the inputs
+before the step; the steps themselves are bracketed by synchronizations and
+timed; value = (2N^3/3 + N^3/3) / time in TFLOP/s.
 
 Also reported (``detail``):
+  * sizes: one warm LU and Cholesky at N = 8192 and 32768;
   * mixed: time-to-solution of A x = b (diagonally dominant, N = 65536,
     nrhs = 1) with the BF16 / FP16 update + FP64 refinement to an HPL scaled
     residual <= 16, against the FP64 path (FP64 LU + solve + the same
-    residual check) on the same matrix; speedup = FP64 time / mixed time;
+    residual check) on the same matrix, both with their tuned block sizes;
+    speedup = FP64 time / mixed time;
   * batched: 4096 LU/Cholesky problems, N log-uniform in [16, 512], one
     graph replay, FP64 and FP32, aggregate TFLOP/s.
 
-``roofline``: the FP64 Schur-complement update GEMM (the dominant kernel),
-replayed with the trailing-update shapes of one LU and timed with HIP events
-on the stream it is launched on.  ``cpu_baseline``: the CPU oracle on the
-first elimination steps of the same N x N inputs.
+``roofline``: the FP64 Schur-complement update GEMM (dgemm_kernel<0,0,false>,
+the dominant kernel): every launch of it inside the timed LU steps is
+bracketed by HIP events on the stream it runs on (the library's kernel-timing
+hook); achieved = algorithmic flops per launch / average launch duration.
+``traffic``: calibrated HBM bytes per launch from the committed rocprofv3 PMC
+summary of this benchmark, when it matches this N, block size and kernel
+source.  ``cpu_baseline``: the CPU oracle on the first elimination steps of
+the same N x N inputs.
 """
 import argparse
 import json
@@ -41,10 +49,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--n", type=int, default=32768)
+    p.add_argument("--n", type=int, default=65536)
+    p.add_argument("--detail-n", type=int, nargs="*", default=[8192, 32768],
+                   help="extra sizes measured once each (LU and Cholesky), reported in detail")
     p.add_argument("--mixed-n", type=int, default=65536)
     p.add_argument("--batch", type=int, default=4096)
-    p.add_argument("--cpu-steps", type=int, default=64, help="elimination steps in the oracle sample")
+    p.add_argument("--cpu-steps", type=int, default=32, help="elimination steps in the oracle sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-chol", action="store_true")
     p.add_argument("--no-mixed", action="store_true")
@@ -57,21 +67,6 @@ def parse():
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def spd_on_device(n, torch, cdf, workloads):
-    """A = B B^T / n + I from the seeded B (input generation on the GPU)."""
-    rng = np.random.default_rng(workloads.SEED_MATRIX)
-    b = torch.from_numpy(rng.standard_normal(size=(n, n))).cuda()
-    s = torch.matmul(b, b.t().contiguous()) / n
-    del b
-    s.diagonal().add_(1.0)
-    s = torch.tril(s) + torch.tril(s, -1).t()
-    out = cdf.cm_empty(n, n)
-    out.copy_(s)
-    del s
-    torch.cuda.empty_cache()
-    return out
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "dgemm_nn_lu_fp64_hbm_traffic.md")
@@ -123,16 +118,16 @@ def events(torch, k):
 
 
 def fp64_section(args, torch, cdf, workloads, h, tuned):
+    """Headline step: FP64 LU of the uniform matrix + FP64 Cholesky of the SPD
+    matrix at N = args.n.  Each factorization works on a scratch copy that is
+    restored from the resident input before the step, outside the timed
+    region; every step is bracketed by synchronizations and timed."""
     n, K, W = args.n, args.steps, args.warmup
-    log(f"FP64: generating inputs n={n}")
-    a_host = workloads.lu_uniform(n)
-    A0 = cdf.to_device(a_host)
-    lu_copies = [A0.clone() for _ in range(K + W)]
-    S0 = None
-    chol_copies = []
-    if not args.no_chol:
-        S0 = spd_on_device(n, torch, cdf, workloads)
-        chol_copies = [S0.clone() for _ in range(K + W)]
+    log(f"FP64: generating inputs on the GPU, n={n}")
+    S0 = None if args.no_chol else workloads.spd_bbt_torch(n)
+    A0 = workloads.lu_uniform_torch(n)
+    A = cdf.cm_empty(n, n)
+    S = cdf.cm_empty(n, n) if S0 is not None else None
     ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
     info_lu = torch.zeros(1, dtype=torch.int32, device="cuda")
     info_ch = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -140,43 +135,48 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
     ch_params = tuned(h, "potrf", n)
     torch.cuda.synchronize()
 
-    def step(i, ev=None):
-        if ev:
-            ev[0].record()
-        cdf.dgetrf(lu_copies[i], ipiv, info_lu)
-        if ev:
-            ev[1].record()
-        if chol_copies:
-            cdf.dpotrf(chol_copies[i], info_ch)
-        if ev:
-            ev[2].record()
+    def restore():
+        A.copy_(A0)
+        if S is not None:
+            S.copy_(S0)
+        torch.cuda.synchronize()
+
+    def step(ev):
+        ev[0].record()
+        cdf.dgetrf(A, ipiv, info_lu)
+        ev[1].record()
+        if S is not None:
+            cdf.dpotrf(S, info_ch)
+        ev[2].record()
 
     for i in range(W):
         log(f"warmup step {i}")
-        step(i)
+        restore()
+        step(events(torch, 3))
     torch.cuda.synchronize()
     evs = [events(torch, 3) for _ in range(K)]
     log(f"timing {K} steps")
-    torch.cuda.synchronize()
+    wall = 0.0
     cdf.profile_begin(h)  # HIP events around every update-GEMM launch, on the stream it runs on
-    t0 = time.perf_counter()
     for i in range(K):
-        step(W + i, evs[i])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+        restore()
+        t0 = time.perf_counter()
+        step(evs[i])
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
     prof_nn = cdf.profile_end("nn", h)
     prof_syrk = cdf.profile_end("syrk", h)
-    assert int(info_lu.item()) == 0 and (not chol_copies or int(info_ch.item()) == 0)
-    ms = (t1 - t0) * 1e3 / K
+    assert int(info_lu.item()) == 0 and (S is None or int(info_ch.item()) == 0)
+    ms = wall * 1e3 / K
     t_lu = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e-3
     t_ch = float(np.mean([e[1].elapsed_time(e[2]) for e in evs])) * 1e-3
     flops_lu = 2.0 * n ** 3 / 3.0
-    flops_ch = n ** 3 / 3.0 if chol_copies else 0.0
+    flops_ch = n ** 3 / 3.0 if S is not None else 0.0
     value = (flops_lu + flops_ch) / (ms * 1e-3) / 1e12
     log(f"ms/step {ms:.1f}  LU {flops_lu / t_lu / 1e12:.2f} TF  Chol {flops_ch / max(t_ch, 1e-12) / 1e12:.2f} TF")
 
     # dominant kernel: the FP64 update GEMM, every launch of it inside the timed LU steps
-    lu_nb = h.get_param("lu_nb") or 256
+    lu_nb = h.get_param("lu_nb") or 512
     launches = max(prof_nn["launches"], 1)
     avg = prof_nn["total_ms"] * 1e-3 / launches
     fpl = prof_nn["flops"] / launches
@@ -193,24 +193,63 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
            "params": {"getrf": lu_params, "potrf": ch_params}}
     for k in list(lu_params) + list(ch_params):
         h.set_param(k, 0)
-    del lu_copies, chol_copies
+    del A, S
     torch.cuda.empty_cache()
-    return out, a_host, S0
+    return out, A0, S0
 
 
-def mixed_section(args, torch, cdf, workloads, h):
+def size_detail(args, torch, cdf, workloads, h, tuned):
+    """One warm LU and one warm Cholesky at each extra size (event-timed)."""
+    res = {}
+    for n in args.detail_n:
+        A0 = workloads.lu_uniform_torch(n)
+        S0 = workloads.spd_bbt_torch(n)
+        ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        r = {}
+        for name, src, op, fl in (("lu", A0, "getrf", 2.0 * n ** 3 / 3), ("chol", S0, "potrf", n ** 3 / 3.0)):
+            params = tuned(h, op, n)
+            X = cdf.cm_empty(n, n)
+            best = None
+            for rep in range(2):
+                X.copy_(src)
+                e0, e1 = events(torch, 2)
+                torch.cuda.synchronize()
+                e0.record()
+                if name == "lu":
+                    cdf.dgetrf(X, ipiv, info)
+                else:
+                    cdf.dpotrf(X, info)
+                e1.record()
+                torch.cuda.synchronize()
+                assert int(info.item()) == 0
+                t = e0.elapsed_time(e1) * 1e-3
+                best = t if rep == 1 else best
+            r[name] = {"seconds": round(best, 5), "tflops": round(fl / best / 1e12, 3),
+                       "frac_peak": round(fl / best / 1e12 / FP64_PEAK, 4), "params": params}
+            for k in params:
+                h.set_param(k, 0)
+            del X
+        log(f"n={n}: LU {r['lu']['tflops']} TF, Cholesky {r['chol']['tflops']} TF")
+        res[str(n)] = r
+        del A0, S0
+        torch.cuda.empty_cache()
+    return res
+
+
+def mixed_section(args, torch, cdf, workloads, h, tuned):
     n = args.mixed_n
     log(f"mixed: generating diagonally dominant n={n}")
     A = workloads.diag_dominant_torch(n)
     b = workloads.rhs_uniform_torch(n)
     X = torch.empty(n, dtype=torch.float64, device="cuda")
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
-    res = {"n": n, "nrhs": 1}
+    res = {"n": n, "nrhs": 1, "params": {"fp64": tuned(h, "getrf", n), "mixed": tuned(h, "mixed_getrf", n)}}
     for prec in ("fp64", "bf16", "fp16"):
-        cdf.dgesv_mixed(prec, A, b, X, info, max_iter=30)  # warm-up (also allocates the workspace)
+        cdf.dgesv_mixed(prec, A, b, X, info, max_iter=30, h=h)  # warm-up (also allocates the workspace)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = cdf.dgesv_mixed(prec, A, b, X, info, max_iter=30)
+        r = cdf.dgesv_mixed(prec, A, b, X, info, max_iter=30, h=h)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         res[prec] = {"seconds": round(t, 4), "iters": r["iters"], "scaled_resid": round(r["scaled_resid"], 4),
@@ -218,6 +257,9 @@ def mixed_section(args, torch, cdf, workloads, h):
         log(f"mixed {prec}: {t:.3f} s, iters {r['iters']}, resid {r['scaled_resid']:.3f}")
     for prec in ("bf16", "fp16"):
         res[prec]["speedup_vs_fp64"] = round(res["fp64"]["seconds"] / res[prec]["seconds"], 3)
+    for group in res["params"].values():
+        for k in group:
+            h.set_param(k, 0)
     del A, X
     torch.cuda.empty_cache()
     return res
@@ -287,7 +329,7 @@ def main():
 
     if args.calibrate_bytes:
         calibrate_copy(torch, args.calibrate_bytes)
-    fp, a_host, S0 = fp64_section(args, torch, cdf, workloads, h, tuned)
+    fp, A0, S0 = fp64_section(args, torch, cdf, workloads, h, tuned)
     detail = {"lu_tflops": round(fp["flops_lu"] / fp["t_lu"] / 1e12, 3),
               "chol_tflops": round(fp["flops_ch"] / fp["t_ch"] / 1e12, 3) if fp["flops_ch"] else None,
               "lu_s": round(fp["t_lu"], 4), "chol_s": round(fp["t_ch"], 4),
@@ -297,9 +339,11 @@ def main():
         import oracle
         s = args.cpu_steps
         log(f"oracle sample: first {s} elimination steps of the n={args.n} LU and Cholesky")
+        a_host = cdf.to_host(A0)
         t = time.perf_counter()
         oracle.dgetrf(a_host, ksteps=s)
         t_cl = time.perf_counter() - t
+        del a_host
         f = oracle.lu_step_flops(args.n, s)
         if S0 is not None:
             s_host = cdf.to_host(S0)
@@ -312,10 +356,12 @@ def main():
                "kind": "oracle",
                "sample": f"first {s} elimination steps of the n={args.n} LU and Cholesky factorizations of the "
                          f"benchmark's own inputs ({f:.3e} flop in {t_cl:.1f} s)"}
-    del a_host, S0
+    del A0, S0
     torch.cuda.empty_cache()
+    if args.detail_n:
+        detail["sizes"] = size_detail(args, torch, cdf, workloads, h, tuned)
     if not args.no_mixed:
-        detail["mixed"] = mixed_section(args, torch, cdf, workloads, h)
+        detail["mixed"] = mixed_section(args, torch, cdf, workloads, h, tuned)
     if not args.no_batched:
         detail["batched"] = batched_section(args, torch, cdf, workloads, h, tuned)
 
@@ -325,7 +371,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(fp["ms"], 2), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"FP64 LU with partial pivoting (uniform[-1,1]) + FP64 Cholesky (B B^T/N + I), "
-                               f"N={n}, one matrix each per step", "n": n, "lu_nb": fp["lu_nb"],
+                               f"N={n}, one matrix each per step (inputs drawn on the GPU)", "n": n,
+                   "lu_nb": fp["lu_nb"],
                    "chol_nb": fp["chol_nb"]},
         "roofline": fp["roofline"],
         "cpu_baseline": cpu,

@@ -19,9 +19,9 @@ inline cdf_status_t bad(cdf_handle_t h, int pos) {
     return CDF_ERR_INVALID_ARG;
 }
 
-inline int lu_nb(cdf_handle_t h) {
+inline int lu_nb(cdf_handle_t h, int n) {
     const int v = h->params[CDF_PARAM_LU_NB];
-    return v > 0 ? v : 256;
+    return v > 0 ? v : (n >= 16384 ? 512 : 256);
 }
 
 inline int chol_nb(cdf_handle_t h) {
@@ -69,6 +69,13 @@ hipError_t lu_panel(cdf_handle_t h, hipStream_t s, int m, int ncols, double *A, 
 // diagonal block, trsm of the block column below it, triangular (lower
 // tiles only) update of the trailing matrix.  Stops (all later launches are
 // no-ops) once *info != 0; info values are offset by info_off.
+hipError_t ensure_aux(cdf_handle_t h) {
+    if (!h->aux) CDF_HIP_RET(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    for (auto &e : h->ev)
+        if (!e) CDF_HIP_RET(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return hipSuccess;
+}
+
 hipError_t potrf_blocked(cdf_handle_t h, int n, double *A, int lda, int *info, int info_off, int nb) {
     hipStream_t s = h->stream;
     for (int k = 0; k < n; k += nb) {
@@ -90,13 +97,6 @@ hipError_t potrf_blocked(cdf_handle_t h, int n, double *A, int lda, int *info, i
 
 namespace {
 
-hipError_t ensure_aux(cdf_handle_t h) {
-    if (!h->aux) CDF_HIP_RET(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
-    for (auto &e : h->ev)
-        if (!e) CDF_HIP_RET(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    return hipSuccess;
-}
-
 struct LuWs {
     int *ipt;    // region-relative pivots of the current panel
     int *pairs;  // its interchange pairs
@@ -116,16 +116,15 @@ hipError_t factor_panel(cdf_handle_t h, hipStream_t s, int n, double *A, int lda
 // update of panel k runs on the handle's stream, panel k+1 (whose columns
 // were updated first) is factored on a second stream; its interchanges are
 // applied to the other columns once both are done.
-hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info) {
+hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ipt, int *pairs) {
     hipStream_t s0 = h->stream;
-    CDF_HIP_RET(ensure_aux(h));
+    CDF_HIP_RET(cdf::ensure_aux(h));
     hipStream_t s1 = h->aux;
     CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
-    const int nb = lu_nb(h);
+    const int nb = lu_nb(h, n);
     LuWs ws;
-    char *base = static_cast<char *>(h->ws) + cdf::kLeafWsBytes;
-    ws.ipt = reinterpret_cast<int *>(base);
-    ws.pairs = reinterpret_cast<int *>(base + kMaxLuNb * sizeof(int));
+    ws.ipt = ipt;
+    ws.pairs = pairs;
     const int kb0 = nb < n ? nb : n;
     CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, 0, kb0, ws));
     CDF_HIP_RET(cdf::apply_pairs(s0, kb0, n, A, lda, ws.pairs));
@@ -167,7 +166,7 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
 // touched; every launch after a failed pivot is a no-op (stop = info).
 hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
     hipStream_t s0 = h->stream;
-    CDF_HIP_RET(ensure_aux(h));
+    CDF_HIP_RET(cdf::ensure_aux(h));
     hipStream_t s1 = h->aux;
     CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
     const int nb = chol_nb(h);
@@ -211,6 +210,16 @@ hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
 }  // namespace
 
 namespace cdf {
+
+size_t getrf_ws_ints() { return kMaxLuNb + 1 + 4 * kMaxLuNb; }
+
+hipError_t getrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ws_ints) {
+    return getrf_impl(h, n, A, lda, ipiv, info, ws_ints, ws_ints + kMaxLuNb);
+}
+
+hipError_t potrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *info) {
+    return potrf_impl(h, n, A, lda, info);
+}
 
 __global__ void offset_kernel(const int *__restrict__ a, int *__restrict__ b, int count, int off) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -358,7 +367,9 @@ cdf_status_t cdf_dgetrf(cdf_handle_t h, int n, double *A, int lda, int *ipiv, in
     }
     cdf_status_t st = cdf::ws_reserve(h, kLuWsBytes);
     if (st != CDF_OK) return st;
-    CDF_HIP_TRY(getrf_impl(h, n, A, lda, ipiv, info));
+    char *base = static_cast<char *>(h->ws) + cdf::kLeafWsBytes;
+    CDF_HIP_TRY(getrf_impl(h, n, A, lda, ipiv, info, reinterpret_cast<int *>(base),
+                           reinterpret_cast<int *>(base + kMaxLuNb * sizeof(int))));
     return CDF_OK;
 }
 

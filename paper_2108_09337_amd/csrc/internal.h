@@ -40,6 +40,17 @@ hipError_t dgemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alph
                  const double *A, int lda, const double *B, int ldb, double beta,
                  double *C, int ldc, bool lower, const int *stop = nullptr);
 
+// The binary64 factorizations behind cdf_dgetrf / cdf_dpotrf on the handle's
+// stream (look-ahead on its second stream); getrf_fp64 takes a device work
+// area of getrf_ws_ints() ints (panel pivots and interchange pairs) besides
+// the leaf's exchange area at the head of the handle's workspace.
+size_t getrf_ws_ints();
+hipError_t getrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ws_ints);
+hipError_t potrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *info);
+
+// Creates the handle's second stream (default priority) and its two events.
+hipError_t ensure_aux(cdf_handle_t h);
+
 // Kernel timing (process-wide): prof_begin records an event before a launch
 // and returns a slot (-1 when timing is off), prof_end records the closing
 // event; prof_collect sums launches / ms / flops of one kernel kind and stops.

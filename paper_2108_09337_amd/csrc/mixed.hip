@@ -495,10 +495,11 @@ struct MixedWs {
     float *W = nullptr;        // binary32 working copy, n x n
     double *Wd = nullptr;      // binary64 copy of the finished factor (for the solves)
     double *Afull = nullptr;   // symmetric extension of A (Cholesky residual)
-    double *P = nullptr;       // binary64 panel, n x nb
+    double *P[2] = {nullptr, nullptr};  // binary64 panels, n x nb each (double-buffered for look-ahead)
     double *U = nullptr;       // binary64 staging of U12, nb x n
     void *QA = nullptr, *QB = nullptr;
     int *ea = nullptr, *eb = nullptr, *ipt = nullptr, *ipiv = nullptr;
+    int *lu_ws = nullptr;      // work area of the binary64 LU (fp64 mode)
     double *R = nullptr, *red = nullptr;
 };
 
@@ -516,13 +517,14 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     const size_t oW = factor_only ? 0 : take(nn * sizeof(float));
     const size_t oWd = factor_only ? 0 : take(nn * sizeof(double));
     const size_t oAf = (chol && !factor_only) ? take(nn * sizeof(double)) : 0;
-    const size_t oP = take((size_t)n * nb * sizeof(double));
+    const size_t oP = take((size_t)n * nb * sizeof(double)), oP1 = take((size_t)n * nb * sizeof(double));
     const size_t oU = take((size_t)n * nb * sizeof(double));
     const size_t oQA = take(kp * n * esize(fmt));
     const size_t oQB = take(kp * n * esize(fmt));
     const int nt = (n + QT - 1) / QT + 1;
     const size_t oea = take(nt * sizeof(int)), oeb = take(nt * sizeof(int));
     const size_t oipt = take((size_t)nb * sizeof(int)), oipiv = take((size_t)n * sizeof(int));
+    const size_t olw = take(cdf::getrf_ws_ints() * sizeof(int));
     const size_t oR = take((size_t)n * nrhs * sizeof(double));
     const size_t ored = take(((size_t)n + 4 * (size_t)nrhs + 8) * sizeof(double));
     cdf_status_t st = cdf::ws_reserve(h, off);
@@ -531,7 +533,8 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     w.W = factor_only ? nullptr : reinterpret_cast<float *>(base + oW);
     w.Wd = factor_only ? nullptr : reinterpret_cast<double *>(base + oWd);
     w.Afull = (chol && !factor_only) ? reinterpret_cast<double *>(base + oAf) : nullptr;
-    w.P = reinterpret_cast<double *>(base + oP);
+    w.P[0] = reinterpret_cast<double *>(base + oP);
+    w.P[1] = reinterpret_cast<double *>(base + oP1);
     w.U = reinterpret_cast<double *>(base + oU);
     w.QA = base + oQA;
     w.QB = base + oQB;
@@ -539,42 +542,73 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     w.eb = reinterpret_cast<int *>(base + oeb);
     w.ipt = reinterpret_cast<int *>(base + oipt);
     w.ipiv = reinterpret_cast<int *>(base + oipiv);
+    w.lu_ws = reinterpret_cast<int *>(base + olw);
     w.R = reinterpret_cast<double *>(base + oR);
     w.red = reinterpret_cast<double *>(base + ored);
     return CDF_OK;
 }
 
-inline int mixed_nb(cdf_handle_t h) {
+inline int mixed_nb(cdf_handle_t h, int n) {
     const int v = h->params[CDF_PARAM_MIXED_NB];
-    return v > 0 ? v : 256;
+    return v > 0 ? v : (n >= 16384 ? 512 : 256);
 }
 
 // Blocked right-looking LU of the binary32 copy W (see the file comment);
-// absolute 1-based pivots go to ipiv.
+// absolute 1-based pivots go to ipiv.  Look-ahead of depth one, as in the
+// binary64 path: the next panel's columns are updated first and that panel
+// is factored on the second stream while the rest of the trailing matrix is
+// updated (when the panel width is a multiple of the quantization tile, so
+// both parts of the update keep the tile exponents of U12).
 hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *ipiv, MixedWs &w, int nb, int *info) {
-    hipStream_t s = h->stream;
+    hipStream_t s0 = h->stream;
+    CDF_HIP_RET(cdf::ensure_aux(h));
+    hipStream_t s1 = h->aux;
     const int kp = kpad_of(nb);
-    for (int k = 0; k < n; k += nb) {
-        const int kb = nb < n - k ? nb : n - k;
-        const int m = n - k, rest = n - k - kb;
-        CDF_HIP_RET(cdf::convert_s2d(s, m, kb, W + k + (size_t)k * ldw, ldw, w.P, m, false));
-        CDF_HIP_RET(cdf::lu_panel(h, s, m, kb, w.P, m, w.ipt, info, 0, kb, k));
+    const bool split = nb % QT == 0;
+    // panel of width kb at column k: binary64 copy in P, factored there,
+    // pivots to w.ipt (relative) and ipiv (absolute), copied back to W
+    auto panel = [&](hipStream_t s, int k, int kb, double *P) -> hipError_t {
+        const int m = n - k;
+        CDF_HIP_RET(cdf::convert_s2d(s, m, kb, W + k + (size_t)k * ldw, ldw, P, m, false));
+        CDF_HIP_RET(cdf::lu_panel(h, s, m, kb, P, m, w.ipt, info, 0, kb, k));
         hipLaunchKernelGGL(add_offset_kernel, dim3((kb + 255) / 256), dim3(256), 0, s, w.ipt, ipiv + k, kb, k);
         CDF_HIP_RET(hipGetLastError());
-        CDF_HIP_RET(cdf::convert_d2s(s, m, kb, w.P, m, W + k + (size_t)k * ldw, ldw, false));
-        CDF_HIP_RET(cdf::slaswp(s, 0, k, W + k, ldw, w.ipt, 0, kb, m));
-        CDF_HIP_RET(cdf::slaswp(s, k + kb, n, W + k, ldw, w.ipt, 0, kb, m));
-        if (rest > 0) {
-            float *w12 = W + k + (size_t)(k + kb) * ldw;
-            float *w21 = W + (k + kb) + (size_t)k * ldw;
-            float *w22 = W + (k + kb) + (size_t)(k + kb) * ldw;
-            CDF_HIP_RET(cdf::convert_s2d(s, kb, rest, w12, ldw, w.U, kb, false));
-            CDF_HIP_RET(cdf::trsm_blocked(s, cdf::TRSM_LLNU, kb, rest, w.P, m, w.U, kb, 64));
-            CDF_HIP_RET(cdf::convert_d2s(s, kb, rest, w.U, kb, w12, ldw, false));
-            CDF_HIP_RET(cdf::quantize(s, fmt, rest, kb, w21, ldw, QT, kb, w.QA, kp, w.ea, true));
-            CDF_HIP_RET(cdf::quantize(s, fmt, kb, rest, w12, ldw, kb, QT, w.QB, kp, w.eb, false));
-            CDF_HIP_RET(cdf::lowp_update(s, fmt, rest, rest, kb, w.QA, kp, w.ea, w.QB, kp, w.eb, w22, ldw, false,
+        return cdf::convert_d2s(s, m, kb, P, m, W + k + (size_t)k * ldw, ldw, false);
+    };
+    CDF_HIP_RET(panel(s0, 0, nb < n ? nb : n, w.P[0]));
+    for (int k = 0, it = 0; k < n; k += nb, ++it) {
+        const int kb = nb < n - k ? nb : n - k;
+        const int m = n - k, rest = n - k - kb;
+        double *P = w.P[it & 1];
+        CDF_HIP_RET(cdf::slaswp(s0, 0, k, W + k, ldw, w.ipt, 0, kb, m));
+        CDF_HIP_RET(cdf::slaswp(s0, k + kb, n, W + k, ldw, w.ipt, 0, kb, m));
+        if (rest <= 0) break;
+        float *w12 = W + k + (size_t)(k + kb) * ldw;
+        float *w21 = W + (k + kb) + (size_t)k * ldw;
+        float *w22 = W + (k + kb) + (size_t)(k + kb) * ldw;
+        CDF_HIP_RET(cdf::convert_s2d(s0, kb, rest, w12, ldw, w.U, kb, false));
+        CDF_HIP_RET(cdf::trsm_blocked(s0, cdf::TRSM_LLNU, kb, rest, P, m, w.U, kb, 64));
+        CDF_HIP_RET(cdf::convert_d2s(s0, kb, rest, w.U, kb, w12, ldw, false));
+        CDF_HIP_RET(cdf::quantize(s0, fmt, rest, kb, w21, ldw, QT, kb, w.QA, kp, w.ea, true));
+        CDF_HIP_RET(cdf::quantize(s0, fmt, kb, rest, w12, ldw, kb, QT, w.QB, kp, w.eb, false));
+        const int k1 = k + kb;
+        const int kb1 = nb < n - k1 ? nb : n - k1;
+        if (split && rest > kb1) {
+            // next panel's columns, then that panel beside the rest of the update
+            CDF_HIP_RET(cdf::lowp_update(s0, fmt, rest, kb1, kb, w.QA, kp, w.ea, w.QB, kp, w.eb, w22, ldw, false,
                                          nullptr));
+            CDF_HIP_RET(hipEventRecord(h->ev[0], s0));
+            CDF_HIP_RET(hipStreamWaitEvent(s1, h->ev[0], 0));
+            CDF_HIP_RET(panel(s1, k1, kb1, w.P[(it + 1) & 1]));
+            CDF_HIP_RET(hipEventRecord(h->ev[1], s1));
+            const char *qb = static_cast<const char *>(w.QB) + (size_t)kb1 * kp * esize(fmt);
+            CDF_HIP_RET(cdf::lowp_update(s0, fmt, rest, rest - kb1, kb, w.QA, kp, w.ea, qb, kp, w.eb + kb1 / QT,
+                                         w22 + (size_t)kb1 * ldw, ldw, false, nullptr));
+            CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[1], 0));
+        } else {
+            CDF_HIP_RET(cdf::lowp_update(s0, fmt, rest, rest, kb, w.QA, kp, w.ea, w.QB, kp, w.eb, w22, ldw, false,
+                                         nullptr));
+            CDF_HIP_RET(panel(s0, k1, kb1, w.P[(it + 1) & 1]));
         }
     }
     return hipSuccess;
@@ -589,13 +623,13 @@ hipError_t mixed_potrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, MixedW
         const int kb = nb < n - k ? nb : n - k;
         const int rest = n - k - kb;
         float *w11 = W + k + (size_t)k * ldw;
-        CDF_HIP_RET(cdf::convert_s2d(s, kb, kb, w11, ldw, w.P, kb, true));
-        CDF_HIP_RET(cdf::potrf_blocked(h, kb, w.P, kb, info, k, 128));
-        CDF_HIP_RET(cdf::convert_d2s(s, kb, kb, w.P, kb, w11, ldw, true));
+        CDF_HIP_RET(cdf::convert_s2d(s, kb, kb, w11, ldw, w.P[0], kb, true));
+        CDF_HIP_RET(cdf::potrf_blocked(h, kb, w.P[0], kb, info, k, 128));
+        CDF_HIP_RET(cdf::convert_d2s(s, kb, kb, w.P[0], kb, w11, ldw, true));
         if (rest > 0) {
             float *w21 = W + (k + kb) + (size_t)k * ldw;
             float *w22 = W + (k + kb) + (size_t)(k + kb) * ldw;
-            CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_RLTN, kb, rest, w.P, kb, w21, ldw, info));
+            CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_RLTN, kb, rest, w.P[0], kb, w21, ldw, info));
             CDF_HIP_RET(cdf::quantize(s, fmt, rest, kb, w21, ldw, QT, kb, w.QA, kp, w.ea, true));
             CDF_HIP_RET(cdf::lowp_update(s, fmt, rest, rest, kb, w.QA, kp, w.ea, w.QA, kp, w.ea, w22, ldw, true,
                                          info));
@@ -620,7 +654,7 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
                          const double *B, int ldb, double *X, int ldx, int max_iter, int *iters, double *resid,
                          int *info) {
     hipStream_t s = h->stream;
-    const int nb = mixed_nb(h);
+    const int nb = mixed_nb(h, n);
     MixedWs w;
     cdf_status_t st = mixed_layout(h, n, nrhs, nb, fmt == 0 ? FMT_BF16 : fmt, chol, w);
     if (st != CDF_OK) return st;
@@ -645,20 +679,8 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
     // factorization of the working copy
     if (fmt == 0) {
         CDF_HIP_TRY(cdf::copy_cols(s, n, n, A, lda, w.Wd, n));
-        if (chol) CDF_HIP_TRY(cdf::potrf_blocked(h, n, w.Wd, n, info, 0, 128));
-        else {
-            const int lnb = h->params[CDF_PARAM_LU_NB] > 0 ? h->params[CDF_PARAM_LU_NB] : 256;
-            for (int k = 0; k < n; k += lnb) {
-                const int kb = lnb < n - k ? lnb : n - k, rest = n - k - kb;
-                CDF_HIP_TRY(cdf::lu_panel(h, s, n, n, w.Wd, n, w.ipiv, info, k, kb, 0));
-                if (rest > 0) {
-                    double *a11 = w.Wd + k + (size_t)k * n, *a12 = w.Wd + k + (size_t)(k + kb) * n;
-                    double *a21 = w.Wd + (k + kb) + (size_t)k * n, *a22 = w.Wd + (k + kb) + (size_t)(k + kb) * n;
-                    CDF_HIP_TRY(cdf::trsm_small(s, cdf::TRSM_LLNU, kb, rest, a11, n, a12, n));
-                    CDF_HIP_TRY(cdf::dgemm(s, 0, 0, rest, rest, kb, -1.0, a21, n, a12, n, 1.0, a22, n, false));
-                }
-            }
-        }
+        if (chol) CDF_HIP_TRY(cdf::potrf_fp64(h, n, w.Wd, n, info));
+        else CDF_HIP_TRY(cdf::getrf_fp64(h, n, w.Wd, n, w.ipiv, info, w.lu_ws));
     } else {
         CDF_HIP_TRY(cdf::convert_d2s(s, n, n, A, lda, w.W, n, chol));
         if (chol) CDF_HIP_TRY(mixed_potrf(h, fmt, n, w.W, n, w, nb, info));
@@ -791,7 +813,7 @@ cdf_status_t cdf_sgetrf_mixed(cdf_handle_t h, cdf_update_prec_t p, int n, const 
     if (!W) return bad(6);
     if (!ipiv) return bad(8);
     MixedWs w;
-    const int nb = mixed_nb(h);
+    const int nb = mixed_nb(h, n);
     cdf_status_t st = mixed_layout(h, n, 1, nb, (int)p, false, w, true);
     if (st != CDF_OK) return st;
     CDF_HIP_TRY(cdf::fill_int(h->stream, info, 1, 0));
@@ -818,7 +840,7 @@ cdf_status_t cdf_spotrf_mixed(cdf_handle_t h, cdf_update_prec_t p, char uplo, in
     if (!A) return bad(5);
     if (!W) return bad(7);
     MixedWs w;
-    const int nb = mixed_nb(h);
+    const int nb = mixed_nb(h, n);
     cdf_status_t st = mixed_layout(h, n, 1, nb, (int)p, true, w, true);
     if (st != CDF_OK) return st;
     CDF_HIP_TRY(cdf::fill_int(h->stream, info, 1, 0));

@@ -115,6 +115,34 @@ def diag_dominant_torch(n: int, seed: int = SEED_MATRIX, device: str = "cuda"):
     return a.t()
 
 
+def lu_uniform_torch(n: int, seed: int = SEED_MATRIX, device: str = "cuda"):
+    """lu_uniform() drawn on the GPU with torch's seeded generator (same
+    distribution, different stream), as a column-major view."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    a = torch.empty((n, n), dtype=torch.float64, device=device)  # a[j, i] = entry (i, j)
+    a.uniform_(-1.0, 1.0, generator=g)
+    return a.t()
+
+
+def spd_bbt_torch(n: int, seed: int = SEED_MATRIX, device: str = "cuda"):
+    """spd_bbt() drawn on the GPU: B B^T / n + I with B iid N(0, 1) from
+    torch's seeded generator, as a column-major view.  The product is
+    symmetric up to rounding; Cholesky reads its lower triangle only."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    b = torch.empty((n, n), dtype=torch.float64, device=device)
+    b.normal_(0.0, 1.0, generator=g)
+    s = torch.mm(b, b.t().contiguous())
+    del b
+    s.div_(n)
+    s.diagonal().add_(1.0)
+    torch.cuda.empty_cache()
+    return s.t()
+
+
 def rhs_uniform_torch(n: int, nrhs: int = 1, seed: int = SEED_RHS, device: str = "cuda"):
     import torch
     g = torch.Generator(device=device)
