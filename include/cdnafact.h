@@ -75,7 +75,7 @@ CDF_API const char *cdf_status_string(cdf_status_t s);
 /* Tunable parameters (block sizes chosen per call when left at 0 = auto). */
 typedef enum {
     CDF_PARAM_LU_NB = 0,         /* LU outer panel width (multiple of 32, <= 512) */
-    CDF_PARAM_CHOL_NB = 1,       /* Cholesky outer block width (multiple of 32, <= 128) */
+    CDF_PARAM_CHOL_NB = 1,       /* Cholesky outer block width (multiple of 32, <= 512) */
     CDF_PARAM_LU_LEAF_ROWS = 2,  /* rows per thread in the LU panel leaf (1 or 2) */
     CDF_PARAM_MIXED_NB = 3,      /* block width of the mixed-precision factorizations (multiple of 32,
                                     <= 512; the Cholesky uses at most 256) */

@@ -170,11 +170,26 @@ hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
     hipStream_t s1 = h->aux;
     CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
     const int nb = chol_nb(h);
+    // block column [k, k+kb): right-looking over sub-blocks of at most 128
+    // columns (the diagonal-block kernel's limit); each sub-block updates
+    // only the rest of this block column.
     auto panel = [&](hipStream_t s, int k, int kb) -> hipError_t {
-        double *a11 = A + k + (size_t)k * lda;
-        CDF_HIP_RET(cdf::potrf_diag(s, kb, a11, lda, info, k));
-        const int rest = n - k - kb;
-        if (rest > 0) CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_RLTN, kb, rest, a11, lda, a11 + kb, lda, info));
+        for (int kk = k; kk < k + kb; kk += 128) {
+            const int kbb = 128 < k + kb - kk ? 128 : k + kb - kk;
+            double *a11 = A + kk + (size_t)kk * lda;
+            CDF_HIP_RET(cdf::potrf_diag(s, kbb, a11, lda, info, kk));
+            const int below = n - kk - kbb;
+            if (below > 0) CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_RLTN, kbb, below, a11, lda, a11 + kbb, lda, info));
+            const int c = kk + kbb, w = k + kb - c;  // remaining columns of the block column
+            if (w > 0) {
+                double *l = A + c + (size_t)kk * lda;  // rows [c, n) of the sub-block's L
+                CDF_HIP_RET(cdf::dgemm(s, 0, 1, w, w, kbb, -1.0, l, lda, l, lda, 1.0, A + c + (size_t)c * lda, lda,
+                                       true, info));
+                if (n - c - w > 0)
+                    CDF_HIP_RET(cdf::dgemm(s, 0, 1, n - c - w, w, kbb, -1.0, l + w, lda, l, lda, 1.0,
+                                           A + (c + w) + (size_t)c * lda, lda, false, info));
+            }
+        }
         return hipSuccess;
     };
     CDF_HIP_RET(panel(s0, 0, nb < n ? nb : n));
@@ -340,7 +355,6 @@ cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value) {
     if ((p == CDF_PARAM_LU_NB || p == CDF_PARAM_CHOL_NB || p == CDF_PARAM_MIXED_NB) && value != 0 &&
         (value % 32 != 0 || value > kMaxLuNb))
         return bad(h, 3);
-    if (p == CDF_PARAM_CHOL_NB && value > 128) return bad(h, 3);
     if (p == CDF_PARAM_LU_LEAF_ROWS && !(value == 0 || value == 1 || value == 2)) return bad(h, 3);
     if (p == CDF_PARAM_VBATCH_NB && !(value == 0 || value == 16)) return bad(h, 3);
     if (p == CDF_PARAM_VBATCH_WG_PER_CU && value > 2) return bad(h, 3);

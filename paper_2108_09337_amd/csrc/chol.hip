@@ -6,50 +6,97 @@
 // the LAPACK info.  Only the lower triangle is read or written.
 #include "internal.h"
 
+#include <type_traits>
+
 namespace {
 
 constexpr int NT = 256;
 constexpr int MAXN = 128;
-constexpr int LD = MAXN + 1;
 
+// Compile-time loop: f(integral_constant<int, I>) for I in [B, E), so that
+// register-array indices are constants before any optimization runs.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// One workgroup of 256 threads; the block's lower triangle lives in
+// registers: thread (wave w, lane l) owns rows l and l + 64 of columns
+// j = w + 4q (q < 32).  Column k (k = 4 kq + kw): its diagonal owner
+// publishes d = L(k,k); every thread checks d > 0 (S1's domain); the owners
+// of column k form sqrt(d) (S1) and the scaled column (S2, division) and
+// publish it in LDS (double-buffered by parity); every thread then updates
+// its elements right of column k (S3) from the published column.  Two
+// barriers per column.
 __global__ __launch_bounds__(NT) void potrf_diag_kernel(int n, double *__restrict__ A, int lda,
                                                         int *__restrict__ info, int info_base) {
     if (*info != 0) return;
-    extern __shared__ double L[];  // L[i + j * LD]
-    __shared__ int fail;
-    const int t = threadIdx.x;
-    for (int e = t; e < n * n; e += NT) {
-        const int i = e % n, j = e / n;
-        if (i >= j) L[i + j * LD] = A[(size_t)i + (size_t)j * lda];
-    }
-    if (t == 0) fail = 0;
-    __syncthreads();
-    int kdone = n;
-    for (int k = 0; k < n; ++k) {
-        if (t == 0) {
-            const double d = L[k + k * LD];
-            if (!(d > 0.0)) fail = k + 1;
-            else L[k + k * LD] = sqrt(d);
+    __shared__ double sc[2][MAXN];
+    __shared__ double sd;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    double a[2][32];
+    static_for<0, 2>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        static_for<0, 32>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int i = lane + 64 * r, j = w + 4 * q;
+            a[r][q] = (i < n && j < n && i >= j) ? A[(size_t)i + (size_t)j * lda] : 0.0;
+        });
+    });
+    int fail = 0;  // uniform: every thread reads the same published diagonal
+    static_for<0, 32>([&](auto kqc) {
+        constexpr int kq = decltype(kqc)::value;
+        for (int kw = 0; kw < 4; ++kw) {
+            const int k = 4 * kq + kw;
+            if (fail || k >= n) continue;
+            const int par = k & 1;
+            const bool own = (w == kw);
+            if (own && lane == (k & 63)) sd = a[kq >> 4][kq];
+            __syncthreads();
+            const double d = sd;
+            if (!(d > 0.0)) {
+                fail = k + 1;
+                continue;
+            }
+            if (own) {
+                const double lkk = sqrt(d);
+                static_for<0, 2>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    const int i = lane + 64 * r;
+                    if (i >= k && i < n) {
+                        const double v = i == k ? lkk : a[r][kq] / lkk;
+                        a[r][kq] = v;
+                        sc[par][i - k] = v;
+                    }
+                });
+            }
+            __syncthreads();
+            // S3 on the elements right of column k: j = w + 4q > k
+            const int i0 = lane, i1 = lane + 64;
+            const double l0 = (i0 > k && i0 < n) ? sc[par][i0 - k] : 0.0;
+            const double l1 = (i1 > k && i1 < n) ? sc[par][i1 - k] : 0.0;
+            static_for<kq, 32>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                const int j = w + 4 * q;
+                if (j > k && j < n) {
+                    const double lj = sc[par][j - k];
+                    if (i0 >= j) a[0][q] = fma(-l0, lj, a[0][q]);
+                    if (i1 >= j && i1 < n) a[1][q] = fma(-l1, lj, a[1][q]);
+                }
+            });
         }
-        __syncthreads();
-        if (fail) { kdone = k; break; }
-        const double lkk = L[k + k * LD];
-        for (int i = k + 1 + t; i < n; i += NT) L[i + k * LD] = L[i + k * LD] / lkk;
-        __syncthreads();
-        // trailing lower triangle: rows i = k+1+ (t%64) + 64q, columns j = k+1 + t/64 + 4r
-        const int r0 = k + 1 + (t & 63), cg = t >> 6;
-        for (int j = k + 1 + cg; j < n; j += 4) {
-            const double ljk = L[j + k * LD];
-            for (int i = r0; i < n; i += 64)
-                if (i >= j) L[i + j * LD] = fma(-L[i + k * LD], ljk, L[i + j * LD]);
-        }
-        __syncthreads();
-    }
-    (void)kdone;
-    for (int e = t; e < n * n; e += NT) {
-        const int i = e % n, j = e / n;
-        if (i >= j) A[(size_t)i + (size_t)j * lda] = L[i + j * LD];
-    }
+    });
+    static_for<0, 2>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        static_for<0, 32>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int i = lane + 64 * r, j = w + 4 * q;
+            if (i < n && j < n && i >= j) A[(size_t)i + (size_t)j * lda] = a[r][q];
+        });
+    });
     if (t == 0 && fail) *info = info_base + fail;
 }
 
@@ -60,15 +107,7 @@ namespace cdf {
 hipError_t potrf_diag(hipStream_t s, int n, double *A, int lda, int *info, int info_base) {
     if (n <= 0) return hipSuccess;
     if (n > MAXN) return hipErrorInvalidValue;
-    static bool attr = false;
-    if (!attr) {
-        CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&potrf_diag_kernel),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        MAXN * LD * sizeof(double)));
-        attr = true;
-    }
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(NT), (size_t)n * LD * sizeof(double), s, n, A, lda, info,
-                       info_base);
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(NT), 0, s, n, A, lda, info, info_base);
     return hipGetLastError();
 }
 

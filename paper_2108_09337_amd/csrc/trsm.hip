@@ -5,7 +5,8 @@
 // triangle one row/column at a time; the triangle's column (or row) for
 // each step is read from L2 (the triangle is at most 256 x 256).
 //   left kinds : B (nb x ncols), 32 columns per workgroup, 8 row groups
-//   right kind : B (nrows x nb), 64 rows per workgroup, 4 column groups
+//   right kind : B (nrows x nb), 64 rows per workgroup, one per lane, the
+//                later columns of each block split over 4 waves
 #include "internal.h"
 
 namespace {
@@ -57,31 +58,72 @@ __global__ __launch_bounds__(NT) void trsm_left_kernel(int nb, int ncols, const 
     }
 }
 
-// B (nrows x nb) <- B L^-T with L lower, non-unit: column j of the result is
-// (B(:, j) - sum_{c<j} X(:, c) L(j, c)) / L(j, j), done right-looking.
+// B (nrows x nb) <- B L^-T with L lower, non-unit.  Rows are independent
+// (row r solves L x_r^T = b_r^T by forward substitution).  A workgroup takes
+// 64 rows (lane l of every wave owns row l) and keeps them in LDS
+// (X[c * RNR + l]).  For each block of 16 columns: the triangle's columns
+// J..J+15 (rows J..nb) are staged in LDS; every wave solves the block for
+// its lanes' rows in registers (x_j = x_j / L(j,j), x_i -= x_j L(i,j)), the
+// same values in all waves; then wave w applies the block to the later
+// columns c = w (mod 4), accumulating -x_j L(c,j) over the block's j in
+// order -- the operations and order of column-by-column right-looking
+// substitution.
 template <typename TB>
 __global__ __launch_bounds__(NT) void trsm_rltn_kernel(int nb, int nrows, const double *__restrict__ T,
                                                        int ldt, TB *__restrict__ B, int ldb,
                                                        const int *stop) {
     if (stop != nullptr && *stop != 0) return;
-    extern __shared__ double X[];  // X[c * RNR + r]
-    const int t = threadIdx.x;
-    const int r = t % RNR, cg = t / RNR;  // 4 column groups
-    const int r0 = blockIdx.x * RNR;
-    const bool live = r0 + r < nrows;
-    for (int cc = cg; cc < nb; cc += 4)
-        X[cc * RNR + r] = live ? (double)B[(size_t)(r0 + r) + (size_t)cc * ldb] : 0.0;
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        if (cg == (j & 3)) X[j * RNR + r] = X[j * RNR + r] / T[(size_t)j + (size_t)j * ldt];
-        __syncthreads();
-        const double xj = X[j * RNR + r];
-        for (int cc = j + 1 + ((cg - (j + 1)) & 3); cc < nb; cc += 4)
-            X[cc * RNR + r] = fma(-xj, T[(size_t)cc + (size_t)j * ldt], X[cc * RNR + r]);
-        __syncthreads();
+    constexpr int CB = 16;
+    constexpr int NW = NT / 64;
+    extern __shared__ double X[];         // X[c * RNR + lane]
+    double *P = X + (size_t)nb * RNR;     // P[jj * nb + (c - J)] = T(c, J + jj)
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int r = blockIdx.x * RNR + lane;
+    const bool live = r < nrows;
+    for (int c0 = wave * 8; c0 < nb; c0 += 8 * NW) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = (live && c0 + q < nb) ? (double)B[(size_t)r + (size_t)(c0 + q) * ldb] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (c0 + q < nb) X[(c0 + q) * RNR + lane] = v[q];
+    }
+    for (int J = 0; J < nb; J += CB) {
+        const int jb = nb - J < CB ? nb - J : CB;
+        for (int e = t; e < jb * (nb - J); e += NT) {
+            const int jj = e / (nb - J), c = J + e % (nb - J);
+            P[jj * nb + (c - J)] = T[(size_t)c + (size_t)(J + jj) * ldt];
+        }
+        __syncthreads();  // panel staged; X of this block final
+        double x[CB];
+#pragma unroll
+        for (int jj = 0; jj < CB; ++jj) x[jj] = jj < jb ? X[(J + jj) * RNR + lane] : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < CB; ++jj) {
+            if (jj < jb) {
+                x[jj] = x[jj] / P[jj * nb + jj];
+#pragma unroll
+                for (int ii = jj + 1; ii < CB; ++ii)
+                    if (ii < jb) x[ii] = fma(-x[jj], P[jj * nb + ii], x[ii]);
+            }
+        }
+        __syncthreads();  // every wave has read the block before it is overwritten
+        if (wave == 0) {
+#pragma unroll
+            for (int jj = 0; jj < CB; ++jj)
+                if (jj < jb) X[(J + jj) * RNR + lane] = x[jj];
+        }
+        for (int c = J + jb + wave; c < nb; c += NW) {
+            double acc = X[c * RNR + lane];
+#pragma unroll
+            for (int jj = 0; jj < CB; ++jj)
+                if (jj < jb) acc = fma(-x[jj], P[jj * nb + (c - J)], acc);
+            X[c * RNR + lane] = acc;
+        }
+        __syncthreads();  // later columns updated; P may be restaged
     }
     if (live)
-        for (int cc = cg; cc < nb; cc += 4) B[(size_t)(r0 + r) + (size_t)cc * ldb] = (TB)X[cc * RNR + r];
+        for (int c = wave; c < nb; c += NW) B[(size_t)r + (size_t)c * ldb] = (TB)X[c * RNR + lane];
 }
 
 template <int KIND, typename TB>
@@ -104,11 +146,11 @@ template <typename TB>
 hipError_t launch_right(hipStream_t s, int nb, int nrows, const double *T, int ldt, TB *B, int ldb,
                         const int *stop) {
     static bool attr = false;
-    const size_t lds = (size_t)nb * RNR * sizeof(double);
+    const size_t lds = (size_t)nb * (RNR + 16) * sizeof(double);  // row block + staged triangle panel
     if (!attr) {
         CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&trsm_rltn_kernel<TB>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        MAXNB * RNR * sizeof(double)));
+                                        MAXNB * (RNR + 16) * sizeof(double)));
         attr = true;
     }
     hipLaunchKernelGGL((trsm_rltn_kernel<TB>), dim3((nrows + RNR - 1) / RNR), dim3(NT), lds, s, nb, nrows, T, ldt,

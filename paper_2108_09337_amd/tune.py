@@ -13,7 +13,7 @@ Search spaces (the parameters the paper tunes are the block size v and the
 replication depth, Sec. 7.2 and Sec. 8; on one GPU they become the panel
 width, the leaf shape and the batched launch shape):
   getrf        lu_nb in {256, 384, 512} x lu_leaf_rows in {1, 2}
-  potrf        chol_nb in {64, 96, 128}
+  potrf        chol_nb in {128, 256, 384, 512}
   mixed_getrf  mixed_nb in {256, 384, 512} (BF16 update)
   vbatch       vbatch_nb in {0 (32 where it fits), 16} x vbatch_wg_per_cu in {1, 2}
 """
@@ -36,7 +36,7 @@ DEFAULT_CACHE = os.path.join(_HERE, "tune_cache.json")
 
 SPACES = {
     "getrf": {"lu_nb": [256, 384, 512], "lu_leaf_rows": [1, 2]},
-    "potrf": {"chol_nb": [64, 96, 128]},
+    "potrf": {"chol_nb": [128, 256, 384, 512]},
     "mixed_getrf": {"mixed_nb": [256, 384, 512]},
     "vbatch": {"vbatch_nb": [0, 16], "vbatch_wg_per_cu": [1, 2]},
 }
@@ -108,7 +108,8 @@ def _time(fn, reps):
 def tune_dense(op: str, n: int, reps: int = 2, log=print) -> dict:
     import workloads
     h = cdf.handle()
-    a0 = cdf.to_device(workloads.lu_uniform(n) if op in ("getrf", "mixed_getrf") else workloads.spd_bbt(n))
+    # inputs drawn on the GPU (same distributions as the host generators)
+    a0 = workloads.lu_uniform_torch(n) if op in ("getrf", "mixed_getrf") else workloads.spd_bbt_torch(n)
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
     ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
     W = cdf.cm_empty(n, n, torch.float32) if op == "mixed_getrf" else None

@@ -143,7 +143,7 @@ def test_getrs(oracle_mod, n, nrhs):
 
 
 @pytest.mark.parametrize("n,nb", [(1, 0), (2, 0), (5, 0), (64, 0), (127, 0), (128, 0), (129, 0), (400, 0),
-                                  (1000, 0), (1300, 64), (700, 96)])
+                                  (1000, 0), (1300, 64), (700, 96), (1500, 256), (900, 384), (1300, 512)])
 def test_chol_parity_random(oracle_mod, n, nb):
     a = workloads.spd_bbt(n, seed=2000 + n)
     l_or, info_or = oracle_mod.dpotrf(a)
@@ -156,12 +156,13 @@ def test_chol_parity_random(oracle_mod, n, nb):
     assert oracle_mod.chol_backward_error(a, l) <= 10.0
 
 
-@pytest.mark.parametrize("n,bad", [(300, 0), (300, 150), (300, 299), (260, 128)])
-def test_chol_not_spd_info(oracle_mod, n, bad):
+@pytest.mark.parametrize("n,bad,nb", [(300, 0, 0), (300, 150, 0), (300, 299, 0), (260, 128, 0), (600, 200, 256),
+                                      (700, 450, 512)])
+def test_chol_not_spd_info(oracle_mod, n, bad, nb):
     a = workloads.spd_bbt(n, seed=3)
     a[bad, bad] = -1.0
     _, info_or = oracle_mod.dpotrf(a)
-    l, info = _chol_gpu(a)
+    l, info = _chol_gpu(a, chol_nb=nb)
     assert info == info_or
     # columns of finished blocks before the failing one agree with the oracle
     lo, _ = oracle_mod.dpotrf(a, ksteps=(bad // 128) * 128)
