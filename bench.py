@@ -54,6 +54,8 @@ def parse():
                    help="extra sizes measured once each (LU and Cholesky), reported in detail")
     p.add_argument("--mixed-n", type=int, default=65536)
     p.add_argument("--batch", type=int, default=4096)
+    p.add_argument("--kernel-n", type=int, default=65536,
+                   help="points of the exponential-kernel Cholesky solve (0 = skip)")
     p.add_argument("--cpu-steps", type=int, default=32, help="elimination steps in the oracle sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-chol", action="store_true")
@@ -261,6 +263,46 @@ def mixed_section(args, torch, cdf, workloads, h, tuned):
         for k in group:
             h.set_param(k, 0)
     del A, X
+    torch.cuda.empty_cache()
+    if args.kernel_n:
+        res["kernel_chol"] = kernel_chol_section(args, torch, cdf, workloads, h, tuned)
+    return res
+
+
+def kernel_chol_section(args, torch, cdf, workloads, h, tuned):
+    """FP8 E4M3 (per-tile scaled) Cholesky update + FP64 refinement on the
+    exponential-kernel SPD matrix (n points uniform in the unit cube, length
+    0.1, nugget 1e-2), 64 FP64 right-hand sides, against the FP64 path."""
+    n, nrhs = args.kernel_n, 64
+    log(f"mixed: exponential-kernel matrix n={n}, nrhs={nrhs}")
+    A = workloads.exp_kernel_matrix_torch(workloads.kernel_points(n))
+    B = workloads.rhs_uniform_torch(n, nrhs, seed=workloads.SEED_POINTS_RHS)
+    X = torch.empty_like(B)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    res = {"n": n, "nrhs": nrhs, "params": {"fp64": tuned(h, "potrf", n)}}
+    for prec in ("fp64", "e4m3", "bf16"):
+        try:
+            cdf.dposv_mixed(prec, A, B, X, info, max_iter=30, h=h)  # warm-up
+        except cdf.CdfError:
+            pass
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            r = cdf.dposv_mixed(prec, A, B, X, info, max_iter=30, h=h)
+        except cdf.CdfError as e:
+            r = {"status": e.status, "converged": False, "iters": None, "scaled_resid": float("nan")}
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res[prec] = {"seconds": round(t, 4), "iters": r["iters"], "scaled_resid": r["scaled_resid"],
+                     "converged": r["converged"], "status": r["status"], "info": int(info.item())}
+        log(f"kernel matrix {prec}: {t:.3f} s, converged {r['converged']}, iters {r['iters']}, "
+            f"resid {r['scaled_resid']}, info {int(info.item())}")
+    for prec in ("e4m3", "bf16"):
+        if res[prec]["converged"]:
+            res[prec]["speedup_vs_fp64"] = round(res["fp64"]["seconds"] / res[prec]["seconds"], 3)
+    for k in res["params"]["fp64"]:
+        h.set_param(k, 0)
+    del A, B, X
     torch.cuda.empty_cache()
     return res
 

@@ -24,9 +24,9 @@ inline int lu_nb(cdf_handle_t h, int n) {
     return v > 0 ? v : (n >= 16384 ? 512 : 256);
 }
 
-inline int chol_nb(cdf_handle_t h) {
+inline int chol_nb(cdf_handle_t h, int n) {
     const int v = h->params[CDF_PARAM_CHOL_NB];
-    return v > 0 ? v : 128;
+    return v > 0 ? v : (n >= 16384 ? 512 : 128);
 }
 
 // LU workspace: the leaf's exchange area, the current panel's pivots (<= 512)
@@ -169,7 +169,7 @@ hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
     CDF_HIP_RET(cdf::ensure_aux(h));
     hipStream_t s1 = h->aux;
     CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
-    const int nb = chol_nb(h);
+    const int nb = chol_nb(h, n);
     // block column [k, k+kb): right-looking over sub-blocks of at most 128
     // columns (the diagonal-block kernel's limit); each sub-block updates
     // only the rest of this block column.

@@ -3,12 +3,16 @@
 //
 //   C = beta * C + alpha * op(A) * op(B)
 //
-// Output-stationary tiling: a 128 x 128 tile of C per workgroup (4 waves in a
-// 2 x 2 arrangement, 64 x 64 per wave as 4 x 4 blocks of the 16x16x4 FP64
-// MFMA), streamed over k in steps of 16 through LDS with register
-// prefetch of the next step.  This is the tile-streaming schedule the I/O
-// bound of Sec. 6.1 is attained by (each loaded element of op(A) / op(B)
-// feeds 128 multiply-adds).
+// Output-stationary tiling: a square tile of C per workgroup (4 waves in a
+// 2 x 2 arrangement, each wave W x W blocks of the 16x16x4 FP64 MFMA),
+// streamed over k in steps of 16 through LDS with register prefetch of the
+// next step.  This is the tile-streaming schedule the I/O bound of Sec. 6.1
+// is attained by (each element of op(A) / op(B) brought into LDS feeds one
+// multiply-add per tile column / row).  A single wave per SIMD does not keep
+// the FP64 matrix pipe busy, so the LU's kernels use 64 x 64 tiles (about
+// 100 registers, 17 KB of LDS: four or more workgroups per CU, some issuing
+// MFMAs while others sit at a barrier or in their epilogue); the Cholesky's
+// (B transposed, lower-triangle SYRK) run faster on 128 x 128 tiles.
 //
 // Workgroups are remapped so that each XCD (hardware assigns workgroup b to
 // XCD b % 8) gets a contiguous run of tiles, and runs are walked in groups of
@@ -22,10 +26,19 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 128;
-constexpr int BN = 128;
 constexpr int BK = 16;
 constexpr int NT = 256;
+
+// Tile shape per kernel: W x W blocks of 16x16 per wave, 2 x 2 waves, sized
+// for OCC workgroups per CU.  The LU's updates (op(B) = B) run best on
+// 64 x 64 tiles, the Cholesky's (op(B) = B^T, including the lower-triangle
+// SYRK) on 128 x 128 tiles (measured).
+template <int TB>
+struct Shape {
+    static constexpr int W = TB == 1 ? 4 : 2;
+    static constexpr int B = 32 * W;
+    static constexpr int OCC = TB == 1 ? 2 : 4;
+};
 constexpr int GROUP_M = 8;
 
 // LDS tile of R (rows of the op-operand along M or N) x BK.
@@ -94,11 +107,12 @@ __device__ inline void lower_tile(int L, int &tm, int &tn) {
 }
 
 template <int TA, int TB, bool LOWER>
-__global__ __launch_bounds__(NT, 2) void dgemm_kernel(int m, int n, int k, double alpha,
+__global__ __launch_bounds__(NT, Shape<TB>::OCC) void dgemm_kernel(int m, int n, int k, double alpha,
                                                       const double *__restrict__ A, int lda,
                                                       const double *__restrict__ B, int ldb,
                                                       double beta, double *__restrict__ C, int ldc,
                                                       int tiles_m, int tiles_n, const int *stop) {
+    constexpr int WI = Shape<TB>::W, WJ = Shape<TB>::W, BM = Shape<TB>::B, BN = Shape<TB>::B;
     if (stop != nullptr && *stop != 0) return;
     constexpr bool A_RC = (TA == 0);  // op(A)(i, kk): A[i + kk*lda] when not transposed
     constexpr bool B_RC = (TB == 1);  // op(B)(kk, j) viewed as (j, kk): B[j + kk*ldb] when transposed
@@ -118,11 +132,11 @@ __global__ __launch_bounds__(NT, 2) void dgemm_kernel(int m, int n, int k, doubl
     const int wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
 
-    v4d acc[4][4];
+    v4d acc[WI][WJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < WJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
     double ra[TA_::PER_THREAD];
     double rb[TB_::PER_THREAD];
@@ -145,15 +159,15 @@ __global__ __launch_bounds__(NT, 2) void dgemm_kernel(int m, int n, int k, doubl
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             const int kk = ks * 4 + lk;
-            double af[4], bf[4];
+            double af[WI], bf[WJ];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) af[i] = As[TA_::idx(wm * 64 + i * 16 + lrow, kk)];
+            for (int i = 0; i < WI; ++i) af[i] = As[TA_::idx(wm * (16 * WI) + i * 16 + lrow, kk)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bf[j] = Bs[TB_::idx(wn * 64 + j * 16 + lrow, kk)];
+            for (int j = 0; j < WJ; ++j) bf[j] = Bs[TB_::idx(wn * (16 * WJ) + j * 16 + lrow, kk)];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < WI; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < WJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
@@ -167,13 +181,13 @@ __global__ __launch_bounds__(NT, 2) void dgemm_kernel(int m, int n, int k, doubl
     // 16x16 output block layout of the FP64 MFMA: register v of a lane holds
     // row 4*v + lane/16, column lane%16.
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = n0 + wn * 64 + j * 16 + lrow;
+        for (int j = 0; j < WJ; ++j) {
+            const int col = n0 + wn * (16 * WJ) + j * 16 + lrow;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm * 64 + i * 16 + v * 4 + lk;
+                const int row = m0 + wm * (16 * WI) + i * 16 + v * 4 + lk;
                 if (row < m && col < n && (!LOWER || row >= col)) {
                     double *p = C + (size_t)row + (size_t)col * ldc;
                     const double c0 = beta == 0.0 ? 0.0 : beta * *p;
@@ -186,6 +200,7 @@ __global__ __launch_bounds__(NT, 2) void dgemm_kernel(int m, int n, int k, doubl
 template <int TA, int TB, bool LOWER>
 hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double *A, int lda,
                   const double *B, int ldb, double beta, double *C, int ldc, const int *stop) {
+    constexpr int BM = Shape<TB>::B, BN = Shape<TB>::B;
     const int tiles_m = (m + BM - 1) / BM;
     const int tiles_n = (n + BN - 1) / BN;
     long long nwg = LOWER ? (long long)tiles_m * (tiles_m + 1) / 2 : (long long)tiles_m * tiles_n;

@@ -143,6 +143,23 @@ def spd_bbt_torch(n: int, seed: int = SEED_MATRIX, device: str = "cuda"):
     return s.t()
 
 
+def exp_kernel_matrix_torch(x: np.ndarray, length: float = 0.1, nugget: float = 1e-2, device: str = "cuda"):
+    """exp_kernel_matrix() evaluated on the GPU (same points, same formula:
+    differences, squares, sum, sqrt, exp), as a column-major view."""
+    import torch
+    n = x.shape[0]
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(device=device, dtype=torch.float64)
+    k = torch.empty((n, n), dtype=torch.float64, device=device)  # k[j, i] = entry (i, j); K is symmetric
+    step = 1024
+    for j0 in range(0, n, step):
+        j1 = min(n, j0 + step)
+        d = xt[j0:j1, None, :] - xt[None, :, :]
+        k[j0:j1] = torch.exp(-torch.sqrt((d * d).sum(dim=2)) / length)
+        del d
+    k.diagonal().add_(nugget)
+    return k.t()
+
+
 def rhs_uniform_torch(n: int, nrhs: int = 1, seed: int = SEED_RHS, device: str = "cuda"):
     import torch
     g = torch.Generator(device=device)
