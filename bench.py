@@ -19,7 +19,7 @@ Also reported (``detail``):
     graph replay, FP64 and FP32, aggregate TFLOP/s.
 
 ``roofline``: the FP64 Schur-complement update GEMM (dgemm_kernel<0,0,false>,
-the dominant kernel): every launch of it inside the timed LU steps is
+the dominant kernel): every launch of it inside the first timed LU step is
 bracketed by HIP events on the stream it runs on (the library's kernel-timing
 hook); achieved = algorithmic flops per launch / average launch duration.
 ``traffic``: calibrated HBM bytes per launch from the committed rocprofv3 PMC
@@ -62,6 +62,10 @@ def parse():
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--no-tune-cache", action="store_true", help="ignore the autotuner cache")
+    p.add_argument("--lu-leaf-rows", type=int, default=0, choices=[0, 1, 2],
+                   help="force the LU panel leaf's rows per thread (counter-collection runs: 2 halves its grid)")
+    p.add_argument("--no-kernel-timing", action="store_true",
+                   help="skip the per-launch GEMM timing events (counter-collection runs)")
     p.add_argument("--calibrate-bytes", type=int, default=0,
                    help="first run a plain elementwise kernel reading and writing this many bytes (PMC scale)")
     return p.parse_args()
@@ -135,6 +139,9 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
     info_ch = torch.zeros(1, dtype=torch.int32, device="cuda")
     lu_params = tuned(h, "getrf", n)
     ch_params = tuned(h, "potrf", n)
+    if args.lu_leaf_rows:
+        h.set_param("lu_leaf_rows", args.lu_leaf_rows)
+        lu_params = dict(lu_params, lu_leaf_rows=args.lu_leaf_rows)
     torch.cuda.synchronize()
 
     def restore():
@@ -159,15 +166,19 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
     evs = [events(torch, 3) for _ in range(K)]
     log(f"timing {K} steps")
     wall = 0.0
-    cdf.profile_begin(h)  # HIP events around every update-GEMM launch, on the stream it runs on
+    prof_nn = prof_syrk = {"launches": 0, "total_ms": 0.0, "flops": 0.0}
     for i in range(K):
         restore()
+        timed = i == 0 and not args.no_kernel_timing
+        if timed:  # HIP events around every update-GEMM launch of the first timed step, on its stream
+            cdf.profile_begin(h)
         t0 = time.perf_counter()
         step(evs[i])
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
-    prof_nn = cdf.profile_end("nn", h)
-    prof_syrk = cdf.profile_end("syrk", h)
+        if timed:
+            prof_nn = cdf.profile_end("nn", h)
+            prof_syrk = cdf.profile_end("syrk", h)
     assert int(info_lu.item()) == 0 and (S is None or int(info_ch.item()) == 0)
     ms = wall * 1e3 / K
     t_lu = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e-3
@@ -182,9 +193,10 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
     launches = max(prof_nn["launches"], 1)
     avg = prof_nn["total_ms"] * 1e-3 / launches
     fpl = prof_nn["flops"] / launches
-    achieved = fpl / avg / 1e12 if avg > 0 else 0.0
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK, 4), "traffic": traffic_per_launch(n, lu_nb),
+    achieved = fpl / avg / 1e12 if avg > 0 else None
+    roofline = {"bound": "mfma", "achieved": None if achieved is None else round(achieved, 3), "peak": FP64_PEAK,
+                "unit": "TFLOP/s", "frac": None if achieved is None else round(achieved / FP64_PEAK, 4),
+                "traffic": traffic_per_launch(n, lu_nb),
                 "kernel": "dgemm_kernel<0,0,false> (FP64 update C -= A B)",
                 "launches": prof_nn["launches"], "avg_launch_us": round(avg * 1e6, 2),
                 "flops_per_launch": round(fpl, 1),
