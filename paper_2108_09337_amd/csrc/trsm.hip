@@ -189,49 +189,108 @@ __global__ __launch_bounds__(256) void trsv_diag_kernel(int kb, int nrhs, const 
     if (lane < kb) B[(size_t)lane + (size_t)c * ldb] = x;
 }
 
-// Y(rows x nrhs) -= T(rows x kb) X(kb x nrhs); one row per thread.
-__global__ __launch_bounds__(256) void gemv_n_kernel(int rows, int kb, int nrhs, const double *__restrict__ T, int ldt,
-                                                     const double *__restrict__ X, int ldx, double *__restrict__ Y,
-                                                     int ldy) {
+// One step of a blocked triangular solve with few right-hand sides (<= 4):
+// the block x[k, k+kb) is final.  Every workgroup subtracts its
+// contribution from 64 of the remaining rows [rbeg, rend) -- forward: chunk
+// b is rows rbeg + 64b.., backward: rows rend - 64(b+1).. -- with the block's
+// columns split over the 4 waves and the partial sums added in wave order;
+// then workgroup 0, whose rows are exactly the next diagonal block
+// [nk, nk + nkb), solves that block (one wave per right-hand side, lane =
+// row), so a step costs one launch.
+template <int KIND>
+__global__ __launch_bounds__(256) void trsv_step_kernel(int nrhs, const double *__restrict__ T, int ldt,
+                                                        double *__restrict__ B, int ldb, int k, int kb, int rbeg,
+                                                        int rend, int nk, int nkb) {
+    constexpr bool forward = (KIND == cdf::TRSM_LLNU || KIND == cdf::TRSM_LLNN);
     __shared__ double xs[4][64];
-    const int t = threadIdx.x;
-    if (t < kb * nrhs) xs[t / kb][t % kb] = X[(size_t)(t % kb) + (size_t)(t / kb) * ldx];
+    __shared__ double red[4][4][64];
+    __shared__ double ynew[4][64];
+    __shared__ double Ts[64 * 65];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t < kb * nrhs) xs[t / kb][t % kb] = B[(size_t)(k + t % kb) + (size_t)(t / kb) * ldb];
+    const bool diag = blockIdx.x == 0 && nkb > 0;
+    if (diag)
+        for (int e = t; e < nkb * nkb; e += 256) {
+            const int i = e % nkb, j = e / nkb;
+            Ts[i + j * 65] = T[(size_t)(nk + i) + (size_t)(nk + j) * ldt];
+        }
     __syncthreads();
-    const int r = blockIdx.x * 256 + t;
-    if (r >= rows) return;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = 0; j < kb; ++j) {
-        const double tv = T[(size_t)r + (size_t)j * ldt];
+    const int r0 = forward ? rbeg + 64 * (int)blockIdx.x : rend - 64 * ((int)blockIdx.x + 1);
+    if (KIND != cdf::TRSM_LLTN) {
+        // lanes = rows: T(r, k + jj) is contiguous over the lanes
+        const int r = r0 + lane;
+        const bool live = r >= rbeg && r < rend;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        const int j0 = 16 * wave, j1 = min(j0 + 16, kb);
+        for (int jj = j0; jj < j1; ++jj) {
+            const double tv = live ? T[(size_t)r + (size_t)(k + jj) * ldt] : 0.0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (c < nrhs) acc[c] = fma(tv, xs[c][j], acc[c]);
+            for (int c = 0; c < 4; ++c)
+                if (c < nrhs) acc[c] = fma(tv, xs[c][jj], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) red[wave][c][lane] = acc[c];
+    } else {
+        // (L^T)(r, k + j) = L(k + j, r): lanes = j (contiguous), wave w takes rows r0 + 16w .. + 16
+        for (int rr = 0; rr < 16; ++rr) {
+            const int r = r0 + 16 * wave + rr;
+            const bool live = r >= rbeg && r < rend && lane < kb;
+            const double lv = live ? T[(size_t)(k + lane) + (size_t)r * ldt] : 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double p = c < nrhs ? lv * xs[c][lane < kb ? lane : 0] : 0.0;
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) p += __shfl_xor(p, off);
+                if (lane == 0) red[0][c][16 * wave + rr] = p;
+            }
+        }
     }
+    __syncthreads();
+    if (wave == 0) {
+        const int r = r0 + lane;
+        const bool live = r >= rbeg && r < rend;
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-        if (c < nrhs) Y[(size_t)r + (size_t)c * ldy] -= acc[c];
+        for (int c = 0; c < 4; ++c) {
+            if (c >= nrhs) continue;
+            const double sum = KIND == cdf::TRSM_LLTN
+                                   ? red[0][c][lane]
+                                   : ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
+            double y = live ? B[(size_t)r + (size_t)c * ldb] - sum : 0.0;
+            ynew[c][lane] = y;
+            if (live && !diag) B[(size_t)r + (size_t)c * ldb] = y;
+        }
+    }
+    if (!diag) return;
+    __syncthreads();
+    // next diagonal block: rows [nk, nk + nkb) are this workgroup's rows
+    if (wave >= nrhs) return;
+    const int c = wave;
+    const int off = nk - r0;  // 0 forward; 64 - nkb never occurs (backward blocks are full)
+    double x = lane < nkb ? ynew[c][lane + off] : 0.0;
+    if (forward) {
+        for (int j = 0; j < nkb; ++j) {
+            if (KIND == cdf::TRSM_LLNN && lane == j) x = x / Ts[j + j * 65];
+            const double xj = __shfl(x, j);
+            if (lane > j && lane < nkb) x = fma(-Ts[lane + j * 65], xj, x);
+        }
+    } else {
+        for (int j = nkb - 1; j >= 0; --j) {
+            if (lane == j) x = x / Ts[j + j * 65];
+            const double xj = __shfl(x, j);
+            if (lane < j) x = fma(KIND == cdf::TRSM_LUNN ? -Ts[lane + j * 65] : -Ts[j + lane * 65], xj, x);
+        }
+    }
+    if (lane < nkb) B[(size_t)(nk + lane) + (size_t)c * ldb] = x;
 }
 
-// Y(cols x nrhs) -= T(kb x cols)^T X(kb x nrhs); one output row (a column of T) per thread.
-__global__ __launch_bounds__(256) void gemv_t_kernel(int cols, int kb, int nrhs, const double *__restrict__ T, int ldt,
-                                                     const double *__restrict__ X, int ldx, double *__restrict__ Y,
-                                                     int ldy) {
-    __shared__ double xs[4][64];
-    const int t = threadIdx.x;
-    if (t < kb * nrhs) xs[t / kb][t % kb] = X[(size_t)(t % kb) + (size_t)(t / kb) * ldx];
-    __syncthreads();
-    const int r = blockIdx.x * 256 + t;
-    if (r >= cols) return;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const double *col = T + (size_t)r * ldt;
-    for (int i = 0; i < kb; ++i) {
-        const double tv = col[i];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (c < nrhs) acc[c] = fma(tv, xs[c][i], acc[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-        if (c < nrhs) Y[(size_t)r + (size_t)c * ldy] -= acc[c];
+template <int KIND>
+hipError_t launch_step(hipStream_t s, int nrhs, const double *T, int ldt, double *B, int ldb, int k, int kb, int rbeg,
+                       int rend, int nk, int nkb) {
+    const int rows = rend - rbeg;
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL((trsv_step_kernel<KIND>), dim3((rows + 63) / 64), dim3(256), 0, s, nrhs, T, ldt, B, ldb, k, kb,
+                       rbeg, rend, nk, nkb);
+    return hipGetLastError();
 }
 
 template <int KIND>
@@ -259,32 +318,27 @@ hipError_t trsv_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const do
             default: return hipErrorInvalidValue;
         }
     };
+    auto step = [&](int k, int kb, int rbeg, int rend, int nk, int nkb) -> hipError_t {
+        switch (kind) {
+            case TRSM_LLNU: return launch_step<TRSM_LLNU>(s, ncols, T, ldt, B, ldb, k, kb, rbeg, rend, nk, nkb);
+            case TRSM_LLNN: return launch_step<TRSM_LLNN>(s, ncols, T, ldt, B, ldb, k, kb, rbeg, rend, nk, nkb);
+            case TRSM_LUNN: return launch_step<TRSM_LUNN>(s, ncols, T, ldt, B, ldb, k, kb, rbeg, rend, nk, nkb);
+            case TRSM_LLTN: return launch_step<TRSM_LLTN>(s, ncols, T, ldt, B, ldb, k, kb, rbeg, rend, nk, nkb);
+            default: return hipErrorInvalidValue;
+        }
+    };
     if (kind == TRSM_LLNU || kind == TRSM_LLNN) {
+        CDF_HIP_RET(diag(0, min(BS, n)));
         for (int k = 0; k < n; k += BS) {
-            const int kb = min(BS, n - k), rest = n - k - kb;
-            CDF_HIP_RET(diag(k, kb));
-            if (rest > 0) {
-                hipLaunchKernelGGL(gemv_n_kernel, dim3((rest + 255) / 256), dim3(256), 0, s, rest, kb, ncols,
-                                   T + (k + kb) + (size_t)k * ldt, ldt, B + k, ldb, B + k + kb, ldb);
-                CDF_HIP_RET(hipGetLastError());
-            }
+            const int kb = min(BS, n - k), nk = k + kb;
+            if (nk >= n) break;
+            CDF_HIP_RET(step(k, kb, nk, n, nk, min(BS, n - nk)));
         }
         return hipSuccess;
     }
     const int last = ((n - 1) / BS) * BS;
-    for (int k = last; k >= 0; k -= BS) {
-        const int kb = min(BS, n - k);
-        CDF_HIP_RET(diag(k, kb));
-        if (k > 0) {
-            if (kind == TRSM_LUNN)
-                hipLaunchKernelGGL(gemv_n_kernel, dim3((k + 255) / 256), dim3(256), 0, s, k, kb, ncols,
-                                   T + (size_t)k * ldt, ldt, B + k, ldb, B, ldb);
-            else
-                hipLaunchKernelGGL(gemv_t_kernel, dim3((k + 255) / 256), dim3(256), 0, s, k, kb, ncols, T + k, ldt,
-                                   B + k, ldb, B, ldb);
-            CDF_HIP_RET(hipGetLastError());
-        }
-    }
+    CDF_HIP_RET(diag(last, n - last));
+    for (int k = last; k > 0; k -= BS) CDF_HIP_RET(step(k, min(BS, n - k), 0, k, k - BS, BS));
     return hipSuccess;
 }
 
