@@ -41,17 +41,14 @@ namespace cdf {
 // Recursive panel factorization of columns [c0, c0 + w) over rows [c0, m) of
 // the m x ncols region A: factor the left half, form its U12 and update the
 // right half, factor the right half.  Leaves (<= 32 columns) apply their
-// interchanges to every other column of the region, so the region stays
-// consistently permuted.  Pivots are written relative to the region's row 0;
+// interchanges to every other column of the region inside the leaf kernel,
+// so the region stays consistently permuted.  Pivots are written relative to the region's row 0;
 // info values are offset by info_off.
 hipError_t lu_panel(cdf_handle_t h, hipStream_t s, int m, int ncols, double *A, int lda, int *ipiv, int *info,
                     int c0, int w, int info_off) {
     if (w <= 32) {
-        CDF_HIP_RET(lu_leaf(h, s, m - c0, w, A + c0 + (size_t)c0 * lda, lda, ipiv + c0, c0, info, info_off + c0,
-                            h->params[CDF_PARAM_LU_LEAF_ROWS]));
-        CDF_HIP_RET(laswp(s, 0, c0, A, lda, ipiv, c0, c0 + w, m));
-        CDF_HIP_RET(laswp(s, c0 + w, ncols, A, lda, ipiv, c0, c0 + w, m));
-        return hipSuccess;
+        return lu_leaf(h, s, m - c0, w, A + c0 + (size_t)c0 * lda, lda, ipiv + c0, c0, info, info_off + c0,
+                       h->params[CDF_PARAM_LU_LEAF_ROWS], A, m, ncols, c0);
     }
     const int n1 = ((w / 2 + 31) / 32) * 32;
     const int n2 = w - n1;

@@ -62,8 +62,12 @@ hipError_t prof_collect(int kind, long long *launches, double *total_ms, double 
 // LU panel leaf: factor the m x n (n <= 32) column block at A with partial
 // pivoting; writes absolute 1-based pivots ipiv[0..n) (row offset `row0`
 // added), first zero pivot into *info (as info_base + j + 1) if *info == 0.
+// The leaf also applies its interchanges to the other columns [0, c0) and
+// [c0 + n, region_cols) of the region (region_rows rows) it belongs to; A is
+// region + c0 + c0 * lda.
 hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, int lda, int *ipiv,
-                   int row0, int *info, int info_base, int rows_per_thread);
+                   int row0, int *info, int info_base, int rows_per_thread, double *region, int region_rows,
+                   int region_cols, int c0);
 
 // Recursive LU panel of columns [c0, c0+w) of the m x ncols region A (rows
 // [c0, m)) on stream s; interchanges are applied to all other columns of the

@@ -31,6 +31,8 @@ namespace {
 constexpr int LW = 32;   // leaf width (columns)
 constexpr int LT = 256;  // threads per workgroup
 constexpr int GMAX = 256;
+constexpr int MAXSW = 64;          // interchanges per pair map
+constexpr int MAXPAIRS = 2 * MAXSW;
 typedef unsigned long long u64;
 
 // Workspace layout of the exchange (at the head of the handle's workspace).
@@ -54,18 +56,68 @@ __device__ inline u64 get_tag(const u64 *p) {
     return __hip_atomic_load(const_cast<u64 *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Builds the (dst, src) row pairs equivalent to applying the interchanges
+// ipiv[k1 - off .. k2 - off) (rows k1..k2-1 swapped with absolute, 1-based
+// rows, k2 - k1 <= 64) in order:
+//   new row dst[q] = old row src[q].
+// Executed by one full wave: the simulated positions (at most 128 distinct
+// rows) live in registers, two per lane, and are searched with ballots.
+// Returns the pair count (wave-uniform); dst/src are written to LDS.
+__device__ int build_pairs_wave(const int *__restrict__ ipiv, int k1, int k2, int nrows, int *dst, int *src,
+                                 int off = 0) {
+    const int lane = threadIdx.x & 63;
+    int myp = (k1 + lane < k2) ? ipiv[k1 + lane - off] - 1 : -1;
+    if (myp < k1 + lane || myp >= nrows) myp = k1 + lane;  // out-of-range interchange: ignored
+    int pos0 = -1, cont0 = -1, pos1 = -1, cont1 = -1;
+    int np = 0;
+    for (int k = k1; k < k2; ++k) {
+        const int p = __shfl(myp, k - k1);
+        if (p == k) continue;
+        unsigned long long b0 = __ballot(pos0 == k), b1 = __ballot(pos1 == k);
+        int ik = b0 ? __builtin_ctzll(b0) : (b1 ? 64 + __builtin_ctzll(b1) : -1);
+        b0 = __ballot(pos0 == p);
+        b1 = __ballot(pos1 == p);
+        int ip = b0 ? __builtin_ctzll(b0) : (b1 ? 64 + __builtin_ctzll(b1) : -1);
+        if (ik < 0) {
+            if (lane == (np & 63)) { if (np < 64) { pos0 = k; cont0 = k; } else { pos1 = k; cont1 = k; } }
+            ik = np++;
+        }
+        if (ip < 0) {
+            if (lane == (np & 63)) { if (np < 64) { pos0 = p; cont0 = p; } else { pos1 = p; cont1 = p; } }
+            ip = np++;
+        }
+        const int ck = ik < 64 ? __shfl(cont0, ik) : __shfl(cont1, ik - 64);
+        const int cp = ip < 64 ? __shfl(cont0, ip) : __shfl(cont1, ip - 64);
+        if (lane == (ik & 63)) { if (ik < 64) cont0 = cp; else cont1 = cp; }
+        if (lane == (ip & 63)) { if (ip < 64) cont0 = ck; else cont1 = ck; }
+    }
+    // compaction of the moved positions
+    const bool m0 = pos0 >= 0 && cont0 != pos0;
+    const bool m1 = pos1 >= 0 && cont1 != pos1;
+    const unsigned long long bm0 = __ballot(m0), bm1 = __ballot(m1);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int c0 = __popcll(bm0);
+    if (m0) { const int q = __popcll(bm0 & below); dst[q] = pos0; src[q] = cont0; }
+    if (m1) { const int q = c0 + __popcll(bm1 & below); dst[q] = pos1; src[q] = cont1; }
+    return c0 + __popcll(bm1);
+}
+
 template <int R>
 __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__restrict__ A, int lda,
                                                      int *__restrict__ ipiv, int row0,
                                                      int *__restrict__ info, int info_base,
                                                      u64 *__restrict__ tags, double *__restrict__ rows,
-                                                     unsigned epoch0) {
+                                                     unsigned epoch0, double *__restrict__ Reg, int rm,
+                                                     int rcols, int rc0) {
     constexpr int RT = LT * R;  // rows per workgroup
     extern __shared__ double X[];  // X[c * RT + local row]
     __shared__ double prow[LW];
     __shared__ double oldj[LW];
     __shared__ double wv[LT / 64], xv[LT / 64];
     __shared__ int wi[LT / 64], xi[LT / 64], xw[LT / 64];
+    __shared__ int spiv[LW];                    // region row (1-based) swapped with row rc0 + j
+    __shared__ int pdst[MAXPAIRS], psrc[MAXPAIRS];
+    __shared__ int s_np;
 
     const int G = gridDim.x;
     const int g = blockIdx.x;
@@ -174,6 +226,7 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
         if (p == INT_MAX) p = j;  // no ordered candidate (NaN column): no interchange
         __syncthreads();
         const double piv = prow[j];
+        if (t == 0) spiv[j] = rc0 + p + 1;
         if (g == 0 && t == 0) {
             ipiv[j] = row0 + p + 1;
             if (piv == 0.0 && *info == 0) *info = info_base + j + 1;
@@ -208,56 +261,33 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
             const int r = rbase + s * LT + t;
             if (r < m) A[(size_t)r + (size_t)c * lda] = X[c * RT + s * LT + t];
         }
+
+    // the block's interchanges on the region's other columns [0, rc0) and
+    // [rc0 + n, rcols): pairs from the pivots (same in every workgroup), then
+    // each wave moves one column at a time (all rows read before any write)
+    if (rcols <= n) return;
+    __syncthreads();
+    if (wave == 0) {
+        const int np = build_pairs_wave(spiv, rc0, rc0 + n, rm, pdst, psrc, rc0);
+        if (lane == 0) s_np = np;
+    }
+    __syncthreads();
+    const int np = s_np;
+    if (np == 0) return;
+    const int others = rcols - n;
+    for (int q = g * (LT / 64) + wave; q < others; q += G * (LT / 64)) {
+        const int c = q < rc0 ? q : q + n;
+        double v0 = 0.0, v1 = 0.0;
+        if (lane < np) v0 = Reg[(size_t)psrc[lane] + (size_t)c * lda];
+        if (lane + 64 < np) v1 = Reg[(size_t)psrc[lane + 64] + (size_t)c * lda];
+        if (lane < np) Reg[(size_t)pdst[lane] + (size_t)c * lda] = v0;
+        if (lane + 64 < np) Reg[(size_t)pdst[lane + 64] + (size_t)c * lda] = v1;
+    }
 }
 
 // ---------------------------------------------------------------- interchanges
 
-constexpr int MAXSW = 64;          // interchanges per map
-constexpr int MAXPAIRS = 2 * MAXSW;
 
-// Builds the (dst, src) row pairs equivalent to applying the interchanges
-// ipiv[k1..k2) (absolute, 1-based, k2 - k1 <= 64) in order:
-//   new row dst[q] = old row src[q].
-// Executed by one full wave: the simulated positions (at most 128 distinct
-// rows) live in registers, two per lane, and are searched with ballots.
-// Returns the pair count (wave-uniform); dst/src are written to LDS.
-__device__ int build_pairs_wave(const int *__restrict__ ipiv, int k1, int k2, int nrows, int *dst, int *src) {
-    const int lane = threadIdx.x & 63;
-    int myp = (k1 + lane < k2) ? ipiv[k1 + lane] - 1 : -1;
-    if (myp < k1 + lane || myp >= nrows) myp = k1 + lane;  // out-of-range interchange: ignored
-    int pos0 = -1, cont0 = -1, pos1 = -1, cont1 = -1;
-    int np = 0;
-    for (int k = k1; k < k2; ++k) {
-        const int p = __shfl(myp, k - k1);
-        if (p == k) continue;
-        unsigned long long b0 = __ballot(pos0 == k), b1 = __ballot(pos1 == k);
-        int ik = b0 ? __builtin_ctzll(b0) : (b1 ? 64 + __builtin_ctzll(b1) : -1);
-        b0 = __ballot(pos0 == p);
-        b1 = __ballot(pos1 == p);
-        int ip = b0 ? __builtin_ctzll(b0) : (b1 ? 64 + __builtin_ctzll(b1) : -1);
-        if (ik < 0) {
-            if (lane == (np & 63)) { if (np < 64) { pos0 = k; cont0 = k; } else { pos1 = k; cont1 = k; } }
-            ik = np++;
-        }
-        if (ip < 0) {
-            if (lane == (np & 63)) { if (np < 64) { pos0 = p; cont0 = p; } else { pos1 = p; cont1 = p; } }
-            ip = np++;
-        }
-        const int ck = ik < 64 ? __shfl(cont0, ik) : __shfl(cont1, ik - 64);
-        const int cp = ip < 64 ? __shfl(cont0, ip) : __shfl(cont1, ip - 64);
-        if (lane == (ik & 63)) { if (ik < 64) cont0 = cp; else cont1 = cp; }
-        if (lane == (ip & 63)) { if (ip < 64) cont0 = ck; else cont1 = ck; }
-    }
-    // compaction of the moved positions
-    const bool m0 = pos0 >= 0 && cont0 != pos0;
-    const bool m1 = pos1 >= 0 && cont1 != pos1;
-    const unsigned long long bm0 = __ballot(m0), bm1 = __ballot(m1);
-    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int c0 = __popcll(bm0);
-    if (m0) { const int q = __popcll(bm0 & below); dst[q] = pos0; src[q] = cont0; }
-    if (m1) { const int q = c0 + __popcll(bm1 & below); dst[q] = pos1; src[q] = cont1; }
-    return c0 + __popcll(bm1);
-}
 
 // Applies interchanges ipiv[k1..k2) (k2 - k1 <= 64) to the ncols columns of
 // A, 64 columns per workgroup: all rows moved are read before any is written.
@@ -405,7 +435,8 @@ __global__ __launch_bounds__(256) void apply_pairs_kernel(int ncols, T *__restri
 namespace cdf {
 
 hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, int lda, int *ipiv, int row0,
-                   int *info, int info_base, int rows_per_thread) {
+                   int *info, int info_base, int rows_per_thread, double *region, int region_rows, int region_cols,
+                   int c0) {
     if (m <= 0 || n <= 0) return hipSuccess;
     if (n > LW || n > m) return hipErrorInvalidValue;
     static bool attr = false;
@@ -432,7 +463,8 @@ hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, 
     h->leaf_epoch += 64u;
     u64 *tags = static_cast<u64 *>(h->ws);
     double *rows = reinterpret_cast<double *>(static_cast<char *>(h->ws) + kTagBytes);
-    void *args[] = {&m, &n, &A, &lda, &ipiv, &row0, &info, &info_base, &tags, &rows, &e0};
+    void *args[] = {&m, &n, &A, &lda, &ipiv, &row0, &info, &info_base, &tags, &rows, &e0, &region, &region_rows,
+                    &region_cols, &c0};
     const void *fn = R == 1 ? reinterpret_cast<const void *>(&lu_leaf_kernel<1>)
                             : reinterpret_cast<const void *>(&lu_leaf_kernel<2>);
     const size_t lds = (size_t)LW * LT * R * sizeof(double);
