@@ -6,22 +6,10 @@
 // the LAPACK info.  Only the lower triangle is read or written.
 #include "internal.h"
 
-#include <type_traits>
-
 namespace {
 
 constexpr int NT = 256;
 constexpr int MAXN = 128;
-
-// Compile-time loop: f(integral_constant<int, I>) for I in [B, E), so that
-// register-array indices are constants before any optimization runs.
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
 
 // One workgroup of 256 threads; the block's lower triangle lives in
 // registers: thread (wave w, lane l) owns rows l and l + 64 of columns
@@ -38,16 +26,16 @@ __global__ __launch_bounds__(NT) void potrf_diag_kernel(int n, double *__restric
     __shared__ double sd;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     double a[2][32];
-    static_for<0, 2>([&](auto rc) {
+    cdf::static_for<0, 2>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
-        static_for<0, 32>([&](auto qc) {
+        cdf::static_for<0, 32>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             const int i = lane + 64 * r, j = w + 4 * q;
             a[r][q] = (i < n && j < n && i >= j) ? A[(size_t)i + (size_t)j * lda] : 0.0;
         });
     });
     int fail = 0;  // uniform: every thread reads the same published diagonal
-    static_for<0, 32>([&](auto kqc) {
+    cdf::static_for<0, 32>([&](auto kqc) {
         constexpr int kq = decltype(kqc)::value;
         for (int kw = 0; kw < 4; ++kw) {
             const int k = 4 * kq + kw;
@@ -63,7 +51,7 @@ __global__ __launch_bounds__(NT) void potrf_diag_kernel(int n, double *__restric
             }
             if (own) {
                 const double lkk = sqrt(d);
-                static_for<0, 2>([&](auto rc) {
+                cdf::static_for<0, 2>([&](auto rc) {
                     constexpr int r = decltype(rc)::value;
                     const int i = lane + 64 * r;
                     if (i >= k && i < n) {
@@ -78,7 +66,7 @@ __global__ __launch_bounds__(NT) void potrf_diag_kernel(int n, double *__restric
             const int i0 = lane, i1 = lane + 64;
             const double l0 = (i0 > k && i0 < n) ? sc[par][i0 - k] : 0.0;
             const double l1 = (i1 > k && i1 < n) ? sc[par][i1 - k] : 0.0;
-            static_for<kq, 32>([&](auto qc) {
+            cdf::static_for<kq, 32>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 const int j = w + 4 * q;
                 if (j > k && j < n) {
@@ -89,9 +77,9 @@ __global__ __launch_bounds__(NT) void potrf_diag_kernel(int n, double *__restric
             });
         }
     });
-    static_for<0, 2>([&](auto rc) {
+    cdf::static_for<0, 2>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
-        static_for<0, 32>([&](auto qc) {
+        cdf::static_for<0, 32>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             const int i = lane + 64 * r, j = w + 4 * q;
             if (i < n && j < n && i >= j) A[(size_t)i + (size_t)j * lda] = a[r][q];

@@ -197,6 +197,111 @@ __global__ __launch_bounds__(NT, Shape<TB>::OCC) void dgemm_kernel(int m, int n,
         }
 }
 
+// C = beta C + alpha A B (no transposes) with the operands brought into LDS
+// by the direct global-to-LDS path (global_load_lds_dwordx4): no staging
+// registers and no LDS store instructions, two LDS stages, one barrier per
+// K step.  32 KB of LDS and about 70 registers give five workgroups per CU;
+// a 64 x 64 tile per workgroup as above.  Lane l of an A load instruction
+// writes bytes [16 l, 16 l + 16) of a 1 KB block: rows 2(l % 32) and
+// 2(l % 32) + 1 of k-column l / 32.  A B instruction covers 8 columns x 16
+// k; its lanes fetch k-pairs in XOR-swizzled order, so that the fragment
+// reads of 16 consecutive columns spread over the LDS banks.  Requirements,
+// checked by the launcher: k % 16 == 0, m and both leading dimensions even,
+// A and B 16-byte aligned.  Rows and columns past the matrix are clamped to
+// valid ones, and their results are discarded.
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glob_void;
+
+__global__ __launch_bounds__(NT, 5) void dgemm_nn_dl_kernel(int m, int n, int k, double alpha,
+                                                            const double *__restrict__ A, int lda,
+                                                            const double *__restrict__ B, int ldb, double beta,
+                                                            double *__restrict__ C, int ldc, int tiles_m,
+                                                            int tiles_n, const int *stop) {
+    if (stop != nullptr && *stop != 0) return;
+    constexpr int W = 2, BT = 64, STAGE = 2 * BT * BK;  // doubles per stage (A then B)
+    __shared__ __attribute__((aligned(16))) double S[2 * STAGE];
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    int tm, tn;
+    grouped_tile(L, tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BT, n0 = tn * BT;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave & 1, wn = wave >> 1, lrow = lane & 15, lk = lane >> 4;
+    const int arow = min(m0 + 2 * (lane & 31), m - 2);
+    const int bcol0 = min(n0 + 16 * wave + (lane >> 3), n - 1);
+    const int bcol1 = min(n0 + 16 * wave + 8 + (lane >> 3), n - 1);
+    const int bq = (lane & 7) ^ (lane >> 3);  // k-pair this lane fetches
+    const double *asrc = A + arow + (size_t)(lane >> 5) * lda;
+    const double *bsrc0 = B + 2 * bq + (size_t)bcol0 * ldb;
+    const double *bsrc1 = B + 2 * bq + (size_t)bcol1 * ldb;
+    auto issue = [&](int kt) {
+        double *st = S + (kt & 1) * STAGE;
+        const size_t k0 = (size_t)kt * BK;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = 2 * wave + u;  // k-columns 2i, 2i + 1
+            __builtin_amdgcn_global_load_lds((glob_void *)(asrc + (k0 + 2 * i) * lda), (lds_void *)(st + i * 128), 16, 0,
+                                             0);
+        }
+        __builtin_amdgcn_global_load_lds((glob_void *)(bsrc0 + k0), (lds_void *)(st + BT * BK + (2 * wave) * 128), 16,
+                                         0, 0);
+        __builtin_amdgcn_global_load_lds((glob_void *)(bsrc1 + k0), (lds_void *)(st + BT * BK + (2 * wave + 1) * 128),
+                                         16, 0, 0);
+    };
+    v4d acc[W][W];
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+#pragma unroll
+        for (int j = 0; j < W; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int nk = k / BK;
+    if (nk > 0) issue(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): this stage's loads have landed in LDS
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();       // ... for every wave; the other stage is free
+        asm volatile("" ::: "memory");
+        if (kt + 1 < nk) issue(kt + 1);
+        const double *As = S + (kt & 1) * STAGE;
+        const double *Bs = As + BT * BK;
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            const int kk = ks * 4 + lk;
+            double af[W], bf[W];
+#pragma unroll
+            for (int i = 0; i < W; ++i) af[i] = As[kk * BT + wm * 32 + i * 16 + lrow];
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                const int cc = wn * 32 + j * 16 + lrow;
+                bf[j] = Bs[cc * BK + (((kk >> 1) ^ (cc & 7)) << 1) + (kk & 1)];
+            }
+#pragma unroll
+            for (int i = 0; i < W; ++i)
+#pragma unroll
+                for (int j = 0; j < W; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const int col = n0 + wn * 32 + j * 16 + lrow;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 32 + i * 16 + v * 4 + lk;
+                if (row < m && col < n) {
+                    double *p = C + (size_t)row + (size_t)col * ldc;
+                    const double c0 = beta == 0.0 ? 0.0 : beta * *p;
+                    *p = fma(alpha, acc[i][j][v], c0);
+                }
+            }
+        }
+}
+
+bool nn_dl_ok(int m, int k, const double *A, int lda, const double *B, int ldb) {
+    return k % BK == 0 && m >= 2 && m % 2 == 0 && lda % 2 == 0 && ldb % 2 == 0 &&
+           (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+}
+
 template <int TA, int TB, bool LOWER>
 hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double *A, int lda,
                   const double *B, int ldb, double beta, double *C, int ldc, const int *stop) {
@@ -209,8 +314,12 @@ hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double
     const int kind = LOWER ? 4 : TA * 2 + TB;
     const double flops = LOWER ? (double)m * (m + 1) * k : 2.0 * m * n * k;
     const int slot = cdf::prof_begin(s, kind, flops);
-    hipLaunchKernelGGL((dgemm_kernel<TA, TB, LOWER>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k,
-                       alpha, A, lda, B, ldb, beta, C, ldc, tiles_m, tiles_n, stop);
+    if (TA == 0 && TB == 0 && !LOWER && BM == 64 && nn_dl_ok(m, k, A, lda, B, ldb))
+        hipLaunchKernelGGL(dgemm_nn_dl_kernel, dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k, alpha, A, lda, B, ldb,
+                           beta, C, ldc, tiles_m, tiles_n, stop);
+    else
+        hipLaunchKernelGGL((dgemm_kernel<TA, TB, LOWER>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k,
+                           alpha, A, lda, B, ldb, beta, C, ldc, tiles_m, tiles_n, stop);
     const hipError_t e = hipGetLastError();
     cdf::prof_end(s, slot);
     return e;

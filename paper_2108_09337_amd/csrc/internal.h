@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 #include "cdnafact.h"
 
@@ -22,6 +23,16 @@ struct cdf_handle_s {
 };
 
 namespace cdf {
+
+// Compile-time loop: f(integral_constant<int, I>) for I in [B, E), so that
+// register-array indices are constants before any optimization runs.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
 // Bytes at the head of the workspace reserved for the panel leaf's exchange.
 constexpr size_t kLeafWsBytes = 256 * 1024;

@@ -3,9 +3,11 @@
 // and row interchanges.
 //
 // Leaf kernel: factors an m x n (n <= 32) column block.  The rows are spread
-// over G workgroups (at most one per CU), each keeping its 256*R rows of the
-// block in LDS (column-major, so a column scan is contiguous).  Every column
-// costs one grid-wide exchange, done without atomics or cache-wide fences:
+// over G workgroups (at most one per CU), 256*R rows each; every thread keeps
+// its R rows of the block in registers (the column loop is unrolled at
+// compile time), so the kernel needs almost no LDS and fits on a CU beside
+// the update GEMM's workgroups.  Every column costs one grid-wide exchange,
+// done without atomics or cache-wide fences:
 //   1. each workgroup finds its best candidate (largest |a|, lowest row on
 //      ties) with wave shuffles and LDS, writes the candidate's whole row
 //      (and, if it owns it, the current row j) to its slot, waits for those
@@ -110,12 +112,10 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
                                                      unsigned epoch0, double *__restrict__ Reg, int rm,
                                                      int rcols, int rc0) {
     constexpr int RT = LT * R;  // rows per workgroup
-    extern __shared__ double X[];  // X[c * RT + local row]
-    __shared__ double prow[LW];
-    __shared__ double oldj[LW];
+    __shared__ double prow[LW], oldj[LW], cand[LW], lrowj[LW];
     __shared__ double wv[LT / 64], xv[LT / 64];
     __shared__ int wi[LT / 64], xi[LT / 64], xw[LT / 64];
-    __shared__ int spiv[LW];                    // region row (1-based) swapped with row rc0 + j
+    __shared__ int spiv[LW];  // region row (1-based) swapped with row rc0 + j
     __shared__ int pdst[MAXPAIRS], psrc[MAXPAIRS];
     __shared__ int s_np;
 
@@ -126,34 +126,29 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
     const int rbase = g * RT;
     double *rowj = rows + (size_t)2 * GMAX * LW;
 
-    // load the block: 8 columns in flight per thread at a time
-    for (int c0 = 0; c0 < n; c0 += 8) {
-        double tmp[8][R];
-#pragma unroll
-        for (int cc = 0; cc < 8; ++cc)
-#pragma unroll
-            for (int s = 0; s < R; ++s) {
-                const int r = rbase + s * LT + t, c = c0 + cc;
-                tmp[cc][s] = (r < m && c < n) ? A[(size_t)r + (size_t)c * lda] : 0.0;
-            }
-#pragma unroll
-        for (int cc = 0; cc < 8; ++cc)
-#pragma unroll
-            for (int s = 0; s < R; ++s)
-                if (c0 + cc < n) X[(c0 + cc) * RT + s * LT + t] = tmp[cc][s];
-    }
-    __syncthreads();
+    // the thread's rows rbase + s*LT + t, all columns, in registers
+    double x[R][LW];
+    cdf::static_for<0, R>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        const int r = rbase + s * LT + t;
+        cdf::static_for<0, LW>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            x[s][c] = (r < m && c < n) ? A[(size_t)r + (size_t)c * lda] : 0.0;
+        });
+    });
 
-    for (int j = 0; j < n; ++j) {
+    cdf::static_for<0, LW>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j >= n) return;
         const int par = j & 1;
         // 1. local candidate of column j among rows >= j
         double bv = -1.0;
         int bi = INT_MAX;
-#pragma unroll
-        for (int s = 0; s < R; ++s) {
+        cdf::static_for<0, R>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
             const int r = rbase + s * LT + t;
-            if (r < m && r >= j) better(bv, bi, fabs(X[j * RT + s * LT + t]), r);
-        }
+            if (r < m && r >= j) better(bv, bi, fabs(x[s][j]), r);
+        });
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             const double ov = __shfl_xor(bv, off);
@@ -166,13 +161,22 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
         int p = wi[0];
 #pragma unroll
         for (int w = 1; w < LT / 64; ++w) better(v, p, wv[w], wi[w]);
-        int win = 0;
+        // the candidate's row and row j go to LDS, each written by its owner
+        cdf::static_for<0, R>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+            const int r = rbase + s * LT + t;
+            if (r == p)
+                cdf::static_for<0, LW>([&](auto cc) { cand[decltype(cc)::value] = x[s][decltype(cc)::value]; });
+            if (r == j)
+                cdf::static_for<0, LW>([&](auto cc) { lrowj[decltype(cc)::value] = x[s][decltype(cc)::value]; });
+        });
+        __syncthreads();
         if (G > 1) {
             const u64 e = (u64)(epoch0 + (unsigned)j) << 32;
             if (wave == 0) {
                 // publish: rows first, then (after they completed) the tags
-                if (p != INT_MAX && t < n) put_dev(rows + ((size_t)par * GMAX + g) * LW + t, X[t * RT + (p - rbase)]);
-                if (j >= rbase && j < rbase + RT && t < n) put_dev(rowj + (size_t)par * LW + t, X[t * RT + (j - rbase)]);
+                if (p != INT_MAX && t < n) put_dev(rows + ((size_t)par * GMAX + g) * LW + t, cand[t]);
+                if (j >= rbase && j < rbase + RT && t < n) put_dev(rowj + (size_t)par * LW + t, lrowj[t]);
                 __builtin_amdgcn_s_waitcnt(0);
                 if (t < 3) {
                     const u64 bits = (u64)__double_as_longlong(v);
@@ -208,7 +212,7 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
             __syncthreads();
             v = xv[0];
             p = xi[0];
-            win = xw[0];
+            int win = xw[0];
 #pragma unroll
             for (int w = 1; w < LT / 64; ++w)
                 if (xv[w] > v || (xv[w] == v && xi[w] < p)) { v = xv[w]; p = xi[w]; win = xw[w]; }
@@ -220,8 +224,8 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
                 prow[t] = p == INT_MAX ? oj : pw;
             }
         } else if (t < n) {
-            oldj[t] = X[t * RT + j];
-            prow[t] = p == INT_MAX ? X[t * RT + j] : X[t * RT + p];
+            oldj[t] = lrowj[t];
+            prow[t] = p == INT_MAX ? lrowj[t] : cand[t];
         }
         if (p == INT_MAX) p = j;  // no ordered candidate (NaN column): no interchange
         __syncthreads();
@@ -232,35 +236,38 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
             if (piv == 0.0 && *info == 0) *info = info_base + j + 1;
         }
         // swap rows j and p, scale and update; every thread owns its rows
-#pragma unroll
-        for (int s = 0; s < R; ++s) {
+        cdf::static_for<0, R>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
             const int r = rbase + s * LT + t;
-            const int rl = s * LT + t;
             if (r == j) {
-                for (int c = 0; c < n; ++c) X[c * RT + rl] = prow[c];
+                cdf::static_for<0, LW>([&](auto cc) { x[s][decltype(cc)::value] = prow[decltype(cc)::value]; });
             } else if (r > j && r < m) {
                 const bool moved = (r == p);
                 if (moved)
-                    for (int c = 0; c < j; ++c) X[c * RT + rl] = oldj[c];
-                const double aj = moved ? oldj[j] : X[j * RT + rl];
+                    cdf::static_for<0, j>([&](auto cc) { x[s][decltype(cc)::value] = oldj[decltype(cc)::value]; });
+                const double aj = moved ? oldj[j] : x[s][j];
                 if (piv != 0.0) {
                     const double l = aj / piv;
-                    X[j * RT + rl] = l;
-                    for (int c = j + 1; c < n; ++c) X[c * RT + rl] = fma(-l, prow[c], moved ? oldj[c] : X[c * RT + rl]);
+                    x[s][j] = l;
+                    cdf::static_for<j + 1, LW>([&](auto cc) {
+                        constexpr int c = decltype(cc)::value;
+                        x[s][c] = fma(-l, prow[c], moved ? oldj[c] : x[s][c]);
+                    });
                 } else if (moved) {
-                    for (int c = j; c < n; ++c) X[c * RT + rl] = oldj[c];
+                    cdf::static_for<j, LW>([&](auto cc) { x[s][decltype(cc)::value] = oldj[decltype(cc)::value]; });
                 }
             }
-        }
-        __syncthreads();
-    }
+        });
+    });
 
-    for (int c = 0; c < n; ++c)
-#pragma unroll
-        for (int s = 0; s < R; ++s) {
-            const int r = rbase + s * LT + t;
-            if (r < m) A[(size_t)r + (size_t)c * lda] = X[c * RT + s * LT + t];
-        }
+    cdf::static_for<0, R>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        const int r = rbase + s * LT + t;
+        cdf::static_for<0, LW>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            if (r < m && c < n) A[(size_t)r + (size_t)c * lda] = x[s][c];
+        });
+    });
 
     // the block's interchanges on the region's other columns [0, rc0) and
     // [rc0 + n, rcols): pairs from the pivots (same in every workgroup), then
@@ -439,14 +446,6 @@ hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, 
                    int c0) {
     if (m <= 0 || n <= 0) return hipSuccess;
     if (n > LW || n > m) return hipErrorInvalidValue;
-    static bool attr = false;
-    if (!attr) {
-        CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&lu_leaf_kernel<1>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, LW * LT * 8));
-        CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&lu_leaf_kernel<2>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, LW * LT * 2 * 8));
-        attr = true;
-    }
     int R = rows_per_thread;
     if (R != 1 && R != 2) R = (m + LT - 1) / LT > h->num_cus / 2 ? 2 : 1;
     int G = (m + LT * R - 1) / (LT * R);
@@ -467,7 +466,7 @@ hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, 
                     &region_cols, &c0};
     const void *fn = R == 1 ? reinterpret_cast<const void *>(&lu_leaf_kernel<1>)
                             : reinterpret_cast<const void *>(&lu_leaf_kernel<2>);
-    const size_t lds = (size_t)LW * LT * R * sizeof(double);
+    const size_t lds = 0;  // the block lives in registers
     // A plain launch: G <= number of CUs and each CU fits a leaf workgroup, so
     // all G become resident at the latest when the (finite) kernels that may
     // run beside it on other streams have drained; the exchange then

@@ -200,6 +200,29 @@ def test_dgemm_update(m, n, k):
     assert np.max(np.abs(got - ref)) <= 4 * k * gpu_util.EPS * (np.abs(a) @ np.abs(b) + np.abs(c)).max()
 
 
+@pytest.mark.parametrize("m,n,k", [(1000, 700, 512), (130, 66, 48), (64, 1, 16)])
+def test_dgemm_update_fast_path_matches_general_path(m, n, k):
+    """Aligned even shapes take the direct-to-LDS kernel; the same product with
+    an odd leading dimension for A takes the general kernel.  Both accumulate
+    in the same order, so the results must agree bit for bit."""
+    rng = np.random.default_rng(m + 3 * n + k)
+    a = rng.uniform(-1, 1, (m, k))
+    b = np.asfortranarray(rng.uniform(-1, 1, (k, n)))
+    c = np.asfortranarray(rng.uniform(-1, 1, (m, n)))
+    A_even = cdf.to_device(np.asfortranarray(a))
+    A_odd_store = cdf.cm_empty(m + 1, k)             # leading dimension m + 1 (odd)
+    A_odd_store[:m].copy_(A_even)
+    A_odd = A_odd_store[:m]
+    B = cdf.to_device(b)
+    C1, C2 = cdf.to_device(c), cdf.to_device(c)
+    cdf.dgemm_update(A_even, B, C1)
+    cdf.dgemm_update(A_odd, B, C2)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    ref = c - a @ b
+    assert np.max(np.abs(cdf.to_host(C1) - ref)) <= 4 * k * gpu_util.EPS * (np.abs(a) @ np.abs(b) + np.abs(c)).max()
+
+
 def test_invalid_arguments():
     h = cdf.handle()
     L = cdf.lib()
