@@ -197,7 +197,8 @@ __global__ __launch_bounds__(NT, Shape<TB>::OCC) void dgemm_kernel(int m, int n,
         }
 }
 
-// C = beta C + alpha A B (no transposes) with the operands brought into LDS
+// C = beta C + alpha A op(B) (op(B) = B or B^T; LOWER: lower-triangle tiles
+// only, as the SYRK of the Cholesky) with the operands brought into LDS
 // by the direct global-to-LDS path (global_load_lds_dwordx4): no staging
 // registers and no LDS store instructions, two LDS stages, one barrier per
 // K step.  32 KB of LDS and about 70 registers give five workgroups per CU;
@@ -206,33 +207,42 @@ __global__ __launch_bounds__(NT, Shape<TB>::OCC) void dgemm_kernel(int m, int n,
 // 2(l % 32) + 1 of k-column l / 32.  A B instruction covers 8 columns x 16
 // k; its lanes fetch k-pairs in XOR-swizzled order, so that the fragment
 // reads of 16 consecutive columns spread over the LDS banks.  Requirements,
-// checked by the launcher: k % 16 == 0, m and both leading dimensions even,
-// A and B 16-byte aligned.  Rows and columns past the matrix are clamped to
+// checked by the launcher: k % 16 == 0, m (and n for B^T) and both leading
+// dimensions even, A and B 16-byte aligned.  For op(B) = B^T the B tile is
+// loaded like the A tile.  Rows and columns past the matrix are clamped to
 // valid ones, and their results are discarded.
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void glob_void;
 
-__global__ __launch_bounds__(NT, 5) void dgemm_nn_dl_kernel(int m, int n, int k, double alpha,
-                                                            const double *__restrict__ A, int lda,
-                                                            const double *__restrict__ B, int ldb, double beta,
-                                                            double *__restrict__ C, int ldc, int tiles_m,
-                                                            int tiles_n, const int *stop) {
+template <int TB, bool LOWER>
+__global__ __launch_bounds__(NT, 5) void dgemm_dl_kernel(int m, int n, int k, double alpha,
+                                                         const double *__restrict__ A, int lda,
+                                                         const double *__restrict__ B, int ldb, double beta,
+                                                         double *__restrict__ C, int ldc, int tiles_m, int tiles_n,
+                                                         const int *stop) {
     if (stop != nullptr && *stop != 0) return;
     constexpr int W = 2, BT = 64, STAGE = 2 * BT * BK;  // doubles per stage (A then B)
     __shared__ __attribute__((aligned(16))) double S[2 * STAGE];
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     int tm, tn;
-    grouped_tile(L, tiles_m, tiles_n, tm, tn);
+    if (LOWER) lower_tile(L, tm, tn);
+    else grouped_tile(L, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BT, n0 = tn * BT;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1, lrow = lane & 15, lk = lane >> 4;
     const int arow = min(m0 + 2 * (lane & 31), m - 2);
-    const int bcol0 = min(n0 + 16 * wave + (lane >> 3), n - 1);
-    const int bcol1 = min(n0 + 16 * wave + 8 + (lane >> 3), n - 1);
-    const int bq = (lane & 7) ^ (lane >> 3);  // k-pair this lane fetches
     const double *asrc = A + arow + (size_t)(lane >> 5) * lda;
-    const double *bsrc0 = B + 2 * bq + (size_t)bcol0 * ldb;
-    const double *bsrc1 = B + 2 * bq + (size_t)bcol1 * ldb;
+    // op(B) = B: column-major k x n, 8 columns x 16 k per instruction, k-pairs swizzled;
+    // op(B) = B^T: B is n x k, loaded like A (2 columns of op(B) per lane, 2 k per instruction)
+    const int bq = (lane & 7) ^ (lane >> 3);
+    const double *bsrc0, *bsrc1;
+    if (TB == 0) {
+        bsrc0 = B + 2 * bq + (size_t)min(n0 + 16 * wave + (lane >> 3), n - 1) * ldb;
+        bsrc1 = B + 2 * bq + (size_t)min(n0 + 16 * wave + 8 + (lane >> 3), n - 1) * ldb;
+    } else {
+        bsrc0 = B + min(n0 + 2 * (lane & 31), n - 2) + (size_t)(lane >> 5) * ldb;
+        bsrc1 = bsrc0;
+    }
     auto issue = [&](int kt) {
         double *st = S + (kt & 1) * STAGE;
         const size_t k0 = (size_t)kt * BK;
@@ -242,10 +252,19 @@ __global__ __launch_bounds__(NT, 5) void dgemm_nn_dl_kernel(int m, int n, int k,
             __builtin_amdgcn_global_load_lds((glob_void *)(asrc + (k0 + 2 * i) * lda), (lds_void *)(st + i * 128), 16, 0,
                                              0);
         }
-        __builtin_amdgcn_global_load_lds((glob_void *)(bsrc0 + k0), (lds_void *)(st + BT * BK + (2 * wave) * 128), 16,
-                                         0, 0);
-        __builtin_amdgcn_global_load_lds((glob_void *)(bsrc1 + k0), (lds_void *)(st + BT * BK + (2 * wave + 1) * 128),
-                                         16, 0, 0);
+        if (TB == 0) {
+            __builtin_amdgcn_global_load_lds((glob_void *)(bsrc0 + k0), (lds_void *)(st + BT * BK + (2 * wave) * 128),
+                                             16, 0, 0);
+            __builtin_amdgcn_global_load_lds((glob_void *)(bsrc1 + k0),
+                                             (lds_void *)(st + BT * BK + (2 * wave + 1) * 128), 16, 0, 0);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int i = 2 * wave + u;
+                __builtin_amdgcn_global_load_lds((glob_void *)(bsrc0 + (k0 + 2 * i) * ldb),
+                                                 (lds_void *)(st + BT * BK + i * 128), 16, 0, 0);
+            }
+        }
     };
     v4d acc[W][W];
 #pragma unroll
@@ -271,7 +290,7 @@ __global__ __launch_bounds__(NT, 5) void dgemm_nn_dl_kernel(int m, int n, int k,
 #pragma unroll
             for (int j = 0; j < W; ++j) {
                 const int cc = wn * 32 + j * 16 + lrow;
-                bf[j] = Bs[cc * BK + (((kk >> 1) ^ (cc & 7)) << 1) + (kk & 1)];
+                bf[j] = TB == 0 ? Bs[cc * BK + (((kk >> 1) ^ (cc & 7)) << 1) + (kk & 1)] : Bs[kk * BT + cc];
             }
 #pragma unroll
             for (int i = 0; i < W; ++i)
@@ -288,7 +307,7 @@ __global__ __launch_bounds__(NT, 5) void dgemm_nn_dl_kernel(int m, int n, int k,
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = m0 + wm * 32 + i * 16 + v * 4 + lk;
-                if (row < m && col < n) {
+                if (row < m && col < n && (!LOWER || row >= col)) {
                     double *p = C + (size_t)row + (size_t)col * ldc;
                     const double c0 = beta == 0.0 ? 0.0 : beta * *p;
                     *p = fma(alpha, acc[i][j][v], c0);
@@ -297,8 +316,8 @@ __global__ __launch_bounds__(NT, 5) void dgemm_nn_dl_kernel(int m, int n, int k,
         }
 }
 
-bool nn_dl_ok(int m, int k, const double *A, int lda, const double *B, int ldb) {
-    return k % BK == 0 && m >= 2 && m % 2 == 0 && lda % 2 == 0 && ldb % 2 == 0 &&
+bool dl_ok(int tb, int m, int n, int k, const double *A, int lda, const double *B, int ldb) {
+    return k % BK == 0 && m >= 2 && m % 2 == 0 && lda % 2 == 0 && ldb % 2 == 0 && (tb == 0 || (n >= 2 && n % 2 == 0)) &&
            (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
 }
 
@@ -306,20 +325,29 @@ template <int TA, int TB, bool LOWER>
 hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double *A, int lda,
                   const double *B, int ldb, double beta, double *C, int ldc, const int *stop) {
     constexpr int BM = Shape<TB>::B, BN = Shape<TB>::B;
+    const int kind = LOWER ? 4 : TA * 2 + TB;
+    const double flops = LOWER ? (double)m * (m + 1) * k : 2.0 * m * n * k;
+    if (TA == 0 && dl_ok(TB, m, n, k, A, lda, B, ldb)) {
+        // direct-to-LDS kernel, 64 x 64 tiles
+        const int tm64 = (m + 63) / 64, tn64 = (n + 63) / 64;
+        const long long nwg = LOWER ? (long long)tm64 * (tm64 + 1) / 2 : (long long)tm64 * tn64;
+        if (nwg <= 0) return hipSuccess;
+        if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
+        const int slot = cdf::prof_begin(s, kind, flops);
+        hipLaunchKernelGGL((dgemm_dl_kernel<TB, LOWER>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k, alpha, A, lda,
+                           B, ldb, beta, C, ldc, tm64, tn64, stop);
+        const hipError_t e = hipGetLastError();
+        cdf::prof_end(s, slot);
+        return e;
+    }
     const int tiles_m = (m + BM - 1) / BM;
     const int tiles_n = (n + BN - 1) / BN;
     long long nwg = LOWER ? (long long)tiles_m * (tiles_m + 1) / 2 : (long long)tiles_m * tiles_n;
     if (nwg <= 0) return hipSuccess;
     if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
-    const int kind = LOWER ? 4 : TA * 2 + TB;
-    const double flops = LOWER ? (double)m * (m + 1) * k : 2.0 * m * n * k;
     const int slot = cdf::prof_begin(s, kind, flops);
-    if (TA == 0 && TB == 0 && !LOWER && BM == 64 && nn_dl_ok(m, k, A, lda, B, ldb))
-        hipLaunchKernelGGL(dgemm_nn_dl_kernel, dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k, alpha, A, lda, B, ldb,
-                           beta, C, ldc, tiles_m, tiles_n, stop);
-    else
-        hipLaunchKernelGGL((dgemm_kernel<TA, TB, LOWER>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k,
-                           alpha, A, lda, B, ldb, beta, C, ldc, tiles_m, tiles_n, stop);
+    hipLaunchKernelGGL((dgemm_kernel<TA, TB, LOWER>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k,
+                       alpha, A, lda, B, ldb, beta, C, ldc, tiles_m, tiles_n, stop);
     const hipError_t e = hipGetLastError();
     cdf::prof_end(s, slot);
     return e;
