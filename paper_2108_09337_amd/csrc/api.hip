@@ -167,12 +167,14 @@ hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
     hipStream_t s1 = h->aux;
     CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
     const int nb = chol_nb(h, n);
-    // block column [k, k+kb): right-looking over sub-blocks of at most 128
-    // columns (the diagonal-block kernel's limit); each sub-block updates
-    // only the rest of this block column.
+    // block column [k, k+kb): right-looking over sub-blocks of at most 64
+    // columns (the register-resident right-side solve's limit, so that the
+    // panel fits beside the update GEMM); each sub-block updates only the
+    // rest of this block column.
+    constexpr int kSub = 64;
     auto panel = [&](hipStream_t s, int k, int kb) -> hipError_t {
-        for (int kk = k; kk < k + kb; kk += 128) {
-            const int kbb = 128 < k + kb - kk ? 128 : k + kb - kk;
+        for (int kk = k; kk < k + kb; kk += kSub) {
+            const int kbb = kSub < k + kb - kk ? kSub : k + kb - kk;
             double *a11 = A + kk + (size_t)kk * lda;
             CDF_HIP_RET(cdf::potrf_diag(s, kbb, a11, lda, info, kk));
             const int below = n - kk - kbb;

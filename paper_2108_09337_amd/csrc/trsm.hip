@@ -126,6 +126,40 @@ __global__ __launch_bounds__(NT) void trsm_rltn_kernel(int nb, int nrows, const 
         for (int c = wave; c < nb; c += NW) B[(size_t)r + (size_t)c * ldb] = (TB)X[c * RNR + lane];
 }
 
+// The same solve for triangles of at most 64 columns with no LDS at all:
+// lane = row, the row in registers (compile-time column loop), the
+// triangle's entries as wave-uniform (scalar) loads.  Same operations in the
+// same order as above.  Fits on a CU beside the update GEMM's workgroups,
+// which take all of its LDS.
+constexpr int RNC = 64;
+template <typename TB>
+__global__ __launch_bounds__(64) void trsm_rltn_reg_kernel(int nb, int nrows, const double *__restrict__ T, int ldt,
+                                                           TB *__restrict__ B, int ldb, const int *stop) {
+    if (stop != nullptr && *stop != 0) return;
+    const int r = blockIdx.x * 64 + threadIdx.x;
+    const bool live = r < nrows;
+    double x[RNC];
+    cdf::static_for<0, RNC>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        x[c] = (live && c < nb) ? (double)B[(size_t)r + (size_t)c * ldb] : 0.0;
+    });
+    cdf::static_for<0, RNC>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j < nb) {
+            x[j] = x[j] / T[(size_t)j + (size_t)j * ldt];
+            cdf::static_for<j + 1, RNC>([&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                if (c < nb) x[c] = fma(-x[j], T[(size_t)c + (size_t)j * ldt], x[c]);
+            });
+        }
+    });
+    if (live)
+        cdf::static_for<0, RNC>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            if (c < nb) B[(size_t)r + (size_t)c * ldb] = (TB)x[c];
+        });
+}
+
 template <int KIND, typename TB>
 hipError_t launch_left(hipStream_t s, int nb, int ncols, const double *T, int ldt, TB *B, int ldb,
                        const int *stop) {
@@ -145,6 +179,11 @@ hipError_t launch_left(hipStream_t s, int nb, int ncols, const double *T, int ld
 template <typename TB>
 hipError_t launch_right(hipStream_t s, int nb, int nrows, const double *T, int ldt, TB *B, int ldb,
                         const int *stop) {
+    if (nb <= RNC) {
+        hipLaunchKernelGGL((trsm_rltn_reg_kernel<TB>), dim3((nrows + 63) / 64), dim3(64), 0, s, nb, nrows, T, ldt, B,
+                           ldb, stop);
+        return hipGetLastError();
+    }
     static bool attr = false;
     const size_t lds = (size_t)nb * (RNR + 16) * sizeof(double);  // row block + staged triangle panel
     if (!attr) {
