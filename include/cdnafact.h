@@ -81,7 +81,10 @@ typedef enum {
                                     <= 512; the Cholesky uses at most 256) */
     CDF_PARAM_VBATCH_NB = 4,     /* batched panel width: 0 = 32 where it fits in LDS, 16 = always 16 */
     CDF_PARAM_VBATCH_WG_PER_CU = 5, /* batched persistent workgroups per CU (1 or 2; 0 = 1) */
-    CDF_PARAM_COUNT = 6
+    CDF_PARAM_GEMM_WG_PER_CU = 6,   /* update-GEMM workgroups resident per CU in this handle's
+                                       factorizations (3, 4 or 5; 0 = 5, all of the LDS).  Fewer
+                                       leave room for the panel kernels on the second stream. */
+    CDF_PARAM_COUNT = 7
 } cdf_param_t;
 CDF_API cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value);
 CDF_API int cdf_get_param(cdf_handle_t h, cdf_param_t p);

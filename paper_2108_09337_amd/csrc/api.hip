@@ -30,9 +30,10 @@ inline int chol_nb(cdf_handle_t h, int n) {
 }
 
 // LU workspace: the leaf's exchange area, the current panel's pivots (<= 512)
-// and its interchange pairs.
+// and the interchange pairs of the last two panels.
 constexpr int kMaxLuNb = 512;
-constexpr size_t kLuWsBytes = cdf::kLeafWsBytes + kMaxLuNb * sizeof(int) + (1 + 4 * kMaxLuNb) * sizeof(int) + 4096;
+constexpr int kPairsInts = 1 + 4 * kMaxLuNb;
+constexpr size_t kLuWsBytes = cdf::kLeafWsBytes + (kMaxLuNb + 2 * kPairsInts) * sizeof(int) + 4096;
 
 }  // namespace
 
@@ -68,6 +69,7 @@ hipError_t lu_panel(cdf_handle_t h, hipStream_t s, int m, int ncols, double *A, 
 // no-ops) once *info != 0; info values are offset by info_off.
 hipError_t ensure_aux(cdf_handle_t h) {
     if (!h->aux) CDF_HIP_RET(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    if (!h->aux2) CDF_HIP_RET(hipStreamCreateWithFlags(&h->aux2, hipStreamNonBlocking));
     for (auto &e : h->ev)
         if (!e) CDF_HIP_RET(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return hipSuccess;
@@ -96,7 +98,8 @@ namespace {
 
 struct LuWs {
     int *ipt;    // region-relative pivots of the current panel
-    int *pairs;  // its interchange pairs
+    int *pairs;  // its interchange pairs (one of the two buffers below)
+    int *buf[2];
 };
 
 // Panel [k, k+kb) over rows [k, n) as a region: pivots relative to row k in
@@ -112,16 +115,26 @@ hipError_t factor_panel(cdf_handle_t h, hipStream_t s, int n, double *A, int lda
 // Blocked right-looking LU with look-ahead of depth one: while the trailing
 // update of panel k runs on the handle's stream, panel k+1 (whose columns
 // were updated first) is factored on a second stream; its interchanges are
-// applied to the other columns once both are done.
+// applied to the trailing columns once both are done.  Their application to
+// the finished L columns to the left, which no later step reads, runs on a
+// third stream beside the next steps (panel p's pairs live in buffer p mod 2,
+// so panel p+2 waits for that stream's use of panel p's pairs).
 hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ipt, int *pairs) {
+    cdf::set_gemm_wg_per_cu(h->params[CDF_PARAM_GEMM_WG_PER_CU]);
     hipStream_t s0 = h->stream;
     CDF_HIP_RET(cdf::ensure_aux(h));
-    hipStream_t s1 = h->aux;
+    hipStream_t s1 = h->aux, s2 = h->aux2;
+    hipEvent_t *left_done = h->ev + 3;  // per pairs buffer
     CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
     const int nb = lu_nb(h, n);
     LuWs ws;
     ws.ipt = ipt;
-    ws.pairs = pairs;
+    ws.buf[0] = pairs;
+    ws.buf[1] = pairs + kPairsInts;
+    ws.pairs = ws.buf[0];
+    // the third stream starts after everything already queued on the handle's
+    CDF_HIP_RET(hipEventRecord(h->ev[2], s0));
+    CDF_HIP_RET(hipStreamWaitEvent(s2, h->ev[2], 0));
     const int kb0 = nb < n ? nb : n;
     CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, 0, kb0, ws));
     CDF_HIP_RET(cdf::apply_pairs(s0, kb0, n, A, lda, ws.pairs));
@@ -131,6 +144,8 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
         if (k1 >= n) break;
         const int kb1 = nb < n - k1 ? nb : n - k1;
         const int rest = n - k1;
+        const int b = (k1 / nb) & 1;  // pairs buffer of panel k1
+        ws.pairs = ws.buf[b];
         double *l11 = A + k + (size_t)k * lda;
         double *a21 = A + k1 + (size_t)k * lda;
         // next panel's columns first
@@ -140,6 +155,7 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
         if (rest > kb1) {
             CDF_HIP_RET(hipEventRecord(h->ev[0], s0));
             CDF_HIP_RET(hipStreamWaitEvent(s1, h->ev[0], 0));
+            CDF_HIP_RET(hipStreamWaitEvent(s1, left_done[b], 0));
             CDF_HIP_RET(factor_panel(h, s1, n, A, lda, ipiv, info, k1, kb1, ws));
             CDF_HIP_RET(hipEventRecord(h->ev[1], s1));
             const int c2 = k1 + kb1;
@@ -148,11 +164,18 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
                                    A + k1 + (size_t)c2 * lda, lda, false));
             CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[1], 0));
         } else {
+            CDF_HIP_RET(hipStreamWaitEvent(s0, left_done[b], 0));
             CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, k1, kb1, ws));
         }
-        CDF_HIP_RET(cdf::apply_pairs(s0, 0, k1, A + k1, lda, ws.pairs));
         CDF_HIP_RET(cdf::apply_pairs(s0, k1 + kb1, n, A + k1, lda, ws.pairs));
+        // columns [0, k1): their last reader, this step's update, is done
+        CDF_HIP_RET(hipEventRecord(h->ev[2], s0));
+        CDF_HIP_RET(hipStreamWaitEvent(s2, h->ev[2], 0));
+        CDF_HIP_RET(cdf::apply_pairs(s2, 0, k1, A + k1, lda, ws.pairs));
+        CDF_HIP_RET(hipEventRecord(left_done[b], s2));
     }
+    CDF_HIP_RET(hipEventRecord(h->ev[2], s2));
+    CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[2], 0));
     return hipSuccess;
 }
 
@@ -162,6 +185,7 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
 // triangle is updated on the handle's stream.  Only the lower triangle is
 // touched; every launch after a failed pivot is a no-op (stop = info).
 hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
+    cdf::set_gemm_wg_per_cu(h->params[CDF_PARAM_GEMM_WG_PER_CU]);
     hipStream_t s0 = h->stream;
     CDF_HIP_RET(cdf::ensure_aux(h));
     hipStream_t s1 = h->aux;
@@ -225,7 +249,7 @@ hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
 
 namespace cdf {
 
-size_t getrf_ws_ints() { return kMaxLuNb + 1 + 4 * kMaxLuNb; }
+size_t getrf_ws_ints() { return kMaxLuNb + 2 * kPairsInts; }
 
 hipError_t getrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ws_ints) {
     return getrf_impl(h, n, A, lda, ipiv, info, ws_ints, ws_ints + kMaxLuNb);
@@ -295,6 +319,7 @@ cdf_status_t cdf_destroy(cdf_handle_t h) {
     (void)hipStreamSynchronize(h->stream);
     if (h->ws) (void)hipFree(h->ws);
     if (h->aux) { (void)hipStreamSynchronize(h->aux); (void)hipStreamDestroy(h->aux); }
+    if (h->aux2) { (void)hipStreamSynchronize(h->aux2); (void)hipStreamDestroy(h->aux2); }
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
     delete h;
@@ -357,6 +382,7 @@ cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value) {
     if (p == CDF_PARAM_LU_LEAF_ROWS && !(value == 0 || value == 1 || value == 2)) return bad(h, 3);
     if (p == CDF_PARAM_VBATCH_NB && !(value == 0 || value == 16)) return bad(h, 3);
     if (p == CDF_PARAM_VBATCH_WG_PER_CU && value > 2) return bad(h, 3);
+    if (p == CDF_PARAM_GEMM_WG_PER_CU && !(value == 0 || (value >= 3 && value <= 5))) return bad(h, 3);
     h->params[p] = value;
     return CDF_OK;
 }
@@ -473,6 +499,7 @@ cdf_status_t cdf_dgemm_update(cdf_handle_t h, int m, int n, int k, const double 
     if (!A) return bad(h, 5);
     if (!B) return bad(h, 7);
     if (!C) return bad(h, 9);
+    cdf::set_gemm_wg_per_cu(h->params[CDF_PARAM_GEMM_WG_PER_CU]);
     CDF_HIP_TRY(cdf::dgemm(h->stream, 0, 0, m, n, k, -1.0, A, lda, B, ldb, 1.0, C, ldc, false));
     return CDF_OK;
 }

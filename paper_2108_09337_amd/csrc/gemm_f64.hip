@@ -19,6 +19,7 @@
 // 8 tile-rows so the A and B panels an XCD touches stay in its L2.
 #include "internal.h"
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -214,6 +215,16 @@ __global__ __launch_bounds__(NT, Shape<TB>::OCC) void dgemm_kernel(int m, int n,
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void glob_void;
 
+// Workgroups resident per CU: the kernel's 32 KB of static LDS fits five in
+// a CU's 160 KB; dynamic LDS that the kernel never touches pads each one so
+// that fewer fit, leaving LDS (and registers) to kernels on other streams.
+std::atomic<int> g_dl_wgs{5};
+inline size_t dl_pad_bytes() {
+    const int w = g_dl_wgs.load(std::memory_order_relaxed);
+    if (w >= 5) return 0;
+    return (size_t)(160 * 1024 / w) / 512 * 512 - 32 * 1024;
+}
+
 template <int TB, bool LOWER>
 __global__ __launch_bounds__(NT, 5) void dgemm_dl_kernel(int m, int n, int k, double alpha,
                                                          const double *__restrict__ A, int lda,
@@ -334,7 +345,8 @@ hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double
         if (nwg <= 0) return hipSuccess;
         if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
         const int slot = cdf::prof_begin(s, kind, flops);
-        hipLaunchKernelGGL((dgemm_dl_kernel<TB, LOWER>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k, alpha, A, lda,
+        hipLaunchKernelGGL((dgemm_dl_kernel<TB, LOWER>), dim3((unsigned)nwg), dim3(NT), dl_pad_bytes(), s, m, n, k,
+                           alpha, A, lda,
                            B, ldb, beta, C, ldc, tm64, tn64, stop);
         const hipError_t e = hipGetLastError();
         cdf::prof_end(s, slot);
@@ -447,5 +459,7 @@ hipError_t dgemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alph
     if (ta == 1 && tb == 0) return launch<1, 0, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop);
     return launch<1, 1, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop);
 }
+
+void set_gemm_wg_per_cu(int w) { g_dl_wgs.store(w >= 3 && w <= 5 ? w : 5, std::memory_order_relaxed); }
 
 }  // namespace cdf

@@ -18,8 +18,9 @@ struct cdf_handle_s {
     unsigned leaf_epoch = 0;     // next epoch of the panel leaf's exchange tags
     int bad_arg = 0;
     hipStream_t aux = nullptr;   // second stream for look-ahead (default priority)
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    int params[CDF_PARAM_COUNT] = {0, 0, 0, 0, 0, 0};
+    hipStream_t aux2 = nullptr;  // third stream: LU interchanges on finished L columns
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int params[CDF_PARAM_COUNT] = {0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace cdf {
@@ -61,6 +62,11 @@ hipError_t potrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *info);
 
 // Creates the handle's second stream (default priority) and its two events.
 hipError_t ensure_aux(cdf_handle_t h);
+
+// Workgroups of the FP64 update GEMM resident per CU (3..5; 0 = 5).  The
+// factorization entry points set it from their handle before launching;
+// dgemm reads it at each launch (process-wide).
+void set_gemm_wg_per_cu(int w);
 
 // Kernel timing (process-wide): prof_begin records an event before a launch
 // and returns a slot (-1 when timing is off), prof_end records the closing

@@ -447,7 +447,10 @@ hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, 
     if (m <= 0 || n <= 0) return hipSuccess;
     if (n > LW || n > m) return hipErrorInvalidValue;
     int R = rows_per_thread;
-    if (R != 1 && R != 2) R = (m + LT - 1) / LT > h->num_cus / 2 ? 2 : 1;
+    // one row per thread whenever the grid fits the CUs: two rows per thread
+    // need more registers, so beside the update GEMM the leaf waits longer
+    // for all of its workgroups to become resident
+    if (R != 1 && R != 2) R = (m + LT - 1) / LT > h->num_cus ? 2 : 1;
     int G = (m + LT * R - 1) / (LT * R);
     if (G > h->num_cus && R == 1) { R = 2; G = (m + LT * R - 1) / (LT * R); }
     if (G > h->num_cus || G > GMAX) return hipErrorInvalidValue;

@@ -560,6 +560,7 @@ inline int mixed_nb(cdf_handle_t h, int n) {
 // updated (when the panel width is a multiple of the quantization tile, so
 // both parts of the update keep the tile exponents of U12).
 hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *ipiv, MixedWs &w, int nb, int *info) {
+    cdf::set_gemm_wg_per_cu(h->params[CDF_PARAM_GEMM_WG_PER_CU]);
     hipStream_t s0 = h->stream;
     CDF_HIP_RET(cdf::ensure_aux(h));
     hipStream_t s1 = h->aux;

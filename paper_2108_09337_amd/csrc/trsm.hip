@@ -132,10 +132,13 @@ __global__ __launch_bounds__(NT) void trsm_rltn_kernel(int nb, int nrows, const 
 // same order as above.  Fits on a CU beside the update GEMM's workgroups,
 // which take all of its LDS.
 constexpr int RNC = 64;
-template <typename TB>
-__global__ __launch_bounds__(64) void trsm_rltn_reg_kernel(int nb, int nrows, const double *__restrict__ T, int ldt,
+// FULL: nb == 64, so no entry is guarded and the compiler batches (and
+// merges) the triangle's scalar loads instead of waiting on each one.
+template <typename TB, bool FULL>
+__global__ __launch_bounds__(64) void trsm_rltn_reg_kernel(int nb_in, int nrows, const double *__restrict__ T, int ldt,
                                                            TB *__restrict__ B, int ldb, const int *stop) {
     if (stop != nullptr && *stop != 0) return;
+    const int nb = FULL ? RNC : nb_in;
     const int r = blockIdx.x * 64 + threadIdx.x;
     const bool live = r < nrows;
     double x[RNC];
@@ -145,11 +148,11 @@ __global__ __launch_bounds__(64) void trsm_rltn_reg_kernel(int nb, int nrows, co
     });
     cdf::static_for<0, RNC>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
-        if (j < nb) {
+        if (FULL || j < nb) {
             x[j] = x[j] / T[(size_t)j + (size_t)j * ldt];
             cdf::static_for<j + 1, RNC>([&](auto cc) {
                 constexpr int c = decltype(cc)::value;
-                if (c < nb) x[c] = fma(-x[j], T[(size_t)c + (size_t)j * ldt], x[c]);
+                if (FULL || c < nb) x[c] = fma(-x[j], T[(size_t)c + (size_t)j * ldt], x[c]);
             });
         }
     });
@@ -179,9 +182,14 @@ hipError_t launch_left(hipStream_t s, int nb, int ncols, const double *T, int ld
 template <typename TB>
 hipError_t launch_right(hipStream_t s, int nb, int nrows, const double *T, int ldt, TB *B, int ldb,
                         const int *stop) {
-    if (nb <= RNC) {
-        hipLaunchKernelGGL((trsm_rltn_reg_kernel<TB>), dim3((nrows + 63) / 64), dim3(64), 0, s, nb, nrows, T, ldt, B,
-                           ldb, stop);
+    if (nb == RNC) {
+        hipLaunchKernelGGL((trsm_rltn_reg_kernel<TB, true>), dim3((nrows + 63) / 64), dim3(64), 0, s, nb, nrows, T,
+                           ldt, B, ldb, stop);
+        return hipGetLastError();
+    }
+    if (nb < RNC) {
+        hipLaunchKernelGGL((trsm_rltn_reg_kernel<TB, false>), dim3((nrows + 63) / 64), dim3(64), 0, s, nb, nrows, T,
+                           ldt, B, ldb, stop);
         return hipGetLastError();
     }
     static bool attr = false;

@@ -31,6 +31,7 @@ def main():
     ap.add_argument("--lu-nb", type=int, default=0)
     ap.add_argument("--chol-nb", type=int, default=0)
     ap.add_argument("--mixed-nb", type=int, default=0)
+    ap.add_argument("--gemm-wg", type=int, default=0, help="update-GEMM workgroups per CU (3, 4 or 5)")
     ap.add_argument("--count", type=int, default=4096)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     args = ap.parse_args()
@@ -49,7 +50,8 @@ def main():
         tune.apply(h, op_key[args.op], args.n)
     if args.op == "gesv-mixed":
         tune.apply(h, "getrf", args.n)
-    for name, v in (("lu_nb", args.lu_nb), ("chol_nb", args.chol_nb), ("mixed_nb", args.mixed_nb)):
+    for name, v in (("lu_nb", args.lu_nb), ("chol_nb", args.chol_nb), ("mixed_nb", args.mixed_nb),
+                    ("gemm_wg_per_cu", args.gemm_wg)):
         if v:
             h.set_param(name, v)
     n = args.n
