@@ -14,6 +14,12 @@ __global__ void fill_int_kernel(int *p, int count, int v) {
     if (i < count) p[i] = v;
 }
 
+// X (n x n, leading dimension ld) = identity
+__global__ void eye_kernel(int n, double *X, int ld) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i < n) X[(size_t)i + (size_t)j * ld] = i == j ? 1.0 : 0.0;
+}
+
 inline cdf_status_t bad(cdf_handle_t h, int pos) {
     h->bad_arg = pos;
     return CDF_ERR_INVALID_ARG;
@@ -100,16 +106,51 @@ struct LuWs {
     int *ipt;    // region-relative pivots of the current panel
     int *pairs;  // its interchange pairs (one of the two buffers below)
     int *buf[2];
+    // Optional (both null: U12 by blocked substitution in place):
+    double *W;       // U12 of the current step, kb x (n - k - kb), leading dimension kb
+    double *Li[2];   // L11^-1 of panels p (buffer p mod 2), kMaxLuNb x kMaxLuNb
 };
+
+// L11^-1 of the unit lower triangle L11 (kb x kb) into Li: identity, then
+// blocked forward substitution (the same solve the in-place U12 path uses,
+// with the identity as right-hand side).
+hipError_t panel_inverse(hipStream_t s, int kb, const double *l11, int lda, double *Li) {
+    hipLaunchKernelGGL(eye_kernel, dim3((kb + 255) / 256, kb), dim3(256), 0, s, kb, Li, kMaxLuNb);
+    CDF_HIP_RET(hipGetLastError());
+    return cdf::trsm_blocked(s, cdf::TRSM_LLNU, kb, kb, l11, lda, Li, kMaxLuNb, 64);
+}
+
+// Columns [c, c + cols) of step k's block row: U12 = L11^-1 A12 into W
+// (columns offset by c - k1), then A22 -= L21 U12, then U12 back into A.
+// Without the inverse: blocked substitution in place, then the update.
+hipError_t u12_and_update(hipStream_t s, int n, double *A, int lda, int k, int kb, int c, int cols,
+                          const LuWs &ws, const double *Li) {
+    const int k1 = k + kb;
+    double *a12 = A + k + (size_t)c * lda;
+    const double *a21 = A + k1 + (size_t)k * lda;
+    double *a22 = A + k1 + (size_t)c * lda;
+    if (!ws.W) {
+        CDF_HIP_RET(cdf::trsm_blocked(s, cdf::TRSM_LLNU, kb, cols, A + k + (size_t)k * lda, lda, a12, lda, 64));
+        return cdf::dgemm(s, 0, 0, n - k1, cols, kb, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false);
+    }
+    double *w = ws.W + (size_t)(c - k1) * kb;
+    CDF_HIP_RET(cdf::dgemm(s, 0, 0, kb, cols, kb, 1.0, Li, kMaxLuNb, a12, lda, 0.0, w, kb, false));
+    CDF_HIP_RET(cdf::dgemm(s, 0, 0, n - k1, cols, kb, -1.0, a21, lda, w, kb, 1.0, a22, lda, false));
+    return hipMemcpy2DAsync(a12, (size_t)lda * sizeof(double), w, (size_t)kb * sizeof(double), (size_t)kb * sizeof(double),
+                            cols, hipMemcpyDeviceToDevice, s);
+}
 
 // Panel [k, k+kb) over rows [k, n) as a region: pivots relative to row k in
 // ws.ipt, absolute (1-based) in ipiv[k..k+kb), pairs built for the region.
 hipError_t factor_panel(cdf_handle_t h, hipStream_t s, int n, double *A, int lda, int *ipiv, int *info, int k,
-                        int kb, LuWs &ws) {
+                        int kb, LuWs &ws, int nb) {
     double *R = A + k + (size_t)k * lda;
     CDF_HIP_RET(cdf::lu_panel(h, s, n - k, kb, R, lda, ws.ipt, info, 0, kb, k));
     CDF_HIP_RET(cdf::offset_pivots(s, ws.ipt, ipiv + k, kb, k));
-    return cdf::build_pairs(s, ws.ipt, 0, kb, n - k, ws.pairs);
+    CDF_HIP_RET(cdf::build_pairs(s, ws.ipt, 0, kb, n - k, ws.pairs));
+    // the inverse is needed only while columns remain right of the panel
+    if (ws.W && k + kb < n) CDF_HIP_RET(panel_inverse(s, kb, R, lda, ws.Li[(k / nb) & 1]));
+    return hipSuccess;
 }
 
 // Blocked right-looking LU with look-ahead of depth one: while the trailing
@@ -119,7 +160,8 @@ hipError_t factor_panel(cdf_handle_t h, hipStream_t s, int n, double *A, int lda
 // the finished L columns to the left, which no later step reads, runs on a
 // third stream beside the next steps (panel p's pairs live in buffer p mod 2,
 // so panel p+2 waits for that stream's use of panel p's pairs).
-hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ipt, int *pairs) {
+hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ipt, int *pairs,
+                      double *W, double *Li) {
     cdf::set_gemm_wg_per_cu(h->params[CDF_PARAM_GEMM_WG_PER_CU]);
     hipStream_t s0 = h->stream;
     CDF_HIP_RET(cdf::ensure_aux(h));
@@ -132,11 +174,14 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
     ws.buf[0] = pairs;
     ws.buf[1] = pairs + kPairsInts;
     ws.pairs = ws.buf[0];
+    ws.W = W;
+    ws.Li[0] = Li;
+    ws.Li[1] = Li ? Li + (size_t)kMaxLuNb * kMaxLuNb : nullptr;
     // the third stream starts after everything already queued on the handle's
     CDF_HIP_RET(hipEventRecord(h->ev[2], s0));
     CDF_HIP_RET(hipStreamWaitEvent(s2, h->ev[2], 0));
     const int kb0 = nb < n ? nb : n;
-    CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, 0, kb0, ws));
+    CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, 0, kb0, ws, nb));
     CDF_HIP_RET(cdf::apply_pairs(s0, kb0, n, A, lda, ws.pairs));
     for (int k = 0; k < n; k += nb) {
         const int kb = nb < n - k ? nb : n - k;
@@ -146,26 +191,21 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
         const int rest = n - k1;
         const int b = (k1 / nb) & 1;  // pairs buffer of panel k1
         ws.pairs = ws.buf[b];
-        double *l11 = A + k + (size_t)k * lda;
-        double *a21 = A + k1 + (size_t)k * lda;
+        const double *li = ws.Li[(k / nb) & 1];
         // next panel's columns first
-        CDF_HIP_RET(cdf::trsm_blocked(s0, cdf::TRSM_LLNU, kb, kb1, l11, lda, A + k + (size_t)k1 * lda, lda, 64));
-        CDF_HIP_RET(cdf::dgemm(s0, 0, 0, rest, kb1, kb, -1.0, a21, lda, A + k + (size_t)k1 * lda, lda, 1.0,
-                               A + k1 + (size_t)k1 * lda, lda, false));
+        CDF_HIP_RET(u12_and_update(s0, n, A, lda, k, kb, k1, kb1, ws, li));
         if (rest > kb1) {
             CDF_HIP_RET(hipEventRecord(h->ev[0], s0));
             CDF_HIP_RET(hipStreamWaitEvent(s1, h->ev[0], 0));
             CDF_HIP_RET(hipStreamWaitEvent(s1, left_done[b], 0));
-            CDF_HIP_RET(factor_panel(h, s1, n, A, lda, ipiv, info, k1, kb1, ws));
+            CDF_HIP_RET(factor_panel(h, s1, n, A, lda, ipiv, info, k1, kb1, ws, nb));
             CDF_HIP_RET(hipEventRecord(h->ev[1], s1));
             const int c2 = k1 + kb1;
-            CDF_HIP_RET(cdf::trsm_blocked(s0, cdf::TRSM_LLNU, kb, n - c2, l11, lda, A + k + (size_t)c2 * lda, lda, 64));
-            CDF_HIP_RET(cdf::dgemm(s0, 0, 0, rest, n - c2, kb, -1.0, a21, lda, A + k + (size_t)c2 * lda, lda, 1.0,
-                                   A + k1 + (size_t)c2 * lda, lda, false));
+            CDF_HIP_RET(u12_and_update(s0, n, A, lda, k, kb, c2, n - c2, ws, li));
             CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[1], 0));
         } else {
             CDF_HIP_RET(hipStreamWaitEvent(s0, left_done[b], 0));
-            CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, k1, kb1, ws));
+            CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, k1, kb1, ws, nb));
         }
         CDF_HIP_RET(cdf::apply_pairs(s0, k1 + kb1, n, A + k1, lda, ws.pairs));
         // columns [0, k1): their last reader, this step's update, is done
@@ -252,7 +292,7 @@ namespace cdf {
 size_t getrf_ws_ints() { return kMaxLuNb + 2 * kPairsInts; }
 
 hipError_t getrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ws_ints) {
-    return getrf_impl(h, n, A, lda, ipiv, info, ws_ints, ws_ints + kMaxLuNb);
+    return getrf_impl(h, n, A, lda, ipiv, info, ws_ints, ws_ints + kMaxLuNb, nullptr, nullptr);
 }
 
 hipError_t potrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *info) {
@@ -404,11 +444,21 @@ cdf_status_t cdf_dgetrf(cdf_handle_t h, int n, double *A, int lda, int *ipiv, in
         CDF_HIP_TRY(cdf::fill_int(h->stream, info, 1, 0));
         return CDF_OK;
     }
-    cdf_status_t st = cdf::ws_reserve(h, kLuWsBytes);
-    if (st != CDF_OK) return st;
+    // U12 through L11^-1 needs kMaxLuNb x n doubles for U12 and two inverses;
+    // if the workspace cap refuses them, U12 is solved in place instead.
+    const size_t off = cdf::align_up(kLuWsBytes, 256);
+    const size_t big = off + ((size_t)kMaxLuNb * n + 2 * (size_t)kMaxLuNb * kMaxLuNb) * sizeof(double);
+    double *W = nullptr, *Li = nullptr;
+    if (cdf::ws_reserve(h, big) == CDF_OK) {
+        W = reinterpret_cast<double *>(static_cast<char *>(h->ws) + off);
+        Li = W + (size_t)kMaxLuNb * n;
+    } else {
+        cdf_status_t st = cdf::ws_reserve(h, kLuWsBytes);
+        if (st != CDF_OK) return st;
+    }
     char *base = static_cast<char *>(h->ws) + cdf::kLeafWsBytes;
     CDF_HIP_TRY(getrf_impl(h, n, A, lda, ipiv, info, reinterpret_cast<int *>(base),
-                           reinterpret_cast<int *>(base + kMaxLuNb * sizeof(int))));
+                           reinterpret_cast<int *>(base + kMaxLuNb * sizeof(int)), W, Li));
     return CDF_OK;
 }
 

@@ -184,38 +184,56 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
                     put_tag(tags + ((size_t)par * GMAX + g) * kTagWords + t, e | half);
                 }
             }
-            // 2. poll every workgroup's tags (one slot per lane)
-            const int q = wave * 64 + lane;
-            const bool act = q < G;
-            const u64 *tq = tags + ((size_t)par * GMAX + (act ? q : 0)) * kTagWords;
-            u64 w0 = 0, w1 = 0, w2 = 0;
-            bool ok;
-            do {
-                if (act) { w0 = get_tag(tq); w1 = get_tag(tq + 1); w2 = get_tag(tq + 2); }
-                ok = !act || ((w0 & ~0xffffffffull) == e && (w1 & ~0xffffffffull) == e && (w2 & ~0xffffffffull) == e);
-            } while (!__all(ok));
-            double cv = -1.0;
-            int ci = INT_MAX, cw = 0;
-            if (act) {
-                cv = __longlong_as_double((long long)((w0 << 32) | (w1 & 0xffffffffull)));
-                ci = (int)(unsigned)(w2 & 0xffffffffull);
-                cw = q;
-            }
+            // 2. wave 0 polls every workgroup's tags (up to GMAX / 64 per lane,
+            //    pausing between rounds so that the polling leaves the memory
+            //    path to kernels running beside the leaf); waves 1.. wait at
+            //    the barrier.  The winner is the largest |a|, then the
+            //    smallest row: a total order, so the reduction order is free.
+            if (wave == 0) {
+                constexpr int QPL = GMAX / 64;
+                u64 w[QPL][3];
+                bool all;
+                do {
+                    bool ok = true;
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double ov = __shfl_xor(cv, off);
-                const int oi = __shfl_xor(ci, off);
-                const int ow = __shfl_xor(cw, off);
-                if (ov > cv || (ov == cv && oi < ci)) { cv = ov; ci = oi; cw = ow; }
+                    for (int i = 0; i < QPL; ++i) {
+                        const int q = lane + 64 * i;
+                        if (q < G) {
+                            const u64 *tq = tags + ((size_t)par * GMAX + q) * kTagWords;
+                            w[i][0] = get_tag(tq);
+                            w[i][1] = get_tag(tq + 1);
+                            w[i][2] = get_tag(tq + 2);
+                            ok = ok && (w[i][0] & ~0xffffffffull) == e && (w[i][1] & ~0xffffffffull) == e &&
+                                 (w[i][2] & ~0xffffffffull) == e;
+                        }
+                    }
+                    all = __all(ok);
+                    if (!all) __builtin_amdgcn_s_sleep(1);
+                } while (!all);
+                double cv = -1.0;
+                int ci = INT_MAX, cw = 0;
+#pragma unroll
+                for (int i = 0; i < QPL; ++i) {
+                    const int q = lane + 64 * i;
+                    if (q < G) {
+                        const double ov = __longlong_as_double((long long)((w[i][0] << 32) | (w[i][1] & 0xffffffffull)));
+                        const int oi = (int)(unsigned)(w[i][2] & 0xffffffffull);
+                        if (ov > cv || (ov == cv && oi < ci)) { cv = ov; ci = oi; cw = q; }
+                    }
+                }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const double ov = __shfl_xor(cv, off);
+                    const int oi = __shfl_xor(ci, off);
+                    const int ow = __shfl_xor(cw, off);
+                    if (ov > cv || (ov == cv && oi < ci)) { cv = ov; ci = oi; cw = ow; }
+                }
+                if (lane == 0) { xv[0] = cv; xi[0] = ci; xw[0] = cw; }
             }
-            if (lane == 0) { xv[wave] = cv; xi[wave] = ci; xw[wave] = cw; }
             __syncthreads();
             v = xv[0];
             p = xi[0];
-            int win = xw[0];
-#pragma unroll
-            for (int w = 1; w < LT / 64; ++w)
-                if (xv[w] > v || (xv[w] == v && xi[w] < p)) { v = xv[w]; p = xi[w]; win = xw[w]; }
+            const int win = xw[0];
             // 3. winning row and current row j
             if (t < n) {
                 const double oj = get_dev(rowj + (size_t)par * LW + t);

@@ -105,6 +105,32 @@ def test_lu_leaf_multi_workgroup(oracle_mod, rows):
     assert oracle_mod.lu_backward_error(a, lu, ip) <= 10.0
 
 
+def test_lu_in_place_u12_under_workspace_cap(oracle_mod):
+    """Capped below U12's buffer, the LU solves U12 in place (blocked substitution)
+    instead of through L11^-1: same pivots as the oracle, same tolerance."""
+    n = 1300
+    a = workloads.lu_uniform(n, seed=4242)
+    lu_or, ip_or, _ = oracle_mod.dgetrf(a)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        h = cdf.handle()  # a fresh handle: its workspace starts empty
+        h.set_workspace_limit(4 << 20)
+        h.set_param("lu_nb", 256)
+        A = cdf.to_device(a)
+        ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+        info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+        cdf.dgetrf(A, ipiv, info, h)
+        torch.cuda.synchronize()
+        assert h.workspace_bytes() <= 4 << 20
+        lu, ip = cdf.to_host(A), ipiv.cpu().numpy()
+    assert int(info.item()) == 0
+    if not np.array_equal(ip, ip_or):
+        pytest.fail(gpu_util.first_pivot_mismatch(ip, ip_or, a, oracle_mod))
+    tol = gpu_util.lu_parity_tolerance(lu_or)
+    assert np.all(np.abs(lu - lu_or) <= tol), float(np.max(np.abs(lu - lu_or) / tol))
+    assert oracle_mod.lu_backward_error(a, lu, ip) <= 10.0
+
+
 def test_lu_singular_info(oracle_mod):
     n = 300
     a = workloads.lu_uniform(n, seed=5)
