@@ -159,7 +159,10 @@ hipError_t factor_panel(cdf_handle_t h, hipStream_t s, int n, double *A, int lda
 // applied to the trailing columns once both are done.  Their application to
 // the finished L columns to the left, which no later step reads, runs on a
 // third stream beside the next steps (panel p's pairs live in buffer p mod 2,
-// so panel p+2 waits for that stream's use of panel p's pairs).
+// so panel p+2 waits for that stream's use of panel p's pairs).  On the
+// trailing columns, only the next panel's are swapped on the handle's stream;
+// the rest are swapped on the third stream while the next panel's columns are
+// updated, and the handle's stream waits for them before updating the rest.
 hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ipt, int *pairs,
                       double *W, double *Li) {
     cdf::set_gemm_wg_per_cu(h->params[CDF_PARAM_GEMM_WG_PER_CU]);
@@ -167,6 +170,7 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
     CDF_HIP_RET(cdf::ensure_aux(h));
     hipStream_t s1 = h->aux, s2 = h->aux2;
     hipEvent_t *left_done = h->ev + 3;  // per pairs buffer
+    hipEvent_t rest_swapped = h->ev[5];
     CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
     const int nb = lu_nb(h, n);
     LuWs ws;
@@ -201,18 +205,26 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
             CDF_HIP_RET(factor_panel(h, s1, n, A, lda, ipiv, info, k1, kb1, ws, nb));
             CDF_HIP_RET(hipEventRecord(h->ev[1], s1));
             const int c2 = k1 + kb1;
+            CDF_HIP_RET(hipStreamWaitEvent(s0, rest_swapped, 0));
             CDF_HIP_RET(u12_and_update(s0, n, A, lda, k, kb, c2, n - c2, ws, li));
             CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[1], 0));
         } else {
             CDF_HIP_RET(hipStreamWaitEvent(s0, left_done[b], 0));
             CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, k1, kb1, ws, nb));
         }
-        CDF_HIP_RET(cdf::apply_pairs(s0, k1 + kb1, n, A + k1, lda, ws.pairs));
-        // columns [0, k1): their last reader, this step's update, is done
+        // panel k1's interchanges: columns [0, k1) (their last reader, this
+        // step's update, is done) and those right of the panel after next on
+        // the third stream; the next panel's columns here
+        const int c2 = k1 + kb1, kb2 = nb < n - c2 ? nb : n - c2, c3 = c2 + (kb2 > 0 ? kb2 : 0);
         CDF_HIP_RET(hipEventRecord(h->ev[2], s0));
         CDF_HIP_RET(hipStreamWaitEvent(s2, h->ev[2], 0));
+        if (c3 < n) {
+            CDF_HIP_RET(cdf::apply_pairs(s2, c3, n, A + k1, lda, ws.pairs));
+            CDF_HIP_RET(hipEventRecord(rest_swapped, s2));
+        }
         CDF_HIP_RET(cdf::apply_pairs(s2, 0, k1, A + k1, lda, ws.pairs));
         CDF_HIP_RET(hipEventRecord(left_done[b], s2));
+        CDF_HIP_RET(cdf::apply_pairs(s0, c2, c3 < n ? c3 : n, A + k1, lda, ws.pairs));
     }
     CDF_HIP_RET(hipEventRecord(h->ev[2], s2));
     CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[2], 0));

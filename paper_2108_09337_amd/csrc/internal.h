@@ -19,7 +19,7 @@ struct cdf_handle_s {
     int bad_arg = 0;
     hipStream_t aux = nullptr;   // second stream for look-ahead (default priority)
     hipStream_t aux2 = nullptr;  // third stream: LU interchanges on finished L columns
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int params[CDF_PARAM_COUNT] = {0, 0, 0, 0, 0, 0, 0};
 };
 
