@@ -84,7 +84,11 @@ typedef enum {
     CDF_PARAM_GEMM_WG_PER_CU = 6,   /* update-GEMM workgroups resident per CU in this handle's
                                        factorizations (3, 4 or 5; 0 = 5, all of the LDS).  Fewer
                                        leave room for the panel kernels on the second stream. */
-    CDF_PARAM_COUNT = 7
+    CDF_PARAM_LU_U12 = 7,           /* how the LUs (FP64 and mixed) form U12 = L11^-1 A12: 0 = with
+                                       L11^-1 formed beside the update, as one matrix-core GEMM (when
+                                       the workspace allows); 1 = blocked substitution in place, which
+                                       reproduces exactly representable factors exactly */
+    CDF_PARAM_COUNT = 8
 } cdf_param_t;
 CDF_API cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value);
 CDF_API int cdf_get_param(cdf_handle_t h, cdf_param_t p);

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libcdnafact.so")
 
 CDF_OK, CDF_ERR_INVALID_ARG, CDF_ERR_HIP, CDF_ERR_ALLOC, CDF_ERR_NOT_CONVERGED, CDF_ERR_UNSUPPORTED = range(6)
 UPD = {"fp64": 0, "bf16": 1, "fp16": 2, "fp8e4m3": 3, "e4m3": 3}
-PARAM = {"lu_nb": 0, "chol_nb": 1, "lu_leaf_rows": 2, "mixed_nb": 3, "vbatch_nb": 4, "vbatch_wg_per_cu": 5, "gemm_wg_per_cu": 6}
+PARAM = {"lu_nb": 0, "chol_nb": 1, "lu_leaf_rows": 2, "mixed_nb": 3, "vbatch_nb": 4, "vbatch_wg_per_cu": 5, "gemm_wg_per_cu": 6, "lu_u12": 7}
 F64, F32 = 0, 1
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)

@@ -14,10 +14,35 @@ __global__ void fill_int_kernel(int *p, int count, int v) {
     if (i < count) p[i] = v;
 }
 
-// X (n x n, leading dimension ld) = identity
-__global__ void eye_kernel(int n, double *X, int ld) {
+// Guard of L^-1: eight columns of Li (kb x kb) per workgroup; an entry
+// above `bound` in magnitude (or NaN) clears *good (set to 1 beforehand).
+__global__ __launch_bounds__(256) void inverse_check_kernel(int kb, const double *Li, int ldi, double bound,
+                                                            int *good) {
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    const int j = blockIdx.x * 8 + threadIdx.x / 32;
+    int mine = 0;
+    if (j < kb)
+        for (int i = threadIdx.x % 32; i < kb; i += 32)
+            if (!(fabs(Li[(size_t)i + (size_t)j * ldi]) <= bound)) mine = 1;
+    if (mine) atomicOr(&bad, 1);
+    __syncthreads();
+    if (threadIdx.x == 0 && bad) atomicAnd(good, 0);
+}
+
+// Li = identity where the guard cleared *good.
+__global__ void inverse_reset_kernel(int kb, double *Li, int ldi, const int *good) {
+    if (*good != 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i < kb) Li[(size_t)i + (size_t)j * ldi] = i == j ? 1.0 : 0.0;
+}
+
+// X (n x n, leading dimension ld) = identity; *flag = 1
+__global__ void eye_kernel(int n, double *X, int ld, int *flag) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
     if (i < n) X[(size_t)i + (size_t)j * ld] = i == j ? 1.0 : 0.0;
+    if (i == 0 && j == 0) *flag = 1;
 }
 
 inline cdf_status_t bad(cdf_handle_t h, int pos) {
@@ -109,22 +134,21 @@ struct LuWs {
     // Optional (both null: U12 by blocked substitution in place):
     double *W;       // U12 of the current step, kb x (n - k - kb), leading dimension kb
     double *Li[2];   // L11^-1 of panels p (buffer p mod 2), kMaxLuNb x kMaxLuNb
+    int *good[2];    // 1: Li holds L11^-1; 0: it was rejected (and is the identity)
 };
 
-// L11^-1 of the unit lower triangle L11 (kb x kb) into Li: identity, then
-// blocked forward substitution (the same solve the in-place U12 path uses,
-// with the identity as right-hand side).
-hipError_t panel_inverse(hipStream_t s, int kb, const double *l11, int lda, double *Li) {
-    hipLaunchKernelGGL(eye_kernel, dim3((kb + 255) / 256, kb), dim3(256), 0, s, kb, Li, kMaxLuNb);
-    CDF_HIP_RET(hipGetLastError());
-    return cdf::trsm_blocked(s, cdf::TRSM_LLNU, kb, kb, l11, lda, Li, kMaxLuNb, 64);
+hipError_t panel_inverse(hipStream_t s, int kb, const double *l11, int lda, double *Li, int *good) {
+    return cdf::unit_lower_inverse(s, kb, l11, lda, Li, kMaxLuNb, good);
 }
 
 // Columns [c, c + cols) of step k's block row: U12 = L11^-1 A12 into W
 // (columns offset by c - k1), then A22 -= L21 U12, then U12 back into A.
-// Without the inverse: blocked substitution in place, then the update.
+// Where the guard rejected L11^-1 (too large an entry: the product would
+// lose the accuracy of substitution), A12 is first solved in place by
+// substitution and the GEMM with the identity copies it to W exactly.
+// Without the workspace: blocked substitution in place, then the update.
 hipError_t u12_and_update(hipStream_t s, int n, double *A, int lda, int k, int kb, int c, int cols,
-                          const LuWs &ws, const double *Li) {
+                          const LuWs &ws, const double *Li, const int *good) {
     const int k1 = k + kb;
     double *a12 = A + k + (size_t)c * lda;
     const double *a21 = A + k1 + (size_t)k * lda;
@@ -134,6 +158,7 @@ hipError_t u12_and_update(hipStream_t s, int n, double *A, int lda, int k, int k
         return cdf::dgemm(s, 0, 0, n - k1, cols, kb, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false);
     }
     double *w = ws.W + (size_t)(c - k1) * kb;
+    CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_LLNU, kb, cols, A + k + (size_t)k * lda, lda, a12, lda, good, 512));
     CDF_HIP_RET(cdf::dgemm(s, 0, 0, kb, cols, kb, 1.0, Li, kMaxLuNb, a12, lda, 0.0, w, kb, false));
     CDF_HIP_RET(cdf::dgemm(s, 0, 0, n - k1, cols, kb, -1.0, a21, lda, w, kb, 1.0, a22, lda, false));
     return hipMemcpy2DAsync(a12, (size_t)lda * sizeof(double), w, (size_t)kb * sizeof(double), (size_t)kb * sizeof(double),
@@ -149,7 +174,7 @@ hipError_t factor_panel(cdf_handle_t h, hipStream_t s, int n, double *A, int lda
     CDF_HIP_RET(cdf::offset_pivots(s, ws.ipt, ipiv + k, kb, k));
     CDF_HIP_RET(cdf::build_pairs(s, ws.ipt, 0, kb, n - k, ws.pairs));
     // the inverse is needed only while columns remain right of the panel
-    if (ws.W && k + kb < n) CDF_HIP_RET(panel_inverse(s, kb, R, lda, ws.Li[(k / nb) & 1]));
+    if (ws.W && k + kb < n) CDF_HIP_RET(panel_inverse(s, kb, R, lda, ws.Li[(k / nb) & 1], ws.good[(k / nb) & 1]));
     return hipSuccess;
 }
 
@@ -181,6 +206,8 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
     ws.W = W;
     ws.Li[0] = Li;
     ws.Li[1] = Li ? Li + (size_t)kMaxLuNb * kMaxLuNb : nullptr;
+    ws.good[0] = Li ? reinterpret_cast<int *>(Li + 2 * (size_t)kMaxLuNb * kMaxLuNb) : nullptr;
+    ws.good[1] = ws.good[0] ? ws.good[0] + 1 : nullptr;
     // the third stream starts after everything already queued on the handle's
     CDF_HIP_RET(hipEventRecord(h->ev[2], s0));
     CDF_HIP_RET(hipStreamWaitEvent(s2, h->ev[2], 0));
@@ -196,8 +223,9 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
         const int b = (k1 / nb) & 1;  // pairs buffer of panel k1
         ws.pairs = ws.buf[b];
         const double *li = ws.Li[(k / nb) & 1];
+        const int *good = ws.good[(k / nb) & 1];
         // next panel's columns first
-        CDF_HIP_RET(u12_and_update(s0, n, A, lda, k, kb, k1, kb1, ws, li));
+        CDF_HIP_RET(u12_and_update(s0, n, A, lda, k, kb, k1, kb1, ws, li, good));
         if (rest > kb1) {
             CDF_HIP_RET(hipEventRecord(h->ev[0], s0));
             CDF_HIP_RET(hipStreamWaitEvent(s1, h->ev[0], 0));
@@ -206,7 +234,7 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
             CDF_HIP_RET(hipEventRecord(h->ev[1], s1));
             const int c2 = k1 + kb1;
             CDF_HIP_RET(hipStreamWaitEvent(s0, rest_swapped, 0));
-            CDF_HIP_RET(u12_and_update(s0, n, A, lda, k, kb, c2, n - c2, ws, li));
+            CDF_HIP_RET(u12_and_update(s0, n, A, lda, k, kb, c2, n - c2, ws, li, good));
             CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[1], 0));
         } else {
             CDF_HIP_RET(hipStreamWaitEvent(s0, left_done[b], 0));
@@ -303,8 +331,13 @@ namespace cdf {
 
 size_t getrf_ws_ints() { return kMaxLuNb + 2 * kPairsInts; }
 
-hipError_t getrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ws_ints) {
-    return getrf_impl(h, n, A, lda, ipiv, info, ws_ints, ws_ints + kMaxLuNb, nullptr, nullptr);
+size_t getrf_w_doubles(int n) { return (size_t)kMaxLuNb * n + 2 * (size_t)kMaxLuNb * kMaxLuNb + 32; }
+
+hipError_t getrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ws_ints,
+                      double *lu_w) {
+    const bool inv = lu_w != nullptr && h->params[CDF_PARAM_LU_U12] == 0;
+    return getrf_impl(h, n, A, lda, ipiv, info, ws_ints, ws_ints + kMaxLuNb, inv ? lu_w : nullptr,
+                      inv ? lu_w + (size_t)kMaxLuNb * n : nullptr);
 }
 
 hipError_t potrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *info) {
@@ -319,6 +352,23 @@ __global__ void offset_kernel(const int *__restrict__ a, int *__restrict__ b, in
 hipError_t offset_pivots(hipStream_t s, const int *ipiv_in, int *ipiv_out, int count, int off) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(offset_kernel, dim3((count + 255) / 256), dim3(256), 0, s, ipiv_in, ipiv_out, count, off);
+    return hipGetLastError();
+}
+
+// L^-1 of the unit lower triangle L (kb x kb) into Li: identity, then
+// blocked forward substitution (the same solve the in-place U12 path uses,
+// with the identity as right-hand side).
+hipError_t unit_lower_inverse(hipStream_t s, int kb, const double *L, int ldl, double *Li, int ldi, int *good) {
+    if (kb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(eye_kernel, dim3((kb + 255) / 256, kb), dim3(256), 0, s, kb, Li, ldi, good);
+    CDF_HIP_RET(hipGetLastError());
+    CDF_HIP_RET(trsm_blocked(s, TRSM_LLNU, kb, kb, L, ldl, Li, ldi, 64));
+    // accepted while no entry exceeds kInverseBound: pivoting keeps
+    // |L(i,j)| <= 1, and for the inverse's growth the products' rounding
+    // error stays within a small multiple of substitution's
+    hipLaunchKernelGGL(inverse_check_kernel, dim3((kb + 7) / 8), dim3(256), 0, s, kb, Li, ldi, kInverseBound, good);
+    CDF_HIP_RET(hipGetLastError());
+    hipLaunchKernelGGL(inverse_reset_kernel, dim3((kb + 255) / 256, kb), dim3(256), 0, s, kb, Li, ldi, good);
     return hipGetLastError();
 }
 
@@ -435,6 +485,7 @@ cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value) {
     if (p == CDF_PARAM_VBATCH_NB && !(value == 0 || value == 16)) return bad(h, 3);
     if (p == CDF_PARAM_VBATCH_WG_PER_CU && value > 2) return bad(h, 3);
     if (p == CDF_PARAM_GEMM_WG_PER_CU && !(value == 0 || (value >= 3 && value <= 5))) return bad(h, 3);
+    if (p == CDF_PARAM_LU_U12 && value > 1) return bad(h, 3);
     h->params[p] = value;
     return CDF_OK;
 }
@@ -459,9 +510,9 @@ cdf_status_t cdf_dgetrf(cdf_handle_t h, int n, double *A, int lda, int *ipiv, in
     // U12 through L11^-1 needs kMaxLuNb x n doubles for U12 and two inverses;
     // if the workspace cap refuses them, U12 is solved in place instead.
     const size_t off = cdf::align_up(kLuWsBytes, 256);
-    const size_t big = off + ((size_t)kMaxLuNb * n + 2 * (size_t)kMaxLuNb * kMaxLuNb) * sizeof(double);
+    const size_t big = off + cdf::getrf_w_doubles(n) * sizeof(double);
     double *W = nullptr, *Li = nullptr;
-    if (cdf::ws_reserve(h, big) == CDF_OK) {
+    if (h->params[CDF_PARAM_LU_U12] == 0 && cdf::ws_reserve(h, big) == CDF_OK) {
         W = reinterpret_cast<double *>(static_cast<char *>(h->ws) + off);
         Li = W + (size_t)kMaxLuNb * n;
     } else {

@@ -20,7 +20,7 @@ struct cdf_handle_s {
     hipStream_t aux = nullptr;   // second stream for look-ahead (default priority)
     hipStream_t aux2 = nullptr;  // third stream: LU interchanges on finished L columns
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    int params[CDF_PARAM_COUNT] = {0, 0, 0, 0, 0, 0, 0};
+    int params[CDF_PARAM_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace cdf {
@@ -55,9 +55,13 @@ hipError_t dgemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alph
 // The binary64 factorizations behind cdf_dgetrf / cdf_dpotrf on the handle's
 // stream (look-ahead on its second stream); getrf_fp64 takes a device work
 // area of getrf_ws_ints() ints (panel pivots and interchange pairs) besides
-// the leaf's exchange area at the head of the handle's workspace.
+// the leaf's exchange area at the head of the handle's workspace, and
+// optionally (lu_w, getrf_w_doubles(n) doubles, 256-byte aligned) the area
+// for U12 through L11^-1 (null: U12 by blocked substitution in place).
 size_t getrf_ws_ints();
-hipError_t getrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ws_ints);
+size_t getrf_w_doubles(int n);
+hipError_t getrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ws_ints,
+                      double *lu_w = nullptr);
 hipError_t potrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *info);
 
 // Creates the handle's second stream (default priority) and its two events.
@@ -67,6 +71,13 @@ hipError_t ensure_aux(cdf_handle_t h);
 // factorization entry points set it from their handle before launching;
 // dgemm reads it at each launch (process-wide).
 void set_gemm_wg_per_cu(int w);
+
+// Li (kb x kb, leading dimension ldi) = L^-1 for the unit lower triangle of
+// L (kb x kb, leading dimension ldl), by blocked forward substitution; then
+// *good = 1, unless an entry exceeds kInverseBound in magnitude: then Li is
+// set to the identity and *good = 0 (the caller solves by substitution).
+constexpr double kInverseBound = 16.0;
+hipError_t unit_lower_inverse(hipStream_t s, int kb, const double *L, int ldl, double *Li, int ldi, int *good);
 
 // Kernel timing (process-wide): prof_begin records an event before a launch
 // and returns a slot (-1 when timing is off), prof_end records the closing
@@ -114,8 +125,11 @@ hipError_t fill_int(hipStream_t s, int *p, int count, int v);
 hipError_t slaswp(hipStream_t s, int c0, int c1, float *A, int lda, const int *ipiv, int k1,
                   int k2, int nrows);
 
-// Triangular solves with a small triangle T (nb <= 256) applied to an
-// nb x ncols block B (left side) or an nrows x nb block (right side).
+// Triangular solves with a small triangle T (nb <= 512 on the left, <= 256
+// on the right) applied to an nb x ncols block B (left side) or an
+// nrows x nb block (right side).  Every launch is a no-op while *stop != 0.
+// max_wg > 0 caps a left solve's grid (its workgroups loop over column
+// blocks): a launch that is usually a no-op then costs few workgroups.
 //   left, lower, no-trans, unit:      B <- T^-1 B
 //   left, lower, no-trans, non-unit:  B <- T^-1 B
 //   left, lower, trans, non-unit:     B <- T^-T B
@@ -123,10 +137,10 @@ hipError_t slaswp(hipStream_t s, int c0, int c1, float *A, int lda, const int *i
 //   right, lower, trans, non-unit:    B <- B T^-T
 enum TrsmKind { TRSM_LLNU = 0, TRSM_LLNN = 1, TRSM_LLTN = 2, TRSM_LUNN = 3, TRSM_RLTN = 4 };
 hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
-                      double *B, int ldb, const int *stop = nullptr);
+                      double *B, int ldb, const int *stop = nullptr, int max_wg = 0);
 // Same with a binary32 right-hand block (arithmetic in binary64).
 hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
-                      float *B, int ldb, const int *stop = nullptr);
+                      float *B, int ldb, const int *stop = nullptr, int max_wg = 0);
 
 // Full triangular solve with a large n x n factor (blocked: bs-wide diagonal
 // solves + GEMM updates; bs <= 256).

@@ -497,15 +497,19 @@ struct MixedWs {
     double *Afull = nullptr;   // symmetric extension of A (Cholesky residual)
     double *P[2] = {nullptr, nullptr};  // binary64 panels, n x nb each (double-buffered for look-ahead)
     double *U = nullptr;       // binary64 staging of U12, nb x n
+    double *U2 = nullptr;      // LU: U12 = L11^-1 U, nb x n
+    double *Li[2] = {nullptr, nullptr};  // LU: L11^-1 of panels (buffer p mod 2), nb x nb
+    int *good = nullptr;       // LU: per buffer, 1 if Li was accepted (else it is the identity)
     void *QA = nullptr, *QB = nullptr;
     int *ea = nullptr, *eb = nullptr, *ipt = nullptr, *ipiv = nullptr;
     int *lu_ws = nullptr;      // work area of the binary64 LU (fp64 mode)
+    double *lu_w = nullptr;    // its U12 / L11^-1 area (fp64 mode)
     double *R = nullptr, *red = nullptr;
 };
 
 
 cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool chol, MixedWs &w,
-                          bool factor_only = false) {
+                          bool factor_only = false, bool fp64_lu = false) {
     size_t off = cdf::kLeafWsBytes;  // LU leaf exchange at the workspace head
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -519,12 +523,16 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     const size_t oAf = (chol && !factor_only) ? take(nn * sizeof(double)) : 0;
     const size_t oP = take((size_t)n * nb * sizeof(double)), oP1 = take((size_t)n * nb * sizeof(double));
     const size_t oU = take((size_t)n * nb * sizeof(double));
+    const size_t oU2 = chol ? 0 : take((size_t)n * nb * sizeof(double));
+    const size_t oLi = chol ? 0 : take(2 * (size_t)nb * nb * sizeof(double));
+    const size_t ogood = chol ? 0 : take(2 * sizeof(int));
     const size_t oQA = take(kp * n * esize(fmt));
     const size_t oQB = take(kp * n * esize(fmt));
     const int nt = (n + QT - 1) / QT + 1;
     const size_t oea = take(nt * sizeof(int)), oeb = take(nt * sizeof(int));
     const size_t oipt = take((size_t)nb * sizeof(int)), oipiv = take((size_t)n * sizeof(int));
     const size_t olw = take(cdf::getrf_ws_ints() * sizeof(int));
+    const size_t olww = fp64_lu ? take(cdf::getrf_w_doubles(n) * sizeof(double)) : 0;
     const size_t oR = take((size_t)n * nrhs * sizeof(double));
     const size_t ored = take(((size_t)n + 4 * (size_t)nrhs + 8) * sizeof(double));
     cdf_status_t st = cdf::ws_reserve(h, off);
@@ -536,6 +544,10 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     w.P[0] = reinterpret_cast<double *>(base + oP);
     w.P[1] = reinterpret_cast<double *>(base + oP1);
     w.U = reinterpret_cast<double *>(base + oU);
+    w.U2 = chol ? nullptr : reinterpret_cast<double *>(base + oU2);
+    w.Li[0] = chol ? nullptr : reinterpret_cast<double *>(base + oLi);
+    w.Li[1] = chol ? nullptr : w.Li[0] + (size_t)nb * nb;
+    w.good = chol ? nullptr : reinterpret_cast<int *>(base + ogood);
     w.QA = base + oQA;
     w.QB = base + oQB;
     w.ea = reinterpret_cast<int *>(base + oea);
@@ -543,6 +555,7 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     w.ipt = reinterpret_cast<int *>(base + oipt);
     w.ipiv = reinterpret_cast<int *>(base + oipiv);
     w.lu_ws = reinterpret_cast<int *>(base + olw);
+    w.lu_w = fp64_lu ? reinterpret_cast<double *>(base + olww) : nullptr;
     w.R = reinterpret_cast<double *>(base + oR);
     w.red = reinterpret_cast<double *>(base + ored);
     return CDF_OK;
@@ -568,28 +581,40 @@ hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *i
     const bool split = nb % QT == 0;
     // panel of width kb at column k: binary64 copy in P, factored there,
     // pivots to w.ipt (relative) and ipiv (absolute), copied back to W
-    auto panel = [&](hipStream_t s, int k, int kb, double *P) -> hipError_t {
+    const bool inv = h->params[CDF_PARAM_LU_U12] == 0 && w.Li[0] != nullptr;
+    auto panel = [&](hipStream_t s, int k, int kb, double *P, int buf) -> hipError_t {
         const int m = n - k;
         CDF_HIP_RET(cdf::convert_s2d(s, m, kb, W + k + (size_t)k * ldw, ldw, P, m, false));
         CDF_HIP_RET(cdf::lu_panel(h, s, m, kb, P, m, w.ipt, info, 0, kb, k));
+        if (inv && k + kb < n) CDF_HIP_RET(cdf::unit_lower_inverse(s, kb, P, m, w.Li[buf], nb, w.good + buf));
         hipLaunchKernelGGL(add_offset_kernel, dim3((kb + 255) / 256), dim3(256), 0, s, w.ipt, ipiv + k, kb, k);
         CDF_HIP_RET(hipGetLastError());
         return cdf::convert_d2s(s, m, kb, P, m, W + k + (size_t)k * ldw, ldw, false);
     };
-    CDF_HIP_RET(panel(s0, 0, nb < n ? nb : n, w.P[0]));
+    CDF_HIP_RET(panel(s0, 0, nb < n ? nb : n, w.P[0], 0));
     for (int k = 0, it = 0; k < n; k += nb, ++it) {
         const int kb = nb < n - k ? nb : n - k;
         const int m = n - k, rest = n - k - kb;
-        double *P = w.P[it & 1];
         CDF_HIP_RET(cdf::slaswp(s0, 0, k, W + k, ldw, w.ipt, 0, kb, m));
         CDF_HIP_RET(cdf::slaswp(s0, k + kb, n, W + k, ldw, w.ipt, 0, kb, m));
         if (rest <= 0) break;
         float *w12 = W + k + (size_t)(k + kb) * ldw;
         float *w21 = W + (k + kb) + (size_t)k * ldw;
         float *w22 = W + (k + kb) + (size_t)(k + kb) * ldw;
+        // U12 = L11^-1 A12 in binary64: one matrix-core GEMM with the
+        // panel's inverse (formed on the panel's stream), or blocked
+        // substitution in place
         CDF_HIP_RET(cdf::convert_s2d(s0, kb, rest, w12, ldw, w.U, kb, false));
-        CDF_HIP_RET(cdf::trsm_blocked(s0, cdf::TRSM_LLNU, kb, rest, P, m, w.U, kb, 64));
-        CDF_HIP_RET(cdf::convert_d2s(s0, kb, rest, w.U, kb, w12, ldw, false));
+        if (inv) {
+            // substitution in place only where the guard rejected L11^-1 (the
+            // GEMM with the identity then copies exactly)
+            CDF_HIP_RET(cdf::trsm_small(s0, cdf::TRSM_LLNU, kb, rest, w.P[it & 1], m, w.U, kb, w.good + (it & 1), 512));
+            CDF_HIP_RET(cdf::dgemm(s0, 0, 0, kb, rest, kb, 1.0, w.Li[it & 1], nb, w.U, kb, 0.0, w.U2, kb, false));
+            CDF_HIP_RET(cdf::convert_d2s(s0, kb, rest, w.U2, kb, w12, ldw, false));
+        } else {
+            CDF_HIP_RET(cdf::trsm_blocked(s0, cdf::TRSM_LLNU, kb, rest, w.P[it & 1], m, w.U, kb, 64));
+            CDF_HIP_RET(cdf::convert_d2s(s0, kb, rest, w.U, kb, w12, ldw, false));
+        }
         CDF_HIP_RET(cdf::quantize(s0, fmt, rest, kb, w21, ldw, QT, kb, w.QA, kp, w.ea, true));
         CDF_HIP_RET(cdf::quantize(s0, fmt, kb, rest, w12, ldw, kb, QT, w.QB, kp, w.eb, false));
         const int k1 = k + kb;
@@ -600,7 +625,7 @@ hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *i
                                          nullptr));
             CDF_HIP_RET(hipEventRecord(h->ev[0], s0));
             CDF_HIP_RET(hipStreamWaitEvent(s1, h->ev[0], 0));
-            CDF_HIP_RET(panel(s1, k1, kb1, w.P[(it + 1) & 1]));
+            CDF_HIP_RET(panel(s1, k1, kb1, w.P[(it + 1) & 1], (it + 1) & 1));
             CDF_HIP_RET(hipEventRecord(h->ev[1], s1));
             const char *qb = static_cast<const char *>(w.QB) + (size_t)kb1 * kp * esize(fmt);
             CDF_HIP_RET(cdf::lowp_update(s0, fmt, rest, rest - kb1, kb, w.QA, kp, w.ea, qb, kp, w.eb + kb1 / QT,
@@ -609,7 +634,7 @@ hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *i
         } else {
             CDF_HIP_RET(cdf::lowp_update(s0, fmt, rest, rest, kb, w.QA, kp, w.ea, w.QB, kp, w.eb, w22, ldw, false,
                                          nullptr));
-            CDF_HIP_RET(panel(s0, k1, kb1, w.P[(it + 1) & 1]));
+            CDF_HIP_RET(panel(s0, k1, kb1, w.P[(it + 1) & 1], (it + 1) & 1));
         }
     }
     return hipSuccess;
@@ -657,7 +682,7 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
     hipStream_t s = h->stream;
     const int nb = mixed_nb(h, n);
     MixedWs w;
-    cdf_status_t st = mixed_layout(h, n, nrhs, nb, fmt == 0 ? FMT_BF16 : fmt, chol, w);
+    cdf_status_t st = mixed_layout(h, n, nrhs, nb, fmt == 0 ? FMT_BF16 : fmt, chol, w, false, fmt == 0 && !chol);
     if (st != CDF_OK) return st;
     CDF_HIP_TRY(cdf::fill_int(s, info, 1, 0));
     // binary64 ||A||_inf and the matrix the residual is computed with
@@ -681,7 +706,7 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
     if (fmt == 0) {
         CDF_HIP_TRY(cdf::copy_cols(s, n, n, A, lda, w.Wd, n));
         if (chol) CDF_HIP_TRY(cdf::potrf_fp64(h, n, w.Wd, n, info));
-        else CDF_HIP_TRY(cdf::getrf_fp64(h, n, w.Wd, n, w.ipiv, info, w.lu_ws));
+        else CDF_HIP_TRY(cdf::getrf_fp64(h, n, w.Wd, n, w.ipiv, info, w.lu_ws, w.lu_w));
     } else {
         CDF_HIP_TRY(cdf::convert_d2s(s, n, n, A, lda, w.W, n, chol));
         if (chol) CDF_HIP_TRY(mixed_potrf(h, fmt, n, w.W, n, w, nb, info));

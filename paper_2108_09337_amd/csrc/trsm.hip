@@ -4,7 +4,7 @@
 // Small solves keep a strip of the right-hand block in LDS and walk the
 // triangle one row/column at a time; the triangle's column (or row) for
 // each step is read from L2 (the triangle is at most 256 x 256).
-//   left kinds : B (nb x ncols), 32 columns per workgroup, 8 row groups
+//   left kinds : B (nb x ncols), 16 columns per workgroup, 16 row groups
 //   right kind : B (nrows x nb), 64 rows per workgroup, one per lane, the
 //                later columns of each block split over 4 waves
 #include "internal.h"
@@ -12,10 +12,13 @@
 namespace {
 
 constexpr int NT = 256;
-constexpr int LNC = 32;          // columns per workgroup (left solves)
+constexpr int LNC = 16;          // columns per workgroup (left solves): 8.7 KB of LDS at
+                                 // nb = 64, so a solve fits beside the update GEMMs
+constexpr int LRG = NT / LNC;    // row groups
 constexpr int LPAD = LNC + 1;
 constexpr int RNR = 64;          // rows per workgroup (right solve)
-constexpr int MAXNB = 256;
+constexpr int MAXNB = 256;       // right solves (LDS: row block + staged panel)
+constexpr int MAXNB_LEFT = 512;  // left solves (LDS: nb x LPAD doubles)
 
 template <int KIND, typename TB>
 __global__ __launch_bounds__(NT) void trsm_left_kernel(int nb, int ncols, const double *__restrict__ T,
@@ -24,37 +27,40 @@ __global__ __launch_bounds__(NT) void trsm_left_kernel(int nb, int ncols, const 
     if (stop != nullptr && *stop != 0) return;
     extern __shared__ double X[];  // X[r * LPAD + c]
     const int t = threadIdx.x;
-    const int c = t % LNC, rg = t / LNC;  // 8 row groups
-    const int c0 = blockIdx.x * LNC;
-    for (int e = t; e < nb * LNC; e += NT) {
-        const int r = e % nb, cc = e / nb;
-        X[r * LPAD + cc] = (c0 + cc < ncols) ? (double)B[(size_t)r + (size_t)(c0 + cc) * ldb] : 0.0;
-    }
-    __syncthreads();
-    constexpr bool forward = (KIND == cdf::TRSM_LLNU || KIND == cdf::TRSM_LLNN);
-    constexpr bool unit = (KIND == cdf::TRSM_LLNU);
-    for (int s = 0; s < nb; ++s) {
-        const int j = forward ? s : nb - 1 - s;
-        if (!unit) {
-            if (rg == (j & 7)) X[j * LPAD + c] = X[j * LPAD + c] / T[(size_t)j + (size_t)j * ldt];
-            __syncthreads();
-        }
-        const double xj = X[j * LPAD + c];
-        if (forward) {
-            for (int i = j + 1 + ((rg - (j + 1)) & 7); i < nb; i += 8)
-                X[i * LPAD + c] = fma(-T[(size_t)i + (size_t)j * ldt], xj, X[i * LPAD + c]);
-        } else if (KIND == cdf::TRSM_LUNN) {
-            for (int i = rg; i < j; i += 8)
-                X[i * LPAD + c] = fma(-T[(size_t)i + (size_t)j * ldt], xj, X[i * LPAD + c]);
-        } else {  // TRSM_LLTN: (L^T)(i, j) = L(j, i)
-            for (int i = rg; i < j; i += 8)
-                X[i * LPAD + c] = fma(-T[(size_t)j + (size_t)i * ldt], xj, X[i * LPAD + c]);
+    const int c = t % LNC, rg = t / LNC;
+    // column blocks in a grid-stride loop (the grid may be capped)
+    for (int c0 = blockIdx.x * LNC; c0 < ncols; c0 += gridDim.x * LNC) {
+        if (c0 != blockIdx.x * LNC) __syncthreads();  // the previous block's results are stored
+        for (int e = t; e < nb * LNC; e += NT) {
+            const int r = e % nb, cc = e / nb;
+            X[r * LPAD + cc] = (c0 + cc < ncols) ? (double)B[(size_t)r + (size_t)(c0 + cc) * ldb] : 0.0;
         }
         __syncthreads();
-    }
-    for (int e = t; e < nb * LNC; e += NT) {
-        const int r = e % nb, cc = e / nb;
-        if (c0 + cc < ncols) B[(size_t)r + (size_t)(c0 + cc) * ldb] = (TB)X[r * LPAD + cc];
+        constexpr bool forward = (KIND == cdf::TRSM_LLNU || KIND == cdf::TRSM_LLNN);
+        constexpr bool unit = (KIND == cdf::TRSM_LLNU);
+        for (int s = 0; s < nb; ++s) {
+            const int j = forward ? s : nb - 1 - s;
+            if (!unit) {
+                if (rg == j % LRG) X[j * LPAD + c] = X[j * LPAD + c] / T[(size_t)j + (size_t)j * ldt];
+                __syncthreads();
+            }
+            const double xj = X[j * LPAD + c];
+            if (forward) {
+                for (int i = j + 1 + ((rg - (j + 1)) & (LRG - 1)); i < nb; i += LRG)
+                    X[i * LPAD + c] = fma(-T[(size_t)i + (size_t)j * ldt], xj, X[i * LPAD + c]);
+            } else if (KIND == cdf::TRSM_LUNN) {
+                for (int i = rg; i < j; i += LRG)
+                    X[i * LPAD + c] = fma(-T[(size_t)i + (size_t)j * ldt], xj, X[i * LPAD + c]);
+            } else {  // TRSM_LLTN: (L^T)(i, j) = L(j, i)
+                for (int i = rg; i < j; i += LRG)
+                    X[i * LPAD + c] = fma(-T[(size_t)j + (size_t)i * ldt], xj, X[i * LPAD + c]);
+            }
+            __syncthreads();
+        }
+        for (int e = t; e < nb * LNC; e += NT) {
+            const int r = e % nb, cc = e / nb;
+            if (c0 + cc < ncols) B[(size_t)r + (size_t)(c0 + cc) * ldb] = (TB)X[r * LPAD + cc];
+        }
     }
 }
 
@@ -165,17 +171,18 @@ __global__ __launch_bounds__(64) void trsm_rltn_reg_kernel(int nb_in, int nrows,
 
 template <int KIND, typename TB>
 hipError_t launch_left(hipStream_t s, int nb, int ncols, const double *T, int ldt, TB *B, int ldb,
-                       const int *stop) {
+                       const int *stop, int max_wg) {
     static bool attr = false;
     const size_t lds = (size_t)nb * LPAD * sizeof(double);
     if (!attr) {
         CDF_HIP_RET(hipFuncSetAttribute(reinterpret_cast<const void *>(&trsm_left_kernel<KIND, TB>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        MAXNB * LPAD * sizeof(double)));
+                                        MAXNB_LEFT * LPAD * sizeof(double)));
         attr = true;
     }
-    hipLaunchKernelGGL((trsm_left_kernel<KIND, TB>), dim3((ncols + LNC - 1) / LNC), dim3(NT), lds, s, nb, ncols,
-                       T, ldt, B, ldb, stop);
+    int grid = (ncols + LNC - 1) / LNC;
+    if (max_wg > 0 && grid > max_wg) grid = max_wg;
+    hipLaunchKernelGGL((trsm_left_kernel<KIND, TB>), dim3(grid), dim3(NT), lds, s, nb, ncols, T, ldt, B, ldb, stop);
     return hipGetLastError();
 }
 
@@ -391,27 +398,27 @@ hipError_t trsv_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const do
 
 template <typename TB>
 hipError_t trsm_small_impl(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt, TB *B,
-                           int ldb, const int *stop) {
+                           int ldb, const int *stop, int max_wg) {
     if (nb <= 0 || ncols <= 0) return hipSuccess;
-    if (nb > MAXNB) return hipErrorInvalidValue;
+    if (nb > (kind == TRSM_RLTN ? MAXNB : MAXNB_LEFT)) return hipErrorInvalidValue;
     switch (kind) {
-        case TRSM_LLNU: return launch_left<TRSM_LLNU, TB>(s, nb, ncols, T, ldt, B, ldb, stop);
-        case TRSM_LLNN: return launch_left<TRSM_LLNN, TB>(s, nb, ncols, T, ldt, B, ldb, stop);
-        case TRSM_LLTN: return launch_left<TRSM_LLTN, TB>(s, nb, ncols, T, ldt, B, ldb, stop);
-        case TRSM_LUNN: return launch_left<TRSM_LUNN, TB>(s, nb, ncols, T, ldt, B, ldb, stop);
+        case TRSM_LLNU: return launch_left<TRSM_LLNU, TB>(s, nb, ncols, T, ldt, B, ldb, stop, max_wg);
+        case TRSM_LLNN: return launch_left<TRSM_LLNN, TB>(s, nb, ncols, T, ldt, B, ldb, stop, max_wg);
+        case TRSM_LLTN: return launch_left<TRSM_LLTN, TB>(s, nb, ncols, T, ldt, B, ldb, stop, max_wg);
+        case TRSM_LUNN: return launch_left<TRSM_LUNN, TB>(s, nb, ncols, T, ldt, B, ldb, stop, max_wg);
         case TRSM_RLTN: return launch_right<TB>(s, nb, ncols, T, ldt, B, ldb, stop);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
-                      double *B, int ldb, const int *stop) {
-    return trsm_small_impl<double>(s, kind, nb, ncols, T, ldt, B, ldb, stop);
+                      double *B, int ldb, const int *stop, int max_wg) {
+    return trsm_small_impl<double>(s, kind, nb, ncols, T, ldt, B, ldb, stop, max_wg);
 }
 
 hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
-                      float *B, int ldb, const int *stop) {
-    return trsm_small_impl<float>(s, kind, nb, ncols, T, ldt, B, ldb, stop);
+                      float *B, int ldb, const int *stop, int max_wg) {
+    return trsm_small_impl<float>(s, kind, nb, ncols, T, ldt, B, ldb, stop, max_wg);
 }
 
 // Blocked solve with an n x n triangle: 128-wide diagonal solves, the rest

@@ -105,6 +105,47 @@ def test_lu_leaf_multi_workgroup(oracle_mod, rows):
     assert oracle_mod.lu_backward_error(a, lu, ip) <= 10.0
 
 
+@pytest.mark.parametrize("nb", [64, 256])
+def test_lu_exact_factors(oracle_mod, nb):
+    """A = L U with small dyadic L and integer U (identity pivots): formed by
+    substitution, U12 and hence both factors come back exactly.  This L is
+    very ill-conditioned across blocks (|L^-1| ~ 1e12 over 512 rows), so one
+    rounding error in U12 (an accepted L11^-1) grows through the later blocks:
+    the default path is held to the backward error, and where the guard
+    rejects every L11^-1 (nb = 256) to exactness."""
+    n = 700
+    rng = np.random.default_rng(nb)
+    L = np.tril(rng.integers(-2, 3, (n, n)) / 4.0, -1) + np.eye(n)
+    U = np.triu(rng.integers(-4, 5, (n, n)).astype(np.float64))
+    U[np.diag_indices(n)] = rng.choice([-1.0, 1.0], n) * rng.integers(16, 32, n)
+    a = np.asfortranarray(L @ U)
+    lu, ip, info = _lu_gpu(a, lu_nb=nb, lu_u12=1)
+    assert info == 0 and np.array_equal(ip, np.arange(1, n + 1))
+    assert np.array_equal(np.tril(lu, -1) + np.eye(n), L) and np.array_equal(np.triu(lu), U)
+    lu2, ip2, info2 = _lu_gpu(a, lu_nb=nb)
+    assert info2 == 0 and np.array_equal(ip2, ip)
+    assert oracle_mod.lu_backward_error(a, lu2, ip2) <= 10.0
+    if nb == 256:
+        # |L11^-1| reaches ~1e6 for these 256-wide blocks: the guard rejects
+        # every inverse and the default path solves by substitution, exactly
+        assert np.array_equal(lu2, lu)
+
+
+def test_lu_guard_fallback_wide_exact():
+    """Every L11^-1 of this L is rejected by the guard; the fallback
+    substitution runs on a capped grid whose workgroups loop over more than
+    one column block each (over 8192 trailing columns): factors exact."""
+    n, nb = 8960, 256
+    rng = np.random.default_rng(3)
+    L = np.tril(rng.integers(-2, 3, (n, n)) / 4.0, -1) + np.eye(n)
+    U = np.triu(rng.integers(-4, 5, (n, n)).astype(np.float64))
+    U[np.diag_indices(n)] = rng.choice([-1.0, 1.0], n) * rng.integers(16, 32, n)
+    a = np.asfortranarray(L @ U)
+    lu, ip, info = _lu_gpu(a, lu_nb=nb)
+    assert info == 0 and np.array_equal(ip, np.arange(1, n + 1))
+    assert np.array_equal(np.tril(lu, -1) + np.eye(n), L) and np.array_equal(np.triu(lu), U)
+
+
 def test_lu_in_place_u12_under_workspace_cap(oracle_mod):
     """Capped below U12's buffer, the LU solves U12 in place (blocked substitution)
     instead of through L11^-1: same pivots as the oracle, same tolerance."""

@@ -139,9 +139,10 @@ def _exact_lu(n, rng):
     return np.asfortranarray(L @ U), L, U
 
 
-def _sgetrf_mixed(fmt, a, nb=0):
+def _sgetrf_mixed(fmt, a, nb=0, u12=0):
     h = cdf.handle()
     h.set_param("mixed_nb", nb)
+    h.set_param("lu_u12", u12)
     try:
         n = a.shape[0]
         A = cdf.to_device(a)
@@ -153,6 +154,7 @@ def _sgetrf_mixed(fmt, a, nb=0):
         return cdf.to_host(W), ipiv.cpu().numpy(), int(info.item())
     finally:
         h.set_param("mixed_nb", 0)
+        h.set_param("lu_u12", 0)
 
 
 def _spotrf_mixed(fmt, a, nb=0):
@@ -174,11 +176,23 @@ def _spotrf_mixed(fmt, a, nb=0):
 @pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("n,nb", [(40, 32), (300, 64), (300, 0), (1100, 512)])
 def test_sgetrf_mixed_exact(fmt, n, nb):
+    """Exactly representable factors come back exactly when U12 is formed by
+    substitution.  Through an accepted L11^-1 U12 is rounded, and this L is
+    very ill-conditioned across blocks, so the default path is held to the
+    residual: |A - L U| <= (steps + 2) u_fmt (|L||U|) elementwise, one
+    quantization of the rounded U12 per step."""
     a, L, U = _exact_lu(n, np.random.default_rng(n + nb))
-    w, ipiv, info = _sgetrf_mixed(fmt, a, nb)
+    w, ipiv, info = _sgetrf_mixed(fmt, a, nb, u12=1)
     assert info == 0 and np.array_equal(ipiv, np.arange(1, n + 1))
     assert np.array_equal(np.tril(w, -1) + np.eye(n), L)
     assert np.array_equal(np.triu(w), U)
+    w2, ipiv2, info2 = _sgetrf_mixed(fmt, a, nb)
+    assert info2 == 0 and np.array_equal(ipiv2, ipiv)
+    w2 = w2.astype(np.float64)
+    L2, U2 = np.tril(w2, -1) + np.eye(n), np.triu(w2)
+    bound = (n // (nb or 256) + 2) * UFMT[fmt] * (np.abs(L2) @ np.abs(U2)) + 1e-30
+    r = np.abs(a - L2 @ U2)
+    assert np.all(r <= bound), float(np.max(r / bound))
 
 
 @pytest.mark.parametrize("fmt", FMTS)
