@@ -38,6 +38,49 @@ __global__ __launch_bounds__(NT) void trsm_left_kernel(int nb, int ncols, const 
         __syncthreads();
         constexpr bool forward = (KIND == cdf::TRSM_LLNU || KIND == cdf::TRSM_LLNN);
         constexpr bool unit = (KIND == cdf::TRSM_LLNU);
+        if (forward && nb <= 4 * LRG) {
+            // Forward solve with at most four rows per thread: the triangle's
+            // entries of step j + 1 are loaded during step j, and the step
+            // barrier waits for LDS only (not for those loads), so no step
+            // waits on a global load.  Same updates in the same order as the
+            // general loop below.
+            double ta[4], tb[4], da = 0.0, db = 0.0;
+            auto load = [&](int j, double (&t)[4], double &d) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = rg + LRG * q;
+                    t[q] = i < nb ? T[(size_t)i + (size_t)j * ldt] : 0.0;
+                }
+                if (!unit) d = T[(size_t)j + (size_t)j * ldt];
+            };
+            auto lds_barrier = [] {
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vector loads may stay in flight
+                __builtin_amdgcn_s_barrier();
+                asm volatile("" ::: "memory");
+            };
+            auto step = [&](int j, const double (&t)[4], double d) {
+                if (!unit) {
+                    if (rg == j % LRG) X[j * LPAD + c] = X[j * LPAD + c] / d;
+                    lds_barrier();
+                }
+                const double xj = X[j * LPAD + c];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = rg + LRG * q;
+                    if (i > j && i < nb) X[i * LPAD + c] = fma(-t[q], xj, X[i * LPAD + c]);
+                }
+                lds_barrier();
+            };
+            load(0, ta, da);
+            for (int j = 0; j < nb; j += 2) {
+                if (j + 1 < nb) load(j + 1, tb, db);
+                step(j, ta, da);
+                if (j + 1 >= nb) break;
+                if (j + 2 < nb) load(j + 2, ta, da);
+                step(j + 1, tb, db);
+            }
+        } else
         for (int s = 0; s < nb; ++s) {
             const int j = forward ? s : nb - 1 - s;
             if (!unit) {
