@@ -525,6 +525,14 @@ cdf_status_t cdf_dgetrf(cdf_handle_t h, int n, double *A, int lda, int *ipiv, in
     return CDF_OK;
 }
 
+// Flag area of the single-launch few-right-hand-side solves, after the leaf's
+// exchange area (the LU's own work area there is idle once it has returned
+// on this stream); null (one launch per block) if the workspace cannot grow.
+static int *solve_sync(cdf_handle_t h, int n) {
+    if (cdf::ws_reserve(h, cdf::kLeafWsBytes + cdf::trsv_sync_ints(n) * sizeof(int)) != CDF_OK) return nullptr;
+    return reinterpret_cast<int *>(static_cast<char *>(h->ws) + cdf::kLeafWsBytes);
+}
+
 cdf_status_t cdf_dgetrs(cdf_handle_t h, char trans, int n, int nrhs, const double *A, int lda, const int *ipiv,
                         double *B, int ldb) {
     if (!h) return CDF_ERR_INVALID_ARG;
@@ -544,8 +552,9 @@ cdf_status_t cdf_dgetrs(cdf_handle_t h, char trans, int n, int nrhs, const doubl
     hipStream_t s = h->stream;
     CDF_HIP_TRY(cdf::laswp(s, 0, nrhs, B, ldb, ipiv, 0, n, n));
     if (nrhs <= 4) {
-        CDF_HIP_TRY(cdf::trsv_blocked(s, cdf::TRSM_LLNU, n, nrhs, A, lda, B, ldb));
-        CDF_HIP_TRY(cdf::trsv_blocked(s, cdf::TRSM_LUNN, n, nrhs, A, lda, B, ldb));
+        int *sync = solve_sync(h, n);
+        CDF_HIP_TRY(cdf::trsv_blocked(s, cdf::TRSM_LLNU, n, nrhs, A, lda, B, ldb, sync));
+        CDF_HIP_TRY(cdf::trsv_blocked(s, cdf::TRSM_LUNN, n, nrhs, A, lda, B, ldb, sync));
         return CDF_OK;
     }
     CDF_HIP_TRY(cdf::trsm_blocked(s, cdf::TRSM_LLNU, n, nrhs, A, lda, B, ldb));
@@ -589,7 +598,7 @@ cdf_status_t cdf_dpotrs(cdf_handle_t h, char uplo, int n, int nrhs, const double
     if (!B) return bad(h, 7);
     hipStream_t s = h->stream;
     if (nrhs <= 4) {
-        CDF_HIP_TRY(cdf::trsv_blocked(s, cdf::TRSM_LLNN, n, nrhs, A, lda, B, ldb));
+        CDF_HIP_TRY(cdf::trsv_blocked(s, cdf::TRSM_LLNN, n, nrhs, A, lda, B, ldb, solve_sync(h, n)));
         CDF_HIP_TRY(cdf::trsv_blocked(s, cdf::TRSM_LLTN, n, nrhs, A, lda, B, ldb));
         return CDF_OK;
     }

@@ -36,7 +36,7 @@ __device__ __forceinline__ void static_for(F &&f) {
 }
 
 // Bytes at the head of the workspace reserved for the panel leaf's exchange.
-constexpr size_t kLeafWsBytes = 256 * 1024;
+constexpr size_t kLeafWsBytes = 512 * 1024;
 
 // Grows the handle's workspace to at least `bytes` (synchronizing the stream
 // before a reallocation).  Returns CDF_ERR_ALLOC on failure or above the cap.
@@ -147,9 +147,13 @@ hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const dou
 hipError_t trsm_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const double *T, int ldt,
                         double *B, int ldb, int bs = 128);
 // Solve with few right-hand sides (ncols <= 4): 64-row diagonal blocks solved
-// by one wave in registers, off-diagonal blocks applied GEMV-style.
+// by one wave in registers, off-diagonal blocks applied GEMV-style.  With a
+// device work area `sync` of trsv_sync_ints(n) ints (LLNU, LLNN, LUNN), the
+// whole solve is one launch whose workgroups hand solved blocks to each
+// other through flags; otherwise one launch per 64-row block.
+size_t trsv_sync_ints(int n);
 hipError_t trsv_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const double *T, int ldt, double *B,
-                        int ldb);
+                        int ldb, int *sync = nullptr);
 
 // Cholesky of one diagonal block (n <= 128) held in LDS; stops at the first
 // non-positive pivot, writing info_base + j + 1 into *info if *info == 0.

@@ -9,17 +9,20 @@
 // the update GEMM's workgroups.  Every column costs one grid-wide exchange,
 // done without atomics or cache-wide fences:
 //   1. each workgroup finds its best candidate (largest |a|, lowest row on
-//      ties) with wave shuffles and LDS, writes the candidate's whole row
-//      (and, if it owns it, the current row j) to its slot, waits for those
-//      stores to complete and then writes three tag words: the candidate's
-//      |a| split in two 32-bit halves and its row index, each paired with a
-//      32-bit epoch unique to this launch and column;
+//      ties) with wave shuffles and LDS, then writes the candidate's whole
+//      row (and, if it owns it, the current row j) to its slot and three tag
+//      words: the candidate's |a| split in two 32-bit halves and its row
+//      index.  Every 64-bit word written (row entries too, as two words per
+//      double) pairs 32 data bits with a 32-bit epoch unique to this launch
+//      and column, so nothing waits for the row stores to complete: a reader
+//      re-reads a word until it carries the current epoch;
 //   2. every workgroup polls the G tag triples with device-coherent loads
 //      until all carry the current epoch (each 64-bit word is written
 //      whole, so a word with the current epoch holds the current half), and
 //      reduces them identically;
-//   3. it reads the winning row, then each thread swaps, scales (division)
-//      and rank-1 updates its own rows.
+//   3. it reads the winning row (and row j), each entry once both of its
+//      words carry the current epoch, then each thread swaps, scales
+//      (division) and rank-1 updates its own rows.
 // Slots are double-buffered by column parity: a workgroup can only overwrite
 // the slots of column j once every workgroup has published column j + 1,
 // which each does after it finished reading column j.  With G = 1 the
@@ -40,22 +43,32 @@ typedef unsigned long long u64;
 // Workspace layout of the exchange (at the head of the handle's workspace).
 constexpr size_t kTagWords = 4;  // per slot: |a| high half, |a| low half, row index, padding
 constexpr size_t kTagBytes = 2 * GMAX * kTagWords * sizeof(u64);
-constexpr size_t kRowBytes = 2 * GMAX * LW * sizeof(double);
-static_assert(kTagBytes + kRowBytes + 2 * LW * sizeof(double) <= cdf::kLeafWsBytes, "leaf workspace");
+constexpr size_t kRowWords = 2 * GMAX * LW * 2;  // candidate rows: two tagged words per entry
+constexpr size_t kRowjWords = 2 * LW * 2;        // row j
+constexpr size_t kExchBytes = kTagBytes + (kRowWords + kRowjWords) * sizeof(u64);
+static_assert(kExchBytes <= cdf::kLeafWsBytes, "leaf workspace");
 
 __device__ inline void better(double &bv, int &bi, double ov, int oi) {
     if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
 }
 
-__device__ inline void put_dev(double *p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline double get_dev(const double *p) {
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ inline void put_tag(u64 *p, u64 v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ inline u64 get_tag(const u64 *p) {
     return __hip_atomic_load(const_cast<u64 *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// A double as two tagged words (high half, low half), each with epoch e.
+__device__ inline void put_pair(u64 *p, double v, u64 e) {
+    const u64 bits = (u64)__double_as_longlong(v);
+    put_tag(p, e | (bits >> 32));
+    put_tag(p + 1, e | (bits & 0xffffffffull));
+}
+__device__ inline double get_pair(const u64 *p, u64 e) {
+    u64 w0, w1;
+    do {
+        w0 = get_tag(p);
+        w1 = get_tag(p + 1);
+    } while ((w0 & ~0xffffffffull) != e || (w1 & ~0xffffffffull) != e);
+    return __longlong_as_double((long long)((w0 << 32) | (w1 & 0xffffffffull)));
 }
 
 // Builds the (dst, src) row pairs equivalent to applying the interchanges
@@ -108,7 +121,7 @@ template <int R>
 __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__restrict__ A, int lda,
                                                      int *__restrict__ ipiv, int row0,
                                                      int *__restrict__ info, int info_base,
-                                                     u64 *__restrict__ tags, double *__restrict__ rows,
+                                                     u64 *__restrict__ tags, u64 *__restrict__ rows,
                                                      unsigned epoch0, double *__restrict__ Reg, int rm,
                                                      int rcols, int rc0) {
     constexpr int RT = LT * R;  // rows per workgroup
@@ -124,7 +137,7 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int rbase = g * RT;
-    double *rowj = rows + (size_t)2 * GMAX * LW;
+    u64 *rowj = rows + kRowWords;
 
     // the thread's rows rbase + s*LT + t, all columns, in registers
     double x[R][LW];
@@ -174,10 +187,9 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
         if (G > 1) {
             const u64 e = (u64)(epoch0 + (unsigned)j) << 32;
             if (wave == 0) {
-                // publish: rows first, then (after they completed) the tags
-                if (p != INT_MAX && t < n) put_dev(rows + ((size_t)par * GMAX + g) * LW + t, cand[t]);
-                if (j >= rbase && j < rbase + RT && t < n) put_dev(rowj + (size_t)par * LW + t, lrowj[t]);
-                __builtin_amdgcn_s_waitcnt(0);
+                // publish rows and tags, all words tagged with the epoch
+                if (p != INT_MAX && t < n) put_pair(rows + (((size_t)par * GMAX + g) * LW + t) * 2, cand[t], e);
+                if (j >= rbase && j < rbase + RT && t < n) put_pair(rowj + ((size_t)par * LW + t) * 2, lrowj[t], e);
                 if (t < 3) {
                     const u64 bits = (u64)__double_as_longlong(v);
                     const u64 half = t == 0 ? bits >> 32 : (t == 1 ? bits & 0xffffffffull : (u64)(unsigned)p);
@@ -236,10 +248,11 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
             const int win = xw[0];
             // 3. winning row and current row j
             if (t < n) {
-                const double oj = get_dev(rowj + (size_t)par * LW + t);
-                const double pw = get_dev(rows + ((size_t)par * GMAX + win) * LW + t);
+                // row j is always published (by its owner); a candidate row
+                // only where that workgroup had one, which the winner did
+                const double oj = get_pair(rowj + ((size_t)par * LW + t) * 2, e);
                 oldj[t] = oj;
-                prow[t] = p == INT_MAX ? oj : pw;
+                prow[t] = p == INT_MAX ? oj : get_pair(rows + (((size_t)par * GMAX + win) * LW + t) * 2, e);
             }
         } else if (t < n) {
             oldj[t] = lrowj[t];
@@ -472,17 +485,18 @@ hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, 
     int G = (m + LT * R - 1) / (LT * R);
     if (G > h->num_cus && R == 1) { R = 2; G = (m + LT * R - 1) / (LT * R); }
     if (G > h->num_cus || G > GMAX) return hipErrorInvalidValue;
-    // Epochs are unique per launch and column; the tag area starts zeroed
-    // (ws_reserve) and epochs below 64 are never issued, so no stale word
-    // can carry a current epoch.
+    // Epochs are unique per launch and column; the exchange area (tags and
+    // row words) is zeroed on first use of a workspace and on wrap-around,
+    // and epochs below 64 are never issued, so no stale word can carry a
+    // current epoch.
     if (h->leaf_epoch < 64u || h->leaf_epoch > 0xffffff00u) {
-        CDF_HIP_RET(fill_int(stream, static_cast<int *>(h->ws), (int)(kTagBytes / sizeof(int)), 0));
+        CDF_HIP_RET(fill_int(stream, static_cast<int *>(h->ws), (int)(kExchBytes / sizeof(int)), 0));
         h->leaf_epoch = 64u;
     }
     unsigned e0 = h->leaf_epoch;
     h->leaf_epoch += 64u;
     u64 *tags = static_cast<u64 *>(h->ws);
-    double *rows = reinterpret_cast<double *>(static_cast<char *>(h->ws) + kTagBytes);
+    u64 *rows = reinterpret_cast<u64 *>(static_cast<char *>(h->ws) + kTagBytes);
     void *args[] = {&m, &n, &A, &lda, &ipiv, &row0, &info, &info_base, &tags, &rows, &e0, &region, &region_rows,
                     &region_cols, &c0};
     const void *fn = R == 1 ? reinterpret_cast<const void *>(&lu_leaf_kernel<1>)

@@ -504,6 +504,7 @@ struct MixedWs {
     int *ea = nullptr, *eb = nullptr, *ipt = nullptr, *ipiv = nullptr;
     int *lu_ws = nullptr;      // work area of the binary64 LU (fp64 mode)
     double *lu_w = nullptr;    // its U12 / L11^-1 area (fp64 mode)
+    int *tsync = nullptr;      // flags of the single-launch triangular solves
     double *R = nullptr, *red = nullptr;
 };
 
@@ -533,6 +534,7 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     const size_t oipt = take((size_t)nb * sizeof(int)), oipiv = take((size_t)n * sizeof(int));
     const size_t olw = take(cdf::getrf_ws_ints() * sizeof(int));
     const size_t olww = fp64_lu ? take(cdf::getrf_w_doubles(n) * sizeof(double)) : 0;
+    const size_t ots = take(cdf::trsv_sync_ints(n) * sizeof(int));
     const size_t oR = take((size_t)n * nrhs * sizeof(double));
     const size_t ored = take(((size_t)n + 4 * (size_t)nrhs + 8) * sizeof(double));
     cdf_status_t st = cdf::ws_reserve(h, off);
@@ -556,6 +558,7 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     w.ipiv = reinterpret_cast<int *>(base + oipiv);
     w.lu_ws = reinterpret_cast<int *>(base + olw);
     w.lu_w = fp64_lu ? reinterpret_cast<double *>(base + olww) : nullptr;
+    w.tsync = reinterpret_cast<int *>(base + ots);
     w.R = reinterpret_cast<double *>(base + oR);
     w.red = reinterpret_cast<double *>(base + ored);
     return CDF_OK;
@@ -722,7 +725,7 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
     *resid = INFINITY;
     if (hinfo != 0) return CDF_ERR_NOT_CONVERGED;
     auto tri = [&](cdf::TrsmKind kind, double *Y, int ldy) -> hipError_t {
-        return nrhs <= 4 ? cdf::trsv_blocked(s, kind, n, nrhs, w.Wd, n, Y, ldy)
+        return nrhs <= 4 ? cdf::trsv_blocked(s, kind, n, nrhs, w.Wd, n, Y, ldy, w.tsync)
                          : cdf::trsm_blocked(s, kind, n, nrhs, w.Wd, n, Y, ldy);
     };
     auto solve = [&](double *Y, int ldy) -> hipError_t {

@@ -380,6 +380,99 @@ __global__ __launch_bounds__(256) void trsv_step_kernel(int nrhs, const double *
     if (lane < nkb) B[(size_t)(nk + lane) + (size_t)c * ldb] = x;
 }
 
+// Single-launch solve for few right-hand sides (kinds with the triangle's
+// rows contiguous over the lanes: LLNU, LLNN, LUNN).  A workgroup takes the
+// next row block in start order (an atomic ticket, so every block it waits
+// for belongs to a workgroup that started earlier), accumulates T(rb, jb) x_jb
+// over the blocks solved before it as their flags appear (wave w takes every
+// fourth block; lanes = rows), then solves its diagonal block (one wave per
+// right-hand side) and publishes x_rb: device-coherent stores, completed,
+// then the block's flag.  sync[0] is the ticket, sync[1 + b] block b's flag;
+// all start at zero.
+__device__ inline double ld_coh(const double *p) {
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_coh(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void trsv_sf_kernel(int n, int nrhs, const double *__restrict__ T, int ldt,
+                                                      double *B, int ldb, int *sync) {
+    constexpr bool forward = (KIND == cdf::TRSM_LLNU || KIND == cdf::TRSM_LLNN);
+    __shared__ int s_q;
+    __shared__ double xs[4][4][64];
+    __shared__ double red[4][4][64];
+    __shared__ double Ts[64 * 65];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nblk = (n + 63) / 64;
+    if (t == 0) s_q = atomicAdd(sync, 1);
+    __syncthreads();
+    const int q = s_q;
+    const int rb = forward ? q : nblk - 1 - q;
+    const int r0 = rb * 64, kb = min(64, n - r0);
+    for (int e = t; e < kb * kb; e += 256) {
+        const int i = e % kb, j = e / kb;
+        Ts[i + j * 65] = T[(size_t)(r0 + i) + (size_t)(r0 + j) * ldt];
+    }
+    const int r = r0 + lane;
+    const bool live = lane < kb;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int nj = forward ? rb : nblk - 1 - rb;  // blocks solved before this one
+    for (int sj = wave; sj < nj; sj += 4) {
+        const int jb = forward ? sj : nblk - 1 - sj;
+        const int c0 = jb * 64, jn = min(64, n - c0);
+        // the block of T does not depend on x: all 64 loads are issued
+        // before waiting for x_jb, so one memory latency covers the block
+        double tv[64];
+#pragma unroll
+        for (int u = 0; u < 64; ++u) tv[u] = (live && u < jn) ? T[(size_t)r + (size_t)(c0 + u) * ldt] : 0.0;
+        if (lane == 0)
+            while (__hip_atomic_load(sync + 1 + jb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+                __builtin_amdgcn_s_sleep(2);
+        asm volatile("" ::: "memory");  // x_jb is read only after its flag was seen
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < nrhs) xs[wave][c][lane] = lane < jn ? ld_coh(B + (size_t)(c0 + lane) + (size_t)c * ldb) : 0.0;
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // this wave's LDS writes done (lgkmcnt 0)
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < 64; ++u)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (c < nrhs && u < jn) acc[c] = fma(tv[u], xs[wave][c][u], acc[c]);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // reads of xs done before the next block overwrites it
+        asm volatile("" ::: "memory");
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[wave][c][lane] = acc[c];
+    __syncthreads();
+    if (wave < nrhs) {
+        const int c = wave;
+        const double sum = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
+        double x = live ? B[(size_t)r + (size_t)c * ldb] - sum : 0.0;
+        if (forward) {
+            for (int j = 0; j < kb; ++j) {
+                if (KIND == cdf::TRSM_LLNN && lane == j) x = x / Ts[j + j * 65];
+                const double xj = __shfl(x, j);
+                if (lane > j && lane < kb) x = fma(-Ts[lane + j * 65], xj, x);
+            }
+        } else {
+            for (int j = kb - 1; j >= 0; --j) {
+                if (lane == j) x = x / Ts[j + j * 65];
+                const double xj = __shfl(x, j);
+                if (lane < j) x = fma(-Ts[lane + j * 65], xj, x);
+            }
+        }
+        if (live) st_coh(B + (size_t)r + (size_t)c * ldb, x);
+        __builtin_amdgcn_s_waitcnt(0);  // the stores have completed
+    }
+    __syncthreads();
+    if (t == 0) __hip_atomic_store(sync + 1 + rb, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int KIND>
 hipError_t launch_step(hipStream_t s, int nrhs, const double *T, int ldt, double *B, int ldb, int k, int kb, int rbeg,
                        int rend, int nk, int nkb) {
@@ -400,11 +493,32 @@ hipError_t launch_diag(hipStream_t s, int kb, int nrhs, const double *T, int ldt
 
 namespace cdf {
 
+size_t trsv_sync_ints(int n) { return (size_t)(n + 63) / 64 + 1; }
+
 hipError_t trsv_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const double *T, int ldt, double *B,
-                        int ldb) {
+                        int ldb, int *sync) {
     constexpr int BS = 64;
     if (n <= 0 || ncols <= 0) return hipSuccess;
     if (ncols > 4) return hipErrorInvalidValue;
+    if (sync != nullptr && kind != TRSM_LLTN) {
+        const int nblk = (n + 63) / 64;
+        CDF_HIP_RET(fill_int(s, sync, nblk + 1, 0));
+        switch (kind) {
+            case TRSM_LLNU:
+                hipLaunchKernelGGL((trsv_sf_kernel<TRSM_LLNU>), dim3(nblk), dim3(256), 0, s, n, ncols, T, ldt, B, ldb,
+                                   sync);
+                break;
+            case TRSM_LLNN:
+                hipLaunchKernelGGL((trsv_sf_kernel<TRSM_LLNN>), dim3(nblk), dim3(256), 0, s, n, ncols, T, ldt, B, ldb,
+                                   sync);
+                break;
+            default:
+                hipLaunchKernelGGL((trsv_sf_kernel<TRSM_LUNN>), dim3(nblk), dim3(256), 0, s, n, ncols, T, ldt, B, ldb,
+                                   sync);
+                break;
+        }
+        return hipGetLastError();
+    }
     auto diag = [&](int k, int kb) -> hipError_t {
         const double *Tk = T + k + (size_t)k * ldt;
         switch (kind) {

@@ -191,7 +191,7 @@ def test_lu_diag_dominant_identity_pivots():
     assert info == 0 and np.array_equal(ip, np.arange(1, 601))
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (300, 1), (1024, 1), (777, 5), (1024, 64)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (300, 1), (1024, 1), (4100, 4), (2000, 2), (777, 5), (1024, 64)])
 def test_getrs(oracle_mod, n, nrhs):
     a = workloads.lu_uniform(n, seed=n)
     b = workloads.rhs_uniform(n, nrhs, seed=n + 1)
@@ -237,7 +237,7 @@ def test_chol_not_spd_info(oracle_mod, n, bad, nb):
     assert np.allclose(np.tril(l)[:, :k], np.tril(lo)[:, :k], rtol=1e-12, atol=1e-12)
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (500, 1), (1024, 64), (333, 3)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (500, 1), (1024, 64), (333, 3), (3001, 4)])
 def test_potrs(oracle_mod, n, nrhs):
     a = workloads.spd_bbt(n, seed=n)
     b = workloads.rhs_uniform(n, nrhs, seed=n + 2)
