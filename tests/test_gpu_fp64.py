@@ -312,3 +312,11 @@ def test_invalid_arguments():
     assert info.item() == 0
     with pytest.raises(cdf.CdfError):
         h.set_param("lu_nb", 33)
+    for name, bad_values in (("gemm_wg_per_cu", (1, 2, 6)), ("lu_u12", (2, -1))):
+        for v in bad_values:
+            with pytest.raises(cdf.CdfError):
+                h.set_param(name, v)
+        assert h.get_param(name) == 0
+    for v in (3, 4, 5, 0):
+        h.set_param("gemm_wg_per_cu", v)
+        assert h.get_param("gemm_wg_per_cu") == v
