@@ -12,8 +12,8 @@ parameters from the cache; the batched plan and the benchmark use it.
 Search spaces (the parameters the paper tunes are the block size v and the
 replication depth, Sec. 7.2 and Sec. 8; on one GPU they become the panel
 width, the leaf shape and the batched launch shape):
-  getrf        lu_nb in {256, 384, 512} x lu_leaf_rows in {1, 2}
-  potrf        chol_nb in {128, 256, 384, 512}
+  getrf        lu_nb in {256, 384, 512} x lu_leaf_rows in {1, 2} x gemm_wg_per_cu in {4, 5}
+  potrf        chol_nb in {128, 256, 384, 512} x gemm_wg_per_cu in {4, 5}
   mixed_getrf  mixed_nb in {256, 384, 512} (BF16 update)
   vbatch       vbatch_nb in {0 (32 where it fits), 16} x vbatch_wg_per_cu in {1, 2}
 """
@@ -35,8 +35,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tune_cache.json")
 
 SPACES = {
-    "getrf": {"lu_nb": [256, 384, 512], "lu_leaf_rows": [1, 2]},
-    "potrf": {"chol_nb": [128, 256, 384, 512]},
+    "getrf": {"lu_nb": [256, 384, 512], "lu_leaf_rows": [1, 2], "gemm_wg_per_cu": [4, 5]},
+    "potrf": {"chol_nb": [128, 256, 384, 512], "gemm_wg_per_cu": [4, 5]},
     "mixed_getrf": {"mixed_nb": [256, 384, 512]},
     "vbatch": {"vbatch_nb": [0, 16], "vbatch_wg_per_cu": [1, 2]},
 }
