@@ -98,13 +98,31 @@ __device__ inline void grouped_tile(int L, int tiles_m, int tiles_n, int &tm, in
     tn = in / gm;
 }
 
-__device__ inline void lower_tile(int L, int &tm, int &tn) {
-    // row-wise enumeration of the lower triangle: L = tm(tm+1)/2 + tn
+__device__ inline void lower_tile(int L, int tiles_m, int &tm, int &tn) {
+    // Lower triangle in bands of GROUP_M tile rows, each band column by
+    // column, so that consecutive workgroups (which share an XCD's L2) reuse
+    // one B column strip across the band's rows, as grouped_tile does for
+    // full matrices.  The band of L is that of its row in the row-wise
+    // enumeration L = r(r+1)/2 + c, since bands are made of whole rows.
     int r = (int)((sqrt(8.0 * (double)L + 1.0) - 1.0) * 0.5);
     while ((r + 1) * (r + 2) / 2 <= L) ++r;
     while (r * (r + 1) / 2 > L) --r;
-    tm = r;
-    tn = L - r * (r + 1) / 2;
+    const int r0 = r / GROUP_M * GROUP_M;
+    const int gr = min(GROUP_M, tiles_m - r0);
+    int in = L - r0 * (r0 + 1) / 2;
+    if (in < r0 * gr) {  // full columns left of the band's diagonal block
+        tn = in / gr;
+        tm = r0 + in % gr;
+        return;
+    }
+    in -= r0 * gr;  // the band's gr x gr diagonal block, column c has gr - c tiles
+    int c = 0;
+    while (in >= gr - c) {
+        in -= gr - c;
+        ++c;
+    }
+    tn = r0 + c;
+    tm = r0 + c + in;
 }
 
 template <int TA, int TB, bool LOWER>
@@ -124,7 +142,7 @@ __global__ __launch_bounds__(NT, Shape<TB>::OCC) void dgemm_kernel(int m, int n,
 
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     int tm, tn;
-    if (LOWER) lower_tile(L, tm, tn);
+    if (LOWER) lower_tile(L, tiles_m, tm, tn);
     else grouped_tile(L, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
 
@@ -236,7 +254,7 @@ __global__ __launch_bounds__(NT, 5) void dgemm_dl_kernel(int m, int n, int k, do
     __shared__ __attribute__((aligned(16))) double S[2 * STAGE];
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     int tm, tn;
-    if (LOWER) lower_tile(L, tm, tn);
+    if (LOWER) lower_tile(L, tiles_m, tm, tn);
     else grouped_tile(L, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BT, n0 = tn * BT;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
