@@ -107,6 +107,12 @@ CDF_API int cdf_get_param(cdf_handle_t h, cdf_param_t p);
  *         with row ipiv[k]-1 at step k (LAPACK convention)
  *   info  device int; on exit 0, or j > 0 if U(j-1,j-1) is exactly zero for
  *         the first such j (the factorization is still completed)
+ * Workspace: about 0.5 MB, plus 512 x n + 2 x 512 x 512 doubles when U12 is
+ * formed through L11^-1 (CDF_PARAM_LU_U12 = 0; if the cap set by
+ * cdf_set_workspace_limit refuses those, U12 is solved in place instead).
+ * Runs on the handle's stream and two more streams of the handle; the call
+ * returns once the work is queued, and all of it is ordered before later
+ * work on the handle's stream.
  */
 CDF_API cdf_status_t cdf_dgetrf(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info);
 
@@ -115,6 +121,9 @@ CDF_API cdf_status_t cdf_dgetrf(cdf_handle_t h, int n, double *A, int lda, int *
  * lower and upper triangular solves.  trans must be 'N'.
  *   A, ipiv  device, as left by cdf_dgetrf; B device n x nrhs, ldb >= n;
  *   on exit B holds X.
+ * For nrhs <= 4 each triangular solve is one launch whose workgroups pass
+ * solved 64-row blocks to each other through device flags (n/64 + 1 ints of
+ * the handle's workspace).
  */
 CDF_API cdf_status_t cdf_dgetrs(cdf_handle_t h, char trans, int n, int nrhs, const double *A, int lda,
                         const int *ipiv, double *B, int ldb);
