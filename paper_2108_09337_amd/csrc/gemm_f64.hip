@@ -88,16 +88,11 @@ __device__ inline int xcd_remap(int bid, int nwg) {
     return (bid & 7) * per + (bid >> 3);
 }
 
-// Full matrices: groups of GM tile rows, each group column by column.  With
-// about 128-160 workgroups resident per XCD, groups of 4 rows keep fewer A
-// and B strips in flight per XCD's L2 than 8 or 16 (measured: 61.5 against
-// 59.9 and 59.5 TF/s for the LU's update shapes).
 __device__ inline void grouped_tile(int L, int tiles_m, int tiles_n, int &tm, int &tn) {
-    constexpr int GM = 4;
-    const int group = GM * tiles_n;
+    const int group = GROUP_M * tiles_n;
     const int g = L / group;
-    const int first_m = g * GM;
-    const int gm = min(tiles_m - first_m, GM);
+    const int first_m = g * GROUP_M;
+    const int gm = min(tiles_m - first_m, GROUP_M);
     const int in = L - g * group;
     tm = first_m + in % gm;
     tn = in / gm;
