@@ -58,6 +58,9 @@ def parse():
                    help="points of the exponential-kernel Cholesky solve (0 = skip)")
     p.add_argument("--cpu-steps", type=int, default=32, help="elimination steps in the oracle sample")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-parity", action="store_true",
+                   help="skip the full-size backward errors (torch FP64 products) after the timed steps")
+    p.add_argument("--no-c1", action="store_true", help="skip the N = 1024 latency leg")
     p.add_argument("--no-chol", action="store_true")
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-batched", action="store_true")
@@ -162,11 +165,12 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
         log(f"warmup step {i}")
         restore()
         step(events(torch, 3))
+        assert cdf.device_status(h) == cdf.CDF_OK
     torch.cuda.synchronize()
     evs = [events(torch, 3) for _ in range(K)]
     log(f"timing {K} steps")
     wall = 0.0
-    prof_nn = prof_syrk = {"launches": 0, "total_ms": 0.0, "flops": 0.0}
+    prof_nn = prof_syrk = prof_u12 = {"launches": 0, "total_ms": 0.0, "flops": 0.0}
     for i in range(K):
         restore()
         timed = i == 0 and not args.no_kernel_timing
@@ -176,9 +180,11 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
         step(evs[i])
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
+        assert cdf.device_status(h) == cdf.CDF_OK, "LU panel exchange timed out"
         if timed:
             prof_nn = cdf.profile_end("nn", h)
             prof_syrk = cdf.profile_end("syrk", h)
+            prof_u12 = cdf.profile_end("u12", h)
     assert int(info_lu.item()) == 0 and (S is None or int(info_ch.item()) == 0)
     ms = wall * 1e3 / K
     t_lu = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e-3
@@ -188,7 +194,9 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
     value = (flops_lu + flops_ch) / (ms * 1e-3) / 1e12
     log(f"ms/step {ms:.1f}  LU {flops_lu / t_lu / 1e12:.2f} TF  Chol {flops_ch / max(t_ch, 1e-12) / 1e12:.2f} TF")
 
-    # dominant kernel: the FP64 update GEMM, every launch of it inside the timed LU steps
+    # dominant kernel: the FP64 update GEMM (Schur-complement updates only;
+    # the products forming U12 = L11^-1 A12 are filed apart), every launch of
+    # it inside the first timed LU step
     lu_nb = h.get_param("lu_nb") or 512
     launches = max(prof_nn["launches"], 1)
     avg = prof_nn["total_ms"] * 1e-3 / launches
@@ -197,19 +205,37 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
     roofline = {"bound": "mfma", "achieved": None if achieved is None else round(achieved, 3), "peak": FP64_PEAK,
                 "unit": "TFLOP/s", "frac": None if achieved is None else round(achieved / FP64_PEAK, 4),
                 "traffic": traffic_per_launch(n, lu_nb),
-                "kernel": "dgemm_dl_kernel<0, false> (FP64 update C -= A B, direct-to-LDS operands; "
-                          "dgemm_kernel<0,0,false> where its shape conditions fail)",
+                "kernel": "dgemm_dl_kernel<0, false> (FP64 Schur-complement update C -= A B, direct-to-LDS "
+                          "operands; dgemm_kernel<0,0,false> where its shape conditions fail)",
                 "launches": prof_nn["launches"], "avg_launch_us": round(avg * 1e6, 2),
                 "flops_per_launch": round(fpl, 1),
+                "u12_products": {"launches": prof_u12["launches"], "gflop": round(prof_u12["flops"] * 1e-9, 1),
+                                 "ms": round(prof_u12["total_ms"], 2),
+                                 "note": "L11^-1 and U12 = L11^-1 A12 as matrix products: work beyond the "
+                                         "method's 2N^3/3, not counted in achieved"},
                 "syrk": {"launches": prof_syrk["launches"],
                          "tflops": round(prof_syrk["flops"] / max(prof_syrk["total_ms"], 1e-9) * 1e-9, 3)}}
+    parity = None
+    if not args.no_parity:
+        from tests import gpu_util
+        log("parity: backward errors of the last LU and Cholesky (torch FP64 products)")
+        t0 = time.perf_counter()
+        ip_host = ipiv.cpu().numpy()
+        parity = {"lu_backward_error": round(gpu_util.lu_backward_error_torch(torch, A0, A, ip_host), 5),
+                  "method": "||PA-LU||_F/(||A||_F N eps) and ||A-LL^T||_F/(||A||_F N eps), eps=2^-53, by "
+                            "torch FP64 matrix products on the GPU (independent of the library's kernels)"}
+        if S is not None:
+            parity["chol_backward_error"] = round(gpu_util.chol_backward_error_torch(torch, S0, S), 5)
+        log(f"parity: {parity} ({time.perf_counter() - t0:.1f} s)")
+        assert parity["lu_backward_error"] <= 10.0 and parity.get("chol_backward_error", 0.0) <= 10.0
+        torch.cuda.empty_cache()
     out = {"value": value, "ms": ms, "t_lu": t_lu, "t_ch": t_ch, "flops_lu": flops_lu, "flops_ch": flops_ch,
            "roofline": roofline, "lu_nb": lu_nb, "chol_nb": h.get_param("chol_nb") or 128,
-           "params": {"getrf": lu_params, "potrf": ch_params}}
+           "params": {"getrf": lu_params, "potrf": ch_params}, "parity": parity,
+           "lu_result": A, "ipiv": ipiv.cpu().numpy(), "chol_result": S}
     for k in list(lu_params) + list(ch_params):
         h.set_param(k, 0)
     del A, S
-    torch.cuda.empty_cache()
     return out, A0, S0
 
 
@@ -320,6 +346,64 @@ def kernel_chol_section(args, torch, cdf, workloads, h, tuned):
     return res
 
 
+def c1_section(args, torch, cdf, workloads, h, n=1024, reps=50):
+    """Latency case: dgetrf + dgetrs of one n = 1024 system (A uniform[-1,1]
+    seed 0, b uniform[-1,1] seed 1), event-timed, median of `reps` after 5
+    warm-ups; A and b restored by device copies outside the timed region.
+    Beside it the CPU oracle's full factor + solve (median of 3, all threads,
+    and once on one thread), and the parity of the two results."""
+    a = workloads.lu_uniform(n, seed=workloads.SEED_MATRIX)
+    b = workloads.rhs_uniform(n, 1, seed=workloads.SEED_RHS)[:, 0]
+    A0, B0 = cdf.to_device(a), cdf.to_device(b)
+    A, B = cdf.cm_empty(n, n), torch.empty_like(B0)
+    ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    times = []
+    for rep in range(5 + reps):
+        A.copy_(A0)
+        B.copy_(B0)
+        e0, e1 = events(torch, 2)
+        torch.cuda.synchronize()
+        e0.record()
+        cdf.dgetrf(A, ipiv, info)
+        cdf.dgetrs(A, ipiv, B)
+        e1.record()
+        torch.cuda.synchronize()
+        if rep >= 5:
+            times.append(e0.elapsed_time(e1) * 1e-3)
+    assert cdf.device_status(h) == cdf.CDF_OK and int(info.item()) == 0
+    t_gpu = float(np.median(times))
+    out = {"n": n, "gpu_seconds_median": round(t_gpu, 7), "reps": reps,
+           "gpu_tflops": round(2.0 * n ** 3 / 3 / t_gpu / 1e12, 4)}
+    if not args.no_cpu:
+        import oracle
+        from tests import gpu_util
+        tc = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            lu_or, ip_or, _ = oracle.dgetrf(a)
+            x_or = oracle.dgetrs(lu_or, ip_or, b)
+            tc.append(time.perf_counter() - t0)
+        threads = oracle.get_threads()
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.dgetrs(*oracle.dgetrf(a)[:2], b)
+        t1 = time.perf_counter() - t0
+        oracle.set_threads(threads)
+        lu, ip, x = cdf.to_host(A), ipiv.cpu().numpy(), B.cpu().numpy()
+        tol = gpu_util.lu_parity_tolerance(lu_or)
+        out.update({"oracle_seconds_median": round(float(np.median(tc)), 4), "oracle_threads": threads,
+                    "oracle_seconds_1thread": round(t1, 4),
+                    "pivots_equal": bool(np.array_equal(ip, ip_or)),
+                    "max_err_over_tol": round(float(np.max(np.abs(lu - lu_or) / tol)), 4),
+                    "backward_error": round(oracle.lu_backward_error(a, lu, ip), 4),
+                    "hpl_scaled_residual": round(oracle.hpl_scaled_residual(a, x, b), 4)})
+        assert out["pivots_equal"] and out["max_err_over_tol"] <= 1.0 and out["backward_error"] <= 10
+        assert out["hpl_scaled_residual"] <= 16
+    log(f"C1 n={n}: GPU {t_gpu * 1e3:.3f} ms (median of {reps}); {out}")
+    return out
+
+
 def batched_section(args, torch, cdf, workloads, h, tuned):
     count = args.batch
     sizes = workloads.batch_sizes(count)
@@ -390,29 +474,58 @@ def main():
               "lu_s": round(fp["t_lu"], 4), "chol_s": round(fp["t_ch"], 4),
               "frac_fp64_peak": round(fp["value"] / FP64_PEAK, 4), "tuned_params": fp["params"]}
     cpu = None
+    lu_res, ip_gpu, ch_res = fp.pop("lu_result"), fp.pop("ipiv"), fp.pop("chol_result")
     if not args.no_cpu:
         import oracle
+        from tests import gpu_util
         s = args.cpu_steps
-        log(f"oracle sample: first {s} elimination steps of the n={args.n} LU and Cholesky")
+        n = args.n
+        log(f"oracle sample: first {s} elimination steps of the n={n} LU and Cholesky")
         a_host = cdf.to_host(A0)
         t = time.perf_counter()
-        oracle.dgetrf(a_host, ksteps=s)
+        lu_s, ip_s, _ = oracle.dgetrf(a_host, ksteps=s)
         t_cl = time.perf_counter() - t
         del a_host
-        f = oracle.lu_step_flops(args.n, s)
+        # the sample is also a parity check of the timed LU: identical first
+        # pivots, and its first columns of L (rows moved by the GPU's later
+        # interchanges) and first rows of U within the rounding tolerance
+        assert np.array_equal(ip_gpu[:s], ip_s[:s]), "GPU pivots differ from the oracle's"
+        perm = gpu_util.perm_from_ipiv(np.concatenate([np.arange(1, s + 1), ip_gpu[s:]]), n)
+        tol = gpu_util.lu_partial_tolerance(np.asfortranarray(lu_s[:, :s]), s, n)
+        err = np.abs(lu_res[:, :s].cpu().numpy() - lu_s[perm, :s])
+        lu_ratio = float(np.max(err / tol[perm]))
+        Lk = np.tril(lu_s[:s, :s], -1) + np.eye(s)
+        utol = 16 * n * gpu_util.EPS * (np.abs(Lk) @ np.abs(lu_s[:s, s:])) + 1e-300
+        u_ratio = float(np.max(np.abs(lu_res[:s, s:].cpu().numpy() - lu_s[:s, s:]) / utol))
+        del lu_s, tol, err, utol, Lk
+        f = oracle.lu_step_flops(n, s)
+        samples = {"lu_first_pivots_equal": s, "lu_first_cols_max_err_over_tol": round(lu_ratio, 4),
+                   "u_first_rows_max_err_over_tol": round(u_ratio, 4)}
+        assert lu_ratio <= 1.0 and u_ratio <= 1.0
         if S0 is not None:
             s_host = cdf.to_host(S0)
             t = time.perf_counter()
-            oracle.dpotrf(s_host, ksteps=s)
+            l_s, _ = oracle.dpotrf(s_host, ksteps=s)
             t_cl += time.perf_counter() - t
-            f += oracle.chol_step_flops(args.n, s)
+            f += oracle.chol_step_flops(n, s)
             del s_host
+            Lk = np.tril(l_s[:, :s])
+            ltol = 16 * n * gpu_util.EPS * (np.abs(Lk) @ np.abs(Lk[:s, :]).T) / np.abs(np.diag(Lk))[None, :]
+            cerr = np.abs(np.tril(ch_res[:, :s].cpu().numpy()) - Lk)
+            samples["chol_first_cols_max_err_over_tol"] = round(float(np.max(cerr / (ltol + 1e-300))), 4)
+            assert samples["chol_first_cols_max_err_over_tol"] <= 1.0
+            del l_s, Lk, ltol, cerr
+        fp["parity"] = dict(fp["parity"] or {}, oracle_sample=samples)
         cpu = {"value": round(f / t_cl / 1e12, 6), "unit": "TFLOP/s", "cores": oracle.get_threads(),
                "kind": "oracle",
-               "sample": f"first {s} elimination steps of the n={args.n} LU and Cholesky factorizations of the "
-                         f"benchmark's own inputs ({f:.3e} flop in {t_cl:.1f} s)"}
-    del A0, S0
+               "sample": f"first {s} elimination steps of the n={n} LU and Cholesky factorizations of the "
+                         f"benchmark's own inputs ({f:.3e} flop in {t_cl:.1f} s)",
+               "cpu_model": oracle.cpu_model(), "host_triad_gbs": round(oracle.host_triad_gbs(), 1)}
+    del A0, S0, lu_res, ch_res
     torch.cuda.empty_cache()
+    detail["parity"] = fp["parity"]
+    if not args.no_c1:
+        detail["c1"] = c1_section(args, torch, cdf, workloads, h)
     if args.detail_n:
         detail["sizes"] = size_detail(args, torch, cdf, workloads, h, tuned)
     if not args.no_mixed:

@@ -52,8 +52,20 @@ typedef enum {
     CDF_ERR_HIP = 2,             /* a HIP runtime call failed */
     CDF_ERR_ALLOC = 3,           /* workspace allocation failed or exceeds the cap */
     CDF_ERR_NOT_CONVERGED = 4,   /* iterative refinement did not reach its target */
-    CDF_ERR_UNSUPPORTED = 5      /* valid but unimplemented option (e.g. uplo 'U') */
+    CDF_ERR_UNSUPPORTED = 5,     /* valid but unimplemented option (e.g. uplo 'U') */
+    CDF_ERR_TIMEOUT = 6          /* a device-side wait ran out of its time budget (see
+                                    cdf_device_status); the outputs of that call are invalid */
 } cdf_status_t;
+
+/*
+ * Device info value written by the LU factorizations (cdf_dgetrf and the
+ * mixed LU) when a wait of the panel's grid-wide pivot exchange ran out of
+ * its budget (CDF_PARAM_LEAF_WAIT_US): the factors and pivots are invalid.
+ * Every workgroup still ends normally, and the remaining work of the call
+ * runs to completion on identity interchanges.  Negative, so it cannot be
+ * confused with LAPACK's zero-pivot info.
+ */
+#define CDF_INFO_TIMEOUT (-1000)
 
 typedef struct cdf_handle_s *cdf_handle_t;
 
@@ -71,6 +83,13 @@ CDF_API size_t cdf_workspace_bytes(cdf_handle_t h);
 CDF_API int cdf_last_bad_arg(cdf_handle_t h);
 /* Human-readable name of a status code (static storage). */
 CDF_API const char *cdf_status_string(cdf_status_t s);
+/*
+ * Synchronizes the handle's streams, then returns CDF_ERR_TIMEOUT if a wait
+ * of the LU panel's grid exchange ran out of budget in the most recent LU
+ * factorization on this handle (each factorization clears the flag when it
+ * starts), else CDF_OK.  CDF_ERR_HIP if a synchronization fails.
+ */
+CDF_API cdf_status_t cdf_device_status(cdf_handle_t h);
 
 /* Tunable parameters (block sizes chosen per call when left at 0 = auto). */
 typedef enum {
@@ -83,12 +102,19 @@ typedef enum {
     CDF_PARAM_VBATCH_WG_PER_CU = 5, /* batched persistent workgroups per CU (1 or 2; 0 = 1) */
     CDF_PARAM_GEMM_WG_PER_CU = 6,   /* update-GEMM workgroups resident per CU in this handle's
                                        factorizations (3, 4 or 5; 0 = 5, all of the LDS).  Fewer
-                                       leave room for the panel kernels on the second stream. */
+                                       leave room for the panel kernels on the second stream.
+                                       Passed with each launch: handles do not affect each other. */
     CDF_PARAM_LU_U12 = 7,           /* how the LUs (FP64 and mixed) form U12 = L11^-1 A12: 0 = with
                                        L11^-1 formed beside the update, as one matrix-core GEMM (when
                                        the workspace allows); 1 = blocked substitution in place, which
                                        reproduces exactly representable factors exactly */
-    CDF_PARAM_COUNT = 8
+    CDF_PARAM_LEAF_WAIT_US = 8,     /* budget of one wait of the LU panel's grid-wide pivot exchange, in
+                                       microseconds (0 = 2 s).  A workgroup that waits longer stops,
+                                       sets the device error word and writes CDF_INFO_TIMEOUT */
+    CDF_PARAM_TEST_EXCHANGE_FAIL = 9, /* testing only: 1 = the exchange waits for a tag no workgroup
+                                       writes, so every wait of a multi-workgroup leaf runs out of its
+                                       budget (exercises the timeout path); 0 = normal */
+    CDF_PARAM_COUNT = 10
 } cdf_param_t;
 CDF_API cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value);
 CDF_API int cdf_get_param(cdf_handle_t h, cdf_param_t p);
@@ -289,17 +315,19 @@ CDF_API double cdf_io_lower_bound_elems(int kind, double n, double m_elems);
 /*
  * Kernel timing for roofline measurement (instrumentation, not part of the
  * method).  Between cdf_profile_begin and cdf_profile_end, every launch of
- * the FP64 update GEMM kernels (any handle, any stream, process-wide) is
- * bracketed by two HIP events recorded on the stream it is launched on.
- *   kernel   0: C -= A B (dgemm_kernel<0,0,false>, the LU trailing update)
+ * the FP64 update GEMM kernels made by this handle's factorizations (on any
+ * of its streams) is bracketed by two HIP events recorded on the stream it
+ * is launched on.
+ *   kernel   0: C -= A B (the LU trailing update and the panels' own updates)
  *            1: A B^T, 2: A^T B, 3: A^T B^T, 4: lower-triangle A B^T (SYRK)
+ *            5: the products that form U12 = L11^-1 A12 and L11^-1 itself
+ *               (the LU's triangular solve done as matrix products)
  *   launches number of launches of that kernel (host)
  *   total_ms sum of their event-measured durations in ms (host)
  *   flops    sum of their algorithmic flops 2mnk (m(m+1)k for SYRK) (host)
  * cdf_profile_end synchronizes the recorded events and stops recording;
  * the records stay readable (one call per kernel kind) until the next
- * cdf_profile_begin.  Without a cdf_profile_begin it returns zeros.  The
- * handle argument is only checked for validity.
+ * cdf_profile_begin.  Without a cdf_profile_begin it returns zeros.
  */
 CDF_API cdf_status_t cdf_profile_begin(cdf_handle_t h);
 CDF_API cdf_status_t cdf_profile_end(cdf_handle_t h, int kernel, long long *launches, double *total_ms,

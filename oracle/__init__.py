@@ -46,6 +46,8 @@ def lib():
     L = ctypes.CDLL(_LIB_PATH)
     L.oracle_set_threads.argtypes = [ctypes.c_int]
     L.oracle_get_threads.restype = ctypes.c_int
+    L.oracle_host_triad_gbs.argtypes = [ctypes.c_long, ctypes.c_int]
+    L.oracle_host_triad_gbs.restype = ctypes.c_double
     L.oracle_dgetrf.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _ip, ctypes.c_int]
     L.oracle_dgetrf.restype = ctypes.c_int
     L.oracle_dgetrs.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _ip, _dp, ctypes.c_int]
@@ -78,6 +80,24 @@ def set_threads(n: int) -> None:
 
 def get_threads() -> int:
     return int(lib().oracle_get_threads())
+
+
+def host_triad_gbs(n: int = 1 << 26, reps: int = 5) -> float:
+    """Host memory bandwidth (GB/s) by a STREAM-style triad on all threads;
+    reported beside the CPU baseline, not part of the method."""
+    return float(lib().oracle_host_triad_gbs(int(n), int(reps)))
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), for the baseline report."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _f64(a: np.ndarray) -> np.ndarray:

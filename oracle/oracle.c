@@ -46,6 +46,44 @@ int oracle_get_threads(void)
 }
 
 /*
+ * Host memory bandwidth probe reported beside the CPU baseline (not part of
+ * the method): a STREAM-style triad c = a + s*b over n doubles per array,
+ * all threads, first touch by the same static partition.  Returns the best
+ * of `reps` passes in GB/s, counting 24 bytes per element (two reads, one
+ * write); 0 if the arrays cannot be allocated.
+ */
+#include <stdlib.h>
+#include <time.h>
+
+static double now_s(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+double oracle_host_triad_gbs(long n, int reps)
+{
+    double *a = malloc((size_t)n * sizeof(double));
+    double *b = malloc((size_t)n * sizeof(double));
+    double *c = malloc((size_t)n * sizeof(double));
+    double best = 0.0;
+    if (!a || !b || !c) { free(a); free(b); free(c); return 0.0; }
+    #pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) { a[i] = 1.0; b[i] = 2.0; c[i] = 0.0; }
+    for (int r = 0; r < reps; ++r) {
+        const double t0 = now_s();
+        #pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i) c[i] = a[i] + 3.0 * b[i];
+        const double t = now_s() - t0;
+        const double gbs = 24.0 * (double)n / t * 1e-9;
+        if (gbs > best) best = gbs;
+    }
+    free(a); free(b); free(c);
+    return best;
+}
+
+/*
  * LU factorization with partial (row) pivoting of an m x n matrix, in place.
  *
  * Follows the two statements of the in-place LU program (Sec. 6.1 and the

@@ -23,9 +23,12 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcdnafact.so")
 
-CDF_OK, CDF_ERR_INVALID_ARG, CDF_ERR_HIP, CDF_ERR_ALLOC, CDF_ERR_NOT_CONVERGED, CDF_ERR_UNSUPPORTED = range(6)
+CDF_OK, CDF_ERR_INVALID_ARG, CDF_ERR_HIP, CDF_ERR_ALLOC, CDF_ERR_NOT_CONVERGED, CDF_ERR_UNSUPPORTED, \
+    CDF_ERR_TIMEOUT = range(7)
+CDF_INFO_TIMEOUT = -1000  # device info of an LU whose panel exchange ran out of its wait budget
 UPD = {"fp64": 0, "bf16": 1, "fp16": 2, "fp8e4m3": 3, "e4m3": 3}
-PARAM = {"lu_nb": 0, "chol_nb": 1, "lu_leaf_rows": 2, "mixed_nb": 3, "vbatch_nb": 4, "vbatch_wg_per_cu": 5, "gemm_wg_per_cu": 6, "lu_u12": 7}
+PARAM = {"lu_nb": 0, "chol_nb": 1, "lu_leaf_rows": 2, "mixed_nb": 3, "vbatch_nb": 4, "vbatch_wg_per_cu": 5,
+         "gemm_wg_per_cu": 6, "lu_u12": 7, "leaf_wait_us": 8, "test_exchange_fail": 9}
 F64, F32 = 0, 1
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
@@ -61,6 +64,7 @@ def lib() -> ctypes.CDLL:
         "cdf_workspace_bytes": (ctypes.c_size_t, [_vp]),
         "cdf_last_bad_arg": (_i, [_vp]),
         "cdf_status_string": (ctypes.c_char_p, [_i]),
+        "cdf_device_status": (_i, [_vp]),
         "cdf_set_param": (_i, [_vp, _i, _i]),
         "cdf_get_param": (_i, [_vp, _i]),
         "cdf_dgetrf": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
@@ -236,11 +240,18 @@ def dgemm_update(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, h: Handle | 
                                                       _p(C), _ld(C)), h.ptr)
 
 
-GEMM_KERNELS = {"nn": 0, "nt": 1, "tn": 2, "tt": 3, "syrk": 4}
+GEMM_KERNELS = {"nn": 0, "nt": 1, "tn": 2, "tt": 3, "syrk": 4, "u12": 5}
+
+
+def device_status(h: Handle | None = None) -> int:
+    """Synchronize the handle's streams; CDF_ERR_TIMEOUT if the last LU's panel
+    exchange ran out of its wait budget, else CDF_OK (see cdf_device_status)."""
+    h = h or handle()
+    return int(lib().cdf_device_status(h.ptr))
 
 
 def profile_begin(h: Handle | None = None) -> None:
-    """Start timing every FP64 update-GEMM launch (process-wide, HIP events on its stream)."""
+    """Start timing every FP64 update-GEMM launch of this handle's calls (HIP events on its stream)."""
     h = h or handle()
     _check("cdf_profile_begin", lib().cdf_profile_begin(h.ptr), h.ptr)
 

@@ -89,8 +89,9 @@ hipError_t lu_panel(cdf_handle_t h, hipStream_t s, int m, int ncols, double *A, 
     double *a12 = A + c0 + (size_t)(c0 + n1) * lda;
     double *a21 = A + (c0 + n1) + (size_t)c0 * lda;
     double *a22 = A + (c0 + n1) + (size_t)(c0 + n1) * lda;
-    CDF_HIP_RET(trsm_blocked(s, TRSM_LLNU, n1, n2, a11, lda, a12, lda, 64));
-    CDF_HIP_RET(dgemm(s, 0, 0, m - c0 - n1, n2, n1, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false));
+    const GemmCtx gc = gemm_ctx(h);
+    CDF_HIP_RET(trsm_blocked(s, TRSM_LLNU, n1, n2, a11, lda, a12, lda, 64, &gc));
+    CDF_HIP_RET(dgemm(s, 0, 0, m - c0 - n1, n2, n1, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false, nullptr, &gc));
     return lu_panel(h, s, m, ncols, A, lda, ipiv, info, c0 + n1, n2, info_off);
 }
 
@@ -108,6 +109,7 @@ hipError_t ensure_aux(cdf_handle_t h) {
 
 hipError_t potrf_blocked(cdf_handle_t h, int n, double *A, int lda, int *info, int info_off, int nb) {
     hipStream_t s = h->stream;
+    const GemmCtx gc = gemm_ctx(h);
     for (int k = 0; k < n; k += nb) {
         const int kb = nb < n - k ? nb : n - k;
         double *a11 = A + k + (size_t)k * lda;
@@ -117,7 +119,7 @@ hipError_t potrf_blocked(cdf_handle_t h, int n, double *A, int lda, int *info, i
             double *a21 = A + (k + kb) + (size_t)k * lda;
             double *a22 = A + (k + kb) + (size_t)(k + kb) * lda;
             CDF_HIP_RET(trsm_small(s, TRSM_RLTN, kb, rest, a11, lda, a21, lda, info));
-            CDF_HIP_RET(dgemm(s, 0, 1, rest, rest, kb, -1.0, a21, lda, a21, lda, 1.0, a22, lda, true, info));
+            CDF_HIP_RET(dgemm(s, 0, 1, rest, rest, kb, -1.0, a21, lda, a21, lda, 1.0, a22, lda, true, info, &gc));
         }
     }
     return hipSuccess;
@@ -137,8 +139,9 @@ struct LuWs {
     int *good[2];    // 1: Li holds L11^-1; 0: it was rejected (and is the identity)
 };
 
-hipError_t panel_inverse(hipStream_t s, int kb, const double *l11, int lda, double *Li, int *good) {
-    return cdf::unit_lower_inverse(s, kb, l11, lda, Li, kMaxLuNb, good);
+hipError_t panel_inverse(cdf_handle_t h, hipStream_t s, int kb, const double *l11, int lda, double *Li, int *good) {
+    const cdf::GemmCtx gu = cdf::gemm_ctx(h, cdf::PROF_U12);
+    return cdf::unit_lower_inverse(s, kb, l11, lda, Li, kMaxLuNb, good, &gu);
 }
 
 // Columns [c, c + cols) of step k's block row: U12 = L11^-1 A12 into W
@@ -147,20 +150,21 @@ hipError_t panel_inverse(hipStream_t s, int kb, const double *l11, int lda, doub
 // lose the accuracy of substitution), A12 is first solved in place by
 // substitution and the GEMM with the identity copies it to W exactly.
 // Without the workspace: blocked substitution in place, then the update.
-hipError_t u12_and_update(hipStream_t s, int n, double *A, int lda, int k, int kb, int c, int cols,
+hipError_t u12_and_update(cdf_handle_t h, hipStream_t s, int n, double *A, int lda, int k, int kb, int c, int cols,
                           const LuWs &ws, const double *Li, const int *good) {
     const int k1 = k + kb;
     double *a12 = A + k + (size_t)c * lda;
     const double *a21 = A + k1 + (size_t)k * lda;
     double *a22 = A + k1 + (size_t)c * lda;
+    const cdf::GemmCtx gc = cdf::gemm_ctx(h), gu = cdf::gemm_ctx(h, cdf::PROF_U12);
     if (!ws.W) {
-        CDF_HIP_RET(cdf::trsm_blocked(s, cdf::TRSM_LLNU, kb, cols, A + k + (size_t)k * lda, lda, a12, lda, 64));
-        return cdf::dgemm(s, 0, 0, n - k1, cols, kb, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false);
+        CDF_HIP_RET(cdf::trsm_blocked(s, cdf::TRSM_LLNU, kb, cols, A + k + (size_t)k * lda, lda, a12, lda, 64, &gu));
+        return cdf::dgemm(s, 0, 0, n - k1, cols, kb, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false, nullptr, &gc);
     }
     double *w = ws.W + (size_t)(c - k1) * kb;
     CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_LLNU, kb, cols, A + k + (size_t)k * lda, lda, a12, lda, good, 512));
-    CDF_HIP_RET(cdf::dgemm(s, 0, 0, kb, cols, kb, 1.0, Li, kMaxLuNb, a12, lda, 0.0, w, kb, false));
-    CDF_HIP_RET(cdf::dgemm(s, 0, 0, n - k1, cols, kb, -1.0, a21, lda, w, kb, 1.0, a22, lda, false));
+    CDF_HIP_RET(cdf::dgemm(s, 0, 0, kb, cols, kb, 1.0, Li, kMaxLuNb, a12, lda, 0.0, w, kb, false, nullptr, &gu));
+    CDF_HIP_RET(cdf::dgemm(s, 0, 0, n - k1, cols, kb, -1.0, a21, lda, w, kb, 1.0, a22, lda, false, nullptr, &gc));
     return hipMemcpy2DAsync(a12, (size_t)lda * sizeof(double), w, (size_t)kb * sizeof(double), (size_t)kb * sizeof(double),
                             cols, hipMemcpyDeviceToDevice, s);
 }
@@ -174,7 +178,7 @@ hipError_t factor_panel(cdf_handle_t h, hipStream_t s, int n, double *A, int lda
     CDF_HIP_RET(cdf::offset_pivots(s, ws.ipt, ipiv + k, kb, k));
     CDF_HIP_RET(cdf::build_pairs(s, ws.ipt, 0, kb, n - k, ws.pairs));
     // the inverse is needed only while columns remain right of the panel
-    if (ws.W && k + kb < n) CDF_HIP_RET(panel_inverse(s, kb, R, lda, ws.Li[(k / nb) & 1], ws.good[(k / nb) & 1]));
+    if (ws.W && k + kb < n) CDF_HIP_RET(panel_inverse(h, s, kb, R, lda, ws.Li[(k / nb) & 1], ws.good[(k / nb) & 1]));
     return hipSuccess;
 }
 
@@ -190,13 +194,13 @@ hipError_t factor_panel(cdf_handle_t h, hipStream_t s, int n, double *A, int lda
 // updated, and the handle's stream waits for them before updating the rest.
 hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ipt, int *pairs,
                       double *W, double *Li) {
-    cdf::set_gemm_wg_per_cu(h->params[CDF_PARAM_GEMM_WG_PER_CU]);
     hipStream_t s0 = h->stream;
     CDF_HIP_RET(cdf::ensure_aux(h));
     hipStream_t s1 = h->aux, s2 = h->aux2;
     hipEvent_t *left_done = h->ev + 3;  // per pairs buffer
     hipEvent_t rest_swapped = h->ev[5];
     CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
+    CDF_HIP_RET(cdf::leaf_reset_error(h, s0));
     const int nb = lu_nb(h, n);
     LuWs ws;
     ws.ipt = ipt;
@@ -225,7 +229,7 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
         const double *li = ws.Li[(k / nb) & 1];
         const int *good = ws.good[(k / nb) & 1];
         // next panel's columns first
-        CDF_HIP_RET(u12_and_update(s0, n, A, lda, k, kb, k1, kb1, ws, li, good));
+        CDF_HIP_RET(u12_and_update(h, s0, n, A, lda, k, kb, k1, kb1, ws, li, good));
         if (rest > kb1) {
             CDF_HIP_RET(hipEventRecord(h->ev[0], s0));
             CDF_HIP_RET(hipStreamWaitEvent(s1, h->ev[0], 0));
@@ -234,7 +238,7 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
             CDF_HIP_RET(hipEventRecord(h->ev[1], s1));
             const int c2 = k1 + kb1;
             CDF_HIP_RET(hipStreamWaitEvent(s0, rest_swapped, 0));
-            CDF_HIP_RET(u12_and_update(s0, n, A, lda, k, kb, c2, n - c2, ws, li, good));
+            CDF_HIP_RET(u12_and_update(h, s0, n, A, lda, k, kb, c2, n - c2, ws, li, good));
             CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[1], 0));
         } else {
             CDF_HIP_RET(hipStreamWaitEvent(s0, left_done[b], 0));
@@ -265,8 +269,8 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
 // triangle is updated on the handle's stream.  Only the lower triangle is
 // touched; every launch after a failed pivot is a no-op (stop = info).
 hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
-    cdf::set_gemm_wg_per_cu(h->params[CDF_PARAM_GEMM_WG_PER_CU]);
     hipStream_t s0 = h->stream;
+    const cdf::GemmCtx gc = cdf::gemm_ctx(h);
     CDF_HIP_RET(cdf::ensure_aux(h));
     hipStream_t s1 = h->aux;
     CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
@@ -287,10 +291,10 @@ hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
             if (w > 0) {
                 double *l = A + c + (size_t)kk * lda;  // rows [c, n) of the sub-block's L
                 CDF_HIP_RET(cdf::dgemm(s, 0, 1, w, w, kbb, -1.0, l, lda, l, lda, 1.0, A + c + (size_t)c * lda, lda,
-                                       true, info));
+                                       true, info, &gc));
                 if (n - c - w > 0)
                     CDF_HIP_RET(cdf::dgemm(s, 0, 1, n - c - w, w, kbb, -1.0, l + w, lda, l, lda, 1.0,
-                                           A + (c + w) + (size_t)c * lda, lda, false, info));
+                                           A + (c + w) + (size_t)c * lda, lda, false, info, &gc));
             }
         }
         return hipSuccess;
@@ -305,10 +309,10 @@ hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
         double *l21 = A + k1 + (size_t)k * lda;                 // rest x kb
         double *d1 = A + k1 + (size_t)k1 * lda;                 // next diagonal block
         // next block column: its diagonal block (lower only) and the rows below it
-        CDF_HIP_RET(cdf::dgemm(s0, 0, 1, kb1, kb1, kb, -1.0, l21, lda, l21, lda, 1.0, d1, lda, true, info));
+        CDF_HIP_RET(cdf::dgemm(s0, 0, 1, kb1, kb1, kb, -1.0, l21, lda, l21, lda, 1.0, d1, lda, true, info, &gc));
         if (rest > kb1)
             CDF_HIP_RET(cdf::dgemm(s0, 0, 1, rest - kb1, kb1, kb, -1.0, l21 + kb1, lda, l21, lda, 1.0, d1 + kb1, lda,
-                                   false, info));
+                                   false, info, &gc));
         if (rest > kb1) {
             CDF_HIP_RET(hipEventRecord(h->ev[0], s0));
             CDF_HIP_RET(hipStreamWaitEvent(s1, h->ev[0], 0));
@@ -316,7 +320,7 @@ hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
             CDF_HIP_RET(hipEventRecord(h->ev[1], s1));
             const int c2 = k1 + kb1;
             CDF_HIP_RET(cdf::dgemm(s0, 0, 1, n - c2, n - c2, kb, -1.0, l21 + kb1, lda, l21 + kb1, lda, 1.0,
-                                   A + c2 + (size_t)c2 * lda, lda, true, info));
+                                   A + c2 + (size_t)c2 * lda, lda, true, info, &gc));
             CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[1], 0));
         } else {
             CDF_HIP_RET(panel(s0, k1, kb1));
@@ -358,11 +362,12 @@ hipError_t offset_pivots(hipStream_t s, const int *ipiv_in, int *ipiv_out, int c
 // L^-1 of the unit lower triangle L (kb x kb) into Li: identity, then
 // blocked forward substitution (the same solve the in-place U12 path uses,
 // with the identity as right-hand side).
-hipError_t unit_lower_inverse(hipStream_t s, int kb, const double *L, int ldl, double *Li, int ldi, int *good) {
+hipError_t unit_lower_inverse(hipStream_t s, int kb, const double *L, int ldl, double *Li, int ldi, int *good,
+                              const GemmCtx *ctx) {
     if (kb <= 0) return hipSuccess;
     hipLaunchKernelGGL(eye_kernel, dim3((kb + 255) / 256, kb), dim3(256), 0, s, kb, Li, ldi, good);
     CDF_HIP_RET(hipGetLastError());
-    CDF_HIP_RET(trsm_blocked(s, TRSM_LLNU, kb, kb, L, ldl, Li, ldi, 64));
+    CDF_HIP_RET(trsm_blocked(s, TRSM_LLNU, kb, kb, L, ldl, Li, ldi, 64, ctx));
     // accepted while no entry exceeds kInverseBound: pivoting keeps
     // |L(i,j)| <= 1, and for the inverse's growth the products' rounding
     // error stays within a small multiple of substitution's
@@ -409,9 +414,11 @@ cdf_status_t cdf_create(cdf_handle_t *h) {
     cdf_handle_s *p = new (std::nothrow) cdf_handle_s();
     if (!p) return CDF_ERR_ALLOC;
     if (hipGetDevice(&p->device) != hipSuccess) { delete p; return CDF_ERR_HIP; }
-    int cus = 0;
+    int cus = 0, khz = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
         p->num_cus = cus;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) == hipSuccess && khz > 0)
+        p->wall_khz = khz;
     *h = p;
     return CDF_OK;
 }
@@ -424,24 +431,37 @@ cdf_status_t cdf_destroy(cdf_handle_t h) {
     if (h->aux2) { (void)hipStreamSynchronize(h->aux2); (void)hipStreamDestroy(h->aux2); }
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
+    cdf::prof_free(h->prof);
     delete h;
     return CDF_OK;
 }
 
+cdf_status_t cdf_device_status(cdf_handle_t h) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    h->bad_arg = 0;
+    CDF_HIP_TRY(hipStreamSynchronize(h->stream));
+    if (h->aux) CDF_HIP_TRY(hipStreamSynchronize(h->aux));
+    if (h->aux2) CDF_HIP_TRY(hipStreamSynchronize(h->aux2));
+    if (!h->ws) return CDF_OK;
+    int e = 0;
+    CDF_HIP_TRY(hipMemcpy(&e, cdf::leaf_error_word(h), sizeof(int), hipMemcpyDeviceToHost));
+    return e != 0 ? CDF_ERR_TIMEOUT : CDF_OK;
+}
+
 cdf_status_t cdf_profile_begin(cdf_handle_t h) {
     if (!h) return CDF_ERR_INVALID_ARG;
-    cdf::prof_enable();
+    CDF_HIP_TRY(cdf::prof_enable(&h->prof));
     return CDF_OK;
 }
 
 cdf_status_t cdf_profile_end(cdf_handle_t h, int kernel, long long *launches, double *total_ms, double *flops) {
     if (!h) return CDF_ERR_INVALID_ARG;
     h->bad_arg = 0;
-    if (kernel < 0 || kernel > 4) { h->bad_arg = 2; return CDF_ERR_INVALID_ARG; }
+    if (kernel < 0 || kernel >= cdf::PROF_KINDS) { h->bad_arg = 2; return CDF_ERR_INVALID_ARG; }
     if (!launches) { h->bad_arg = 3; return CDF_ERR_INVALID_ARG; }
     if (!total_ms) { h->bad_arg = 4; return CDF_ERR_INVALID_ARG; }
     if (!flops) { h->bad_arg = 5; return CDF_ERR_INVALID_ARG; }
-    CDF_HIP_TRY(cdf::prof_collect(kernel, launches, total_ms, flops));
+    CDF_HIP_TRY(cdf::prof_collect(h->prof, kernel, launches, total_ms, flops));
     return CDF_OK;
 }
 
@@ -469,6 +489,7 @@ const char *cdf_status_string(cdf_status_t s) {
         case CDF_ERR_ALLOC: return "CDF_ERR_ALLOC";
         case CDF_ERR_NOT_CONVERGED: return "CDF_ERR_NOT_CONVERGED";
         case CDF_ERR_UNSUPPORTED: return "CDF_ERR_UNSUPPORTED";
+        case CDF_ERR_TIMEOUT: return "CDF_ERR_TIMEOUT";
     }
     return "CDF_ERR_UNKNOWN";
 }
@@ -486,6 +507,7 @@ cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value) {
     if (p == CDF_PARAM_VBATCH_WG_PER_CU && value > 2) return bad(h, 3);
     if (p == CDF_PARAM_GEMM_WG_PER_CU && !(value == 0 || (value >= 3 && value <= 5))) return bad(h, 3);
     if (p == CDF_PARAM_LU_U12 && value > 1) return bad(h, 3);
+    if (p == CDF_PARAM_TEST_EXCHANGE_FAIL && value > 1) return bad(h, 3);
     h->params[p] = value;
     return CDF_OK;
 }
@@ -621,8 +643,8 @@ cdf_status_t cdf_dgemm_update(cdf_handle_t h, int m, int n, int k, const double 
     if (!A) return bad(h, 5);
     if (!B) return bad(h, 7);
     if (!C) return bad(h, 9);
-    cdf::set_gemm_wg_per_cu(h->params[CDF_PARAM_GEMM_WG_PER_CU]);
-    CDF_HIP_TRY(cdf::dgemm(h->stream, 0, 0, m, n, k, -1.0, A, lda, B, ldb, 1.0, C, ldc, false));
+    const cdf::GemmCtx gc = cdf::gemm_ctx(h);
+    CDF_HIP_TRY(cdf::dgemm(h->stream, 0, 0, m, n, k, -1.0, A, lda, B, ldb, 1.0, C, ldc, false, nullptr, &gc));
     return CDF_OK;
 }
 

@@ -19,8 +19,8 @@
 // 8 tile-rows so the A and B panels an XCD touches stay in its L2.
 #include "internal.h"
 
-#include <atomic>
 #include <mutex>
+#include <new>
 #include <vector>
 
 namespace {
@@ -236,9 +236,9 @@ typedef __attribute__((address_space(1))) void glob_void;
 // Workgroups resident per CU: the kernel's 32 KB of static LDS fits five in
 // a CU's 160 KB; dynamic LDS that the kernel never touches pads each one so
 // that fewer fit, leaving LDS (and registers) to kernels on other streams.
-std::atomic<int> g_dl_wgs{5};
-inline size_t dl_pad_bytes() {
-    const int w = g_dl_wgs.load(std::memory_order_relaxed);
+// The count comes with each call (the calling handle's setting).
+inline size_t dl_pad_bytes(int wg_per_cu) {
+    const int w = wg_per_cu >= 3 && wg_per_cu <= 5 ? wg_per_cu : 5;
     if (w >= 5) return 0;
     return (size_t)(160 * 1024 / w) / 512 * 512 - 32 * 1024;
 }
@@ -352,9 +352,10 @@ bool dl_ok(int tb, int m, int n, int k, const double *A, int lda, const double *
 
 template <int TA, int TB, bool LOWER>
 hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double *A, int lda,
-                  const double *B, int ldb, double beta, double *C, int ldc, const int *stop) {
+                  const double *B, int ldb, double beta, double *C, int ldc, const int *stop,
+                  const cdf::GemmCtx &ctx) {
     constexpr int BM = Shape<TB>::B, BN = Shape<TB>::B;
-    const int kind = LOWER ? 4 : TA * 2 + TB;
+    const int kind = ctx.tag >= 0 ? ctx.tag : (LOWER ? cdf::PROF_SYRK : TA * 2 + TB);
     const double flops = LOWER ? (double)m * (m + 1) * k : 2.0 * m * n * k;
     if (TA == 0 && dl_ok(TB, m, n, k, A, lda, B, ldb)) {
         // direct-to-LDS kernel, 64 x 64 tiles
@@ -362,12 +363,11 @@ hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double
         const long long nwg = LOWER ? (long long)tm64 * (tm64 + 1) / 2 : (long long)tm64 * tn64;
         if (nwg <= 0) return hipSuccess;
         if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
-        const int slot = cdf::prof_begin(s, kind, flops);
-        hipLaunchKernelGGL((dgemm_dl_kernel<TB, LOWER>), dim3((unsigned)nwg), dim3(NT), dl_pad_bytes(), s, m, n, k,
-                           alpha, A, lda,
-                           B, ldb, beta, C, ldc, tm64, tn64, stop);
+        const int slot = cdf::prof_begin(ctx.prof, s, kind, flops);
+        hipLaunchKernelGGL((dgemm_dl_kernel<TB, LOWER>), dim3((unsigned)nwg), dim3(NT), dl_pad_bytes(ctx.wg_per_cu), s,
+                           m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tm64, tn64, stop);
         const hipError_t e = hipGetLastError();
-        cdf::prof_end(s, slot);
+        cdf::prof_end(ctx.prof, s, slot);
         return e;
     }
     const int tiles_m = (m + BM - 1) / BM;
@@ -375,11 +375,11 @@ hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double
     long long nwg = LOWER ? (long long)tiles_m * (tiles_m + 1) / 2 : (long long)tiles_m * tiles_n;
     if (nwg <= 0) return hipSuccess;
     if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
-    const int slot = cdf::prof_begin(s, kind, flops);
+    const int slot = cdf::prof_begin(ctx.prof, s, kind, flops);
     hipLaunchKernelGGL((dgemm_kernel<TA, TB, LOWER>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k,
                        alpha, A, lda, B, ldb, beta, C, ldc, tiles_m, tiles_n, stop);
     const hipError_t e = hipGetLastError();
-    cdf::prof_end(s, slot);
+    cdf::prof_end(ctx.prof, s, slot);
     return e;
 }
 
@@ -387,7 +387,6 @@ hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double
 
 namespace cdf {
 
-namespace {
 struct ProfRec {
     hipEvent_t a, b;
     int kind;
@@ -399,85 +398,100 @@ struct ProfState {
     std::vector<ProfRec> recs;  // recs[0, used) are live; events reused across sessions
     size_t used = 0;
 };
-ProfState &prof_state() {
-    static ProfState st;
-    return st;
-}
-}  // namespace
 
-int prof_begin(hipStream_t s, int kind, double flops) {
-    ProfState &st = prof_state();
-    std::lock_guard<std::mutex> lk(st.mu);
-    if (!st.on) return -1;
-    if (st.used == st.recs.size()) {
+int prof_begin(ProfState *st, hipStream_t s, int kind, double flops) {
+    if (!st) return -1;
+    std::lock_guard<std::mutex> lk(st->mu);
+    if (!st->on) return -1;
+    if (st->used == st->recs.size()) {
         ProfRec r{nullptr, nullptr, 0, 0.0};
         if (hipEventCreate(&r.a) != hipSuccess) return -1;
         if (hipEventCreate(&r.b) != hipSuccess) { (void)hipEventDestroy(r.a); return -1; }
-        st.recs.push_back(r);
+        st->recs.push_back(r);
     }
-    ProfRec &r = st.recs[st.used];
+    ProfRec &r = st->recs[st->used];
     r.kind = kind;
     r.flops = flops;
     if (hipEventRecord(r.a, s) != hipSuccess) return -1;
-    return (int)st.used++;
+    return (int)st->used++;
 }
 
-void prof_end(hipStream_t s, int slot) {
-    if (slot < 0) return;
-    ProfState &st = prof_state();
-    std::lock_guard<std::mutex> lk(st.mu);
-    if ((size_t)slot < st.used) (void)hipEventRecord(st.recs[slot].b, s);
+void prof_end(ProfState *st, hipStream_t s, int slot) {
+    if (!st || slot < 0) return;
+    std::lock_guard<std::mutex> lk(st->mu);
+    if ((size_t)slot < st->used) (void)hipEventRecord(st->recs[slot].b, s);
 }
 
-void prof_enable() {
-    ProfState &st = prof_state();
-    std::lock_guard<std::mutex> lk(st.mu);
-    st.on = true;
-    st.used = 0;
+hipError_t prof_enable(ProfState **pst) {
+    if (!*pst) {
+        *pst = new (std::nothrow) ProfState();
+        if (!*pst) return hipErrorOutOfMemory;
+    }
+    std::lock_guard<std::mutex> lk((*pst)->mu);
+    (*pst)->on = true;
+    (*pst)->used = 0;
+    return hipSuccess;
 }
 
-hipError_t prof_collect(int kind, long long *launches, double *total_ms, double *flops) {
-    ProfState &st = prof_state();
-    std::lock_guard<std::mutex> lk(st.mu);
+hipError_t prof_collect(ProfState *st, int kind, long long *launches, double *total_ms, double *flops) {
+    *launches = 0;
+    *total_ms = 0.0;
+    *flops = 0.0;
+    if (!st) return hipSuccess;
+    std::lock_guard<std::mutex> lk(st->mu);
     long long cnt = 0;
     double ms = 0.0, fl = 0.0;
     hipError_t err = hipSuccess;
-    {
-        for (size_t i = 0; i < st.used; ++i) {
-            const ProfRec &r = st.recs[i];
-            if (r.kind != kind) continue;
-            float t = 0.0f;
-            if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
-                err = hipErrorUnknown;
-                continue;
-            }
-            ++cnt;
-            ms += t;
-            fl += r.flops;
+    for (size_t i = 0; i < st->used; ++i) {
+        const ProfRec &r = st->recs[i];
+        if (r.kind != kind) continue;
+        float t = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+            err = hipErrorUnknown;
+            continue;
         }
+        ++cnt;
+        ms += t;
+        fl += r.flops;
     }
-    st.on = false;  // records stay readable until the next prof_enable
+    st->on = false;  // records stay readable until the next prof_enable
     *launches = cnt;
     *total_ms = ms;
     *flops = fl;
     return err;
 }
 
-hipError_t dgemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha, const double *A,
-                 int lda, const double *B, int ldb, double beta, double *C, int ldc, bool lower,
-                 const int *stop) {
-    if (m <= 0 || n <= 0) return hipSuccess;
-    if (lower) {
-        if (m != n) return hipErrorInvalidValue;
-        if (ta == 0 && tb == 1) return launch<0, 1, true>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop);
-        return hipErrorInvalidValue;
+void prof_free(ProfState *st) {
+    if (!st) return;
+    for (auto &r : st->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
     }
-    if (ta == 0 && tb == 0) return launch<0, 0, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop);
-    if (ta == 0 && tb == 1) return launch<0, 1, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop);
-    if (ta == 1 && tb == 0) return launch<1, 0, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop);
-    return launch<1, 1, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop);
+    delete st;
 }
 
-void set_gemm_wg_per_cu(int w) { g_dl_wgs.store(w >= 3 && w <= 5 ? w : 5, std::memory_order_relaxed); }
+GemmCtx gemm_ctx(cdf_handle_t h, int tag) {
+    GemmCtx c;
+    c.wg_per_cu = h->params[CDF_PARAM_GEMM_WG_PER_CU];
+    c.prof = h->prof;
+    c.tag = tag;
+    return c;
+}
+
+hipError_t dgemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha, const double *A,
+                 int lda, const double *B, int ldb, double beta, double *C, int ldc, bool lower,
+                 const int *stop, const GemmCtx *ctx) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    const GemmCtx c = ctx ? *ctx : GemmCtx();
+    if (lower) {
+        if (m != n) return hipErrorInvalidValue;
+        if (ta == 0 && tb == 1) return launch<0, 1, true>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop, c);
+        return hipErrorInvalidValue;
+    }
+    if (ta == 0 && tb == 0) return launch<0, 0, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop, c);
+    if (ta == 0 && tb == 1) return launch<0, 1, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop, c);
+    if (ta == 1 && tb == 0) return launch<1, 0, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop, c);
+    return launch<1, 1, false>(s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stop, c);
+}
 
 }  // namespace cdf

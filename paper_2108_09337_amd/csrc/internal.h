@@ -8,6 +8,10 @@
 
 #include "cdnafact.h"
 
+namespace cdf {
+struct ProfState;
+}
+
 struct cdf_handle_s {
     int device = 0;
     int num_cus = 256;
@@ -20,7 +24,10 @@ struct cdf_handle_s {
     hipStream_t aux = nullptr;   // second stream for look-ahead (default priority)
     hipStream_t aux2 = nullptr;  // third stream: LU interchanges on finished L columns
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    int params[CDF_PARAM_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int params[CDF_PARAM_COUNT] = {};
+    int wall_khz = 100000;       // rate of the device's constant wall clock
+    int leaf_occ[2] = {0, 0};    // resident leaf workgroups per CU (R = 1, 2); 0 = not yet queried
+    cdf::ProfState *prof = nullptr;  // kernel-timing records (cdf_profile_begin / _end)
 };
 
 namespace cdf {
@@ -35,8 +42,13 @@ __device__ __forceinline__ void static_for(F &&f) {
     }
 }
 
-// Bytes at the head of the workspace reserved for the panel leaf's exchange.
+// Bytes at the head of the workspace reserved for the panel leaf's exchange
+// (its last 256 bytes hold the device error word of the bounded waits).
 constexpr size_t kLeafWsBytes = 512 * 1024;
+// Default budget of one wait of the leaf's grid exchange (microseconds).  A
+// legitimate wait lasts as long as the longest kernel beside the leaf keeps
+// CUs busy (tens of ms for the first trailing update at n = 65536).
+constexpr long long kLeafWaitUsDefault = 2000000;
 
 // Grows the handle's workspace to at least `bytes` (synchronizing the stream
 // before a reallocation).  Returns CDF_ERR_ALLOC on failure or above the cap.
@@ -44,13 +56,33 @@ cdf_status_t ws_reserve(cdf_handle_t h, size_t bytes);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Kernel-timing records of a handle (cdf_profile_begin / _end) and the kinds
+// they are filed under.
+enum ProfKind { PROF_NN = 0, PROF_NT = 1, PROF_TN = 2, PROF_TT = 3, PROF_SYRK = 4, PROF_U12 = 5, PROF_KINDS = 6 };
+int prof_begin(ProfState *st, hipStream_t s, int kind, double flops);  // -1 when not timing
+void prof_end(ProfState *st, hipStream_t s, int slot);
+hipError_t prof_enable(ProfState **st);  // creates the records on first use
+hipError_t prof_collect(ProfState *st, int kind, long long *launches, double *total_ms, double *flops);
+void prof_free(ProfState *st);
+
+// Per-call options of the FP64 GEMM: update-GEMM workgroups resident per CU
+// (3..5; 0 = 5), the calling handle's timing records (null: not timed), and
+// the kind a timed launch is filed under (-1: by its shape).
+struct GemmCtx {
+    int wg_per_cu = 0;
+    ProfState *prof = nullptr;
+    int tag = -1;
+};
+GemmCtx gemm_ctx(cdf_handle_t h, int tag = -1);
+
 // C = beta*C + alpha*op(A)*op(B); op(A) is m x k, op(B) is k x n.
 // ta: 0 -> A is m x k, 1 -> A is k x m (op = transpose); same for tb.
 // lower: only the lower triangle (i >= j) of C is read or written (C square).
 // stop: optional device flag; a nonzero value makes the launch a no-op.
+// ctx: launch options (null: five workgroups per CU, not timed).
 hipError_t dgemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha,
                  const double *A, int lda, const double *B, int ldb, double beta,
-                 double *C, int ldc, bool lower, const int *stop = nullptr);
+                 double *C, int ldc, bool lower, const int *stop = nullptr, const GemmCtx *ctx = nullptr);
 
 // The binary64 factorizations behind cdf_dgetrf / cdf_dpotrf on the handle's
 // stream (look-ahead on its second stream); getrf_fp64 takes a device work
@@ -67,25 +99,13 @@ hipError_t potrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *info);
 // Creates the handle's second stream (default priority) and its two events.
 hipError_t ensure_aux(cdf_handle_t h);
 
-// Workgroups of the FP64 update GEMM resident per CU (3..5; 0 = 5).  The
-// factorization entry points set it from their handle before launching;
-// dgemm reads it at each launch (process-wide).
-void set_gemm_wg_per_cu(int w);
-
 // Li (kb x kb, leading dimension ldi) = L^-1 for the unit lower triangle of
 // L (kb x kb, leading dimension ldl), by blocked forward substitution; then
 // *good = 1, unless an entry exceeds kInverseBound in magnitude: then Li is
 // set to the identity and *good = 0 (the caller solves by substitution).
 constexpr double kInverseBound = 16.0;
-hipError_t unit_lower_inverse(hipStream_t s, int kb, const double *L, int ldl, double *Li, int ldi, int *good);
-
-// Kernel timing (process-wide): prof_begin records an event before a launch
-// and returns a slot (-1 when timing is off), prof_end records the closing
-// event; prof_collect sums launches / ms / flops of one kernel kind and stops.
-int prof_begin(hipStream_t s, int kind, double flops);
-void prof_end(hipStream_t s, int slot);
-void prof_enable();
-hipError_t prof_collect(int kind, long long *launches, double *total_ms, double *flops);
+hipError_t unit_lower_inverse(hipStream_t s, int kb, const double *L, int ldl, double *Li, int ldi, int *good,
+                              const GemmCtx *ctx = nullptr);
 
 // LU panel leaf: factor the m x n (n <= 32) column block at A with partial
 // pivoting; writes absolute 1-based pivots ipiv[0..n) (row offset `row0`
@@ -96,6 +116,13 @@ hipError_t prof_collect(int kind, long long *launches, double *total_ms, double 
 hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, int lda, int *ipiv,
                    int row0, int *info, int info_base, int rows_per_thread, double *region, int region_rows,
                    int region_cols, int c0);
+// The leaf's device error word (set when a wait of its exchange ran out of
+// budget) and its reset, ordered on `stream`; every factorization that runs
+// leaves resets it first.  Needs the handle's workspace.
+int *leaf_error_word(cdf_handle_t h);
+// The leaf kernel for two rows per thread (for hipLaunchKernel / occupancy).
+const void *leaf_kernel_r2();
+hipError_t leaf_reset_error(cdf_handle_t h, hipStream_t stream);
 
 // Recursive LU panel of columns [c0, c0+w) of the m x ncols region A (rows
 // [c0, m)) on stream s; interchanges are applied to all other columns of the
@@ -145,7 +172,7 @@ hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const dou
 // Full triangular solve with a large n x n factor (blocked: bs-wide diagonal
 // solves + GEMM updates; bs <= 256).
 hipError_t trsm_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const double *T, int ldt,
-                        double *B, int ldb, int bs = 128);
+                        double *B, int ldb, int bs = 128, const GemmCtx *ctx = nullptr);
 // Solve with few right-hand sides (ncols <= 4): 64-row diagonal blocks solved
 // by one wave in registers, off-diagonal blocks applied GEMV-style.  With a
 // device work area `sync` of trsv_sync_ints(n) ints (LLNU, LLNN, LUNN), the

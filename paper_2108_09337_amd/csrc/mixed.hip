@@ -576,9 +576,10 @@ inline int mixed_nb(cdf_handle_t h, int n) {
 // updated (when the panel width is a multiple of the quantization tile, so
 // both parts of the update keep the tile exponents of U12).
 hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *ipiv, MixedWs &w, int nb, int *info) {
-    cdf::set_gemm_wg_per_cu(h->params[CDF_PARAM_GEMM_WG_PER_CU]);
     hipStream_t s0 = h->stream;
+    const cdf::GemmCtx gu = cdf::gemm_ctx(h, cdf::PROF_U12);
     CDF_HIP_RET(cdf::ensure_aux(h));
+    CDF_HIP_RET(cdf::leaf_reset_error(h, s0));
     hipStream_t s1 = h->aux;
     const int kp = kpad_of(nb);
     const bool split = nb % QT == 0;
@@ -589,7 +590,7 @@ hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *i
         const int m = n - k;
         CDF_HIP_RET(cdf::convert_s2d(s, m, kb, W + k + (size_t)k * ldw, ldw, P, m, false));
         CDF_HIP_RET(cdf::lu_panel(h, s, m, kb, P, m, w.ipt, info, 0, kb, k));
-        if (inv && k + kb < n) CDF_HIP_RET(cdf::unit_lower_inverse(s, kb, P, m, w.Li[buf], nb, w.good + buf));
+        if (inv && k + kb < n) CDF_HIP_RET(cdf::unit_lower_inverse(s, kb, P, m, w.Li[buf], nb, w.good + buf, &gu));
         hipLaunchKernelGGL(add_offset_kernel, dim3((kb + 255) / 256), dim3(256), 0, s, w.ipt, ipiv + k, kb, k);
         CDF_HIP_RET(hipGetLastError());
         return cdf::convert_d2s(s, m, kb, P, m, W + k + (size_t)k * ldw, ldw, false);
@@ -612,10 +613,11 @@ hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *i
             // substitution in place only where the guard rejected L11^-1 (the
             // GEMM with the identity then copies exactly)
             CDF_HIP_RET(cdf::trsm_small(s0, cdf::TRSM_LLNU, kb, rest, w.P[it & 1], m, w.U, kb, w.good + (it & 1), 512));
-            CDF_HIP_RET(cdf::dgemm(s0, 0, 0, kb, rest, kb, 1.0, w.Li[it & 1], nb, w.U, kb, 0.0, w.U2, kb, false));
+            CDF_HIP_RET(cdf::dgemm(s0, 0, 0, kb, rest, kb, 1.0, w.Li[it & 1], nb, w.U, kb, 0.0, w.U2, kb, false,
+                                   nullptr, &gu));
             CDF_HIP_RET(cdf::convert_d2s(s0, kb, rest, w.U2, kb, w12, ldw, false));
         } else {
-            CDF_HIP_RET(cdf::trsm_blocked(s0, cdf::TRSM_LLNU, kb, rest, w.P[it & 1], m, w.U, kb, 64));
+            CDF_HIP_RET(cdf::trsm_blocked(s0, cdf::TRSM_LLNU, kb, rest, w.P[it & 1], m, w.U, kb, 64, &gu));
             CDF_HIP_RET(cdf::convert_d2s(s0, kb, rest, w.U, kb, w12, ldw, false));
         }
         CDF_HIP_RET(cdf::quantize(s0, fmt, rest, kb, w21, ldw, QT, kb, w.QA, kp, w.ea, true));
@@ -723,6 +725,7 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
     CDF_HIP_TRY(hipStreamSynchronize(s));
     *iters = 0;
     *resid = INFINITY;
+    if (hinfo == CDF_INFO_TIMEOUT) return CDF_ERR_TIMEOUT;
     if (hinfo != 0) return CDF_ERR_NOT_CONVERGED;
     auto tri = [&](cdf::TrsmKind kind, double *Y, int ldy) -> hipError_t {
         return nrhs <= 4 ? cdf::trsv_blocked(s, kind, n, nrhs, w.Wd, n, Y, ldy, w.tsync)

@@ -581,7 +581,7 @@ hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const dou
 // Blocked solve with an n x n triangle: 128-wide diagonal solves, the rest
 // of the right-hand block updated with the FP64 GEMM.
 hipError_t trsm_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const double *T, int ldt,
-                        double *B, int ldb, int BS) {
+                        double *B, int ldb, int BS, const GemmCtx *ctx) {
     if (BS <= 0 || BS > MAXNB) return hipErrorInvalidValue;
     if (n <= 0 || ncols <= 0) return hipSuccess;
     if (kind == TRSM_LLNU || kind == TRSM_LLNN) {
@@ -590,7 +590,7 @@ hipError_t trsm_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const do
             CDF_HIP_RET(trsm_small(s, kind, kb, ncols, T + k + (size_t)k * ldt, ldt, B + k, ldb));
             if (k + kb < n)
                 CDF_HIP_RET(dgemm(s, 0, 0, n - k - kb, ncols, kb, -1.0, T + (k + kb) + (size_t)k * ldt, ldt,
-                                  B + k, ldb, 1.0, B + k + kb, ldb, false));
+                                  B + k, ldb, 1.0, B + k + kb, ldb, false, nullptr, ctx));
         }
         return hipSuccess;
     }
@@ -602,9 +602,10 @@ hipError_t trsm_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const do
             if (k > 0) {
                 if (kind == TRSM_LUNN)
                     CDF_HIP_RET(dgemm(s, 0, 0, k, ncols, kb, -1.0, T + (size_t)k * ldt, ldt, B + k, ldb, 1.0, B,
-                                      ldb, false));
+                                      ldb, false, nullptr, ctx));
                 else  // rows [0,k) -= L(k:k+kb, 0:k)^T X(k:k+kb)
-                    CDF_HIP_RET(dgemm(s, 1, 0, k, ncols, kb, -1.0, T + k, ldt, B + k, ldb, 1.0, B, ldb, false));
+                    CDF_HIP_RET(dgemm(s, 1, 0, k, ncols, kb, -1.0, T + k, ldt, B + k, ldb, 1.0, B, ldb, false,
+                                      nullptr, ctx));
             }
         }
         return hipSuccess;

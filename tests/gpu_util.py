@@ -36,3 +36,83 @@ def first_pivot_mismatch(ip_gpu, ip_or, a, oracle):
     g, o = int(ip_gpu[k]) - 1 - k, int(ip_or[k]) - 1 - k
     gap = abs(col[o] - col[g]) / max(col[o], 1e-300)
     return f"step {k}: gpu row {g + k} |a|={col[g]!r}, oracle row {o + k} |a|={col[o]!r}, rel gap {gap:.3e}"
+
+
+# ----------------------------------------------------------------- large n
+# Checks of GPU results at sizes where the CPU oracle cannot factor the whole
+# matrix: invariants evaluated with torch's FP64 matrix products (rocBLAS),
+# which share nothing with the library's kernels.
+
+def perm_from_ipiv(ipiv, n):
+    """Row permutation p (0-based): (P A)[i] = A[p[i]] for LAPACK interchanges."""
+    p = np.arange(n)
+    for k, piv in enumerate(np.asarray(ipiv)):
+        j = int(piv) - 1
+        p[k], p[j] = p[j], p[k]
+    return p
+
+
+def lu_backward_error_torch(torch, A0, LU, ipiv, strip=4096):
+    """||P A - L U||_F / (||A||_F n eps) in FP64 on the GPU, by row strips.
+
+    A0, LU: n x n device tensors (any strides), ipiv: host int array."""
+    n = A0.shape[0]
+    perm = torch.from_numpy(perm_from_ipiv(ipiv, n)).to(A0.device)
+    U = torch.triu(LU).contiguous()
+    ss = torch.zeros((), dtype=torch.float64, device=A0.device)
+    for r0 in range(0, n, strip):
+        r1 = min(n, r0 + strip)
+        Ls = LU[r0:r1, :r1].contiguous()
+        rows = torch.arange(r0, r1, device=A0.device)[:, None]
+        cols = torch.arange(0, r1, device=A0.device)[None, :]
+        Ls = torch.where(cols < rows, Ls, torch.where(cols == rows, torch.ones_like(Ls), torch.zeros_like(Ls)))
+        R = A0[perm[r0:r1], :] - Ls @ U[:r1, :]
+        ss += (R * R).sum()
+        del Ls, R
+    del U
+    an = torch.linalg.norm(A0.contiguous() if not A0.is_contiguous() else A0)
+    return float(torch.sqrt(ss) / (an * n * EPS))
+
+
+def chol_backward_error_torch(torch, A0, L, strip=4096):
+    """||A - L L^T||_F / (||A||_F n eps) on the lower triangle's symmetric
+    extension (as the oracle defines it), FP64 on the GPU, by row strips."""
+    n = A0.shape[0]
+    ss = torch.zeros((), dtype=torch.float64, device=A0.device)
+    an = torch.zeros((), dtype=torch.float64, device=A0.device)
+    for r0 in range(0, n, strip):
+        r1 = min(n, r0 + strip)
+        rows = torch.arange(r0, r1, device=A0.device)[:, None]
+        cols = torch.arange(0, r1, device=A0.device)[None, :]
+        low = cols <= rows
+        w = torch.where(cols == rows, 1.0, 2.0).to(torch.float64) * low  # symmetric extension weights
+        Ls = torch.where(low, L[r0:r1, :r1], 0.0).contiguous()
+        Lt = torch.tril(L[:r1, :r1]).contiguous()
+        R = torch.where(low, A0[r0:r1, :r1], 0.0) - Ls @ Lt.t()
+        ss += (w * R * R).sum()
+        a = torch.where(low, A0[r0:r1, :r1], 0.0)
+        an += (w * a * a).sum()
+        del Ls, Lt, R, a, w
+    return float(torch.sqrt(ss) / (torch.sqrt(an) * n * EPS))
+
+
+def lu_partial_tolerance(lu_k, k, n_full):
+    """Elementwise tolerance for the first k steps of an n_full x n_full LU,
+    from the oracle's k-step result on a column subset (first k columns then
+    sampled ones): 16 n eps (|L||U|)_ij, divided by |u_jj| for L entries.
+    Entries outside L[:, :k] and U[:k, :] get an infinite tolerance."""
+    m, c = lu_k.shape
+    L = np.tril(lu_k[:, :k], -1)
+    L[np.arange(k), np.arange(k)] = 1.0
+    U = np.triu(lu_k[:k, :])
+    tol = np.full((m, c), np.inf)
+    LU = np.abs(L) @ np.abs(U)
+    t = 16 * n_full * EPS * LU + 1e-300
+    d = np.abs(np.diag(U[:, :k]))
+    d[d == 0] = 1.0
+    low = np.tril(np.ones((m, k), dtype=bool), -1)
+    tl = t[:, :k] / d[None, :]
+    tol[:, :k] = np.where(low, tl, np.inf)
+    upper = np.triu(np.ones((k, c), dtype=bool))
+    tol[:k, :] = np.where(upper, t[:k, :], tol[:k, :])
+    return tol

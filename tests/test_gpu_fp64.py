@@ -105,6 +105,161 @@ def test_lu_leaf_multi_workgroup(oracle_mod, rows):
     assert oracle_mod.lu_backward_error(a, lu, ip) <= 10.0
 
 
+def test_lu_parity_n8192_full(oracle_mod):
+    """The smallest LU size of the benchmark's size set (n = 8192), whole
+    matrix against the oracle: identical pivots, every entry within the
+    rounding-order tolerance, backward error <= 10.  The leaf runs with 32
+    workgroups at the default parameters."""
+    n = 8192
+    a = workloads.lu_uniform(n, seed=8192)
+    lu_or, ip_or, info_or = oracle_mod.dgetrf(a)
+    lu, ip, info = _lu_gpu(a)
+    assert info == info_or == 0
+    if not np.array_equal(ip, ip_or):
+        pytest.fail(gpu_util.first_pivot_mismatch(ip, ip_or, a, oracle_mod))
+    # tolerance 16 n eps (|L||U|)_ij (/ |u_jj| for L) with |L||U| from the
+    # oracle's factors, formed with torch's FP64 product on the GPU
+    Lo = torch.from_numpy(np.tril(lu_or, -1) + np.eye(n)).cuda().abs()
+    Uo = torch.from_numpy(np.triu(lu_or)).cuda().abs()
+    LU = (Lo @ Uo).cpu().numpy()
+    del Lo, Uo
+    tol = 16 * n * gpu_util.EPS * LU + 1e-300
+    d = np.abs(np.diag(lu_or)).copy()
+    low = np.tril(np.ones((n, n), dtype=bool), -1)
+    tol[low] = (tol / d[None, :])[low]
+    err = np.abs(lu - lu_or)
+    assert np.all(err <= tol), float(np.max(err / tol))
+    A0 = torch.from_numpy(a).cuda()
+    be = gpu_util.lu_backward_error_torch(torch, A0, torch.from_numpy(lu).cuda(), ip)
+    assert be <= 10.0, be
+
+
+def test_chol_parity_n8192_full(oracle_mod):
+    """Cholesky at n = 8192, whole lower triangle against the oracle."""
+    n = 8192
+    a = workloads.spd_bbt(n, seed=8193)
+    l_or, info_or = oracle_mod.dpotrf(a)
+    l, info = _chol_gpu(a)
+    assert info == info_or == 0
+    Lo = torch.from_numpy(np.tril(l_or)).cuda().abs()
+    LL = (Lo @ Lo.t().contiguous()).cpu().numpy()
+    del Lo
+    d = np.abs(np.diag(l_or))
+    tol = np.tril(16 * n * gpu_util.EPS * LL / d[None, :]) + 1e-300
+    err = np.abs(np.tril(l) - np.tril(l_or))
+    assert np.all(err <= tol), float(np.max(err / tol))
+    assert np.array_equal(np.triu(l, 1), np.triu(a, 1)), "upper triangle was written"
+    be = gpu_util.chol_backward_error_torch(torch, torch.from_numpy(a).cuda(), torch.from_numpy(l).cuda())
+    assert be <= 10.0, be
+
+
+@pytest.mark.parametrize("n,k", [(32768, 1024)])
+def test_lu_parity_large_first_steps(oracle_mod, n, k):
+    """A size of the benchmark's size set (n = 32768) at default parameters:
+    512-wide panels, and a leaf grid of 128 workgroups, so every lane of the
+    polling wave reads two workgroups' tags.  The oracle factors the first k
+    columns plus 256 sampled ones for k steps (the first k steps of
+    elimination read nothing else), which fixes the first k pivots, the
+    first k columns of L (up to the later interchanges, taken from the GPU's
+    pivots) and rows [0, k) of U in the sampled columns.  The whole factor is
+    held to the backward-error bound with torch's FP64 products."""
+    A0 = workloads.lu_uniform_torch(n, seed=32768)
+    rng = np.random.default_rng(5)
+    sample = np.sort(rng.choice(np.arange(k, n), 256, replace=False))
+    cols = np.concatenate([np.arange(k), sample])
+    a_sub = np.asfortranarray(A0[:, torch.from_numpy(cols).cuda()].cpu().numpy())
+    A = cdf.cm_empty(n, n)
+    A.copy_(A0)
+    ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    cdf.dgetrf(A, ipiv, info)
+    assert cdf.device_status() == cdf.CDF_OK
+    assert int(info.item()) == 0
+    ip = ipiv.cpu().numpy()
+    lu_k, ip_k, info_k = oracle_mod.dgetrf(a_sub, ksteps=k)
+    assert info_k == 0
+    if not np.array_equal(ip[:k], ip_k[:k]):
+        j = int(np.nonzero(ip[:k] != ip_k[:k])[0][0])
+        part, _, _ = oracle_mod.dgetrf(np.asfortranarray(a_sub[:, :j + 1]), ksteps=j)
+        col = np.abs(part[j:, j])
+        g, o = int(ip[j]) - 1 - j, int(ip_k[j]) - 1 - j
+        pytest.fail(f"step {j}: gpu row {g + j} |a|={col[g]!r}, oracle row {o + j} |a|={col[o]!r}")
+    tol = gpu_util.lu_partial_tolerance(lu_k, k, n)
+    # the GPU's later interchanges (steps >= k) also moved rows of L[:, :k]
+    perm = gpu_util.perm_from_ipiv(np.concatenate([np.arange(1, k + 1), ip[k:]]), n)
+    got = np.zeros((n, k + len(sample)))
+    got[:, :k] = A[:, :k].cpu().numpy()
+    got[:k, k:] = A[:k, torch.from_numpy(sample).cuda()].cpu().numpy()
+    want = lu_k.copy()
+    want[:, :k] = want[perm, :k]
+    tol[:, :k] = tol[perm, :k]
+    err = np.abs(got - want)
+    assert np.all(err <= tol), float(np.nanmax(np.where(np.isfinite(tol), err / tol, 0.0)))
+    be = gpu_util.lu_backward_error_torch(torch, A0, A, ip)
+    assert be <= 10.0, be
+
+
+@pytest.mark.parametrize("n,nb", [(1300, 256), (600, 64)])
+def test_lu_exchange_timeout_returns(oracle_mod, n, nb):
+    """The leaf's grid-exchange waits are bounded.  With the testing switch
+    that makes every wait of a multi-workgroup leaf wait for a tag nobody
+    writes, each wait gives up after its budget (200 us here): info reads
+    CDF_INFO_TIMEOUT, cdf_device_status reports CDF_ERR_TIMEOUT, the pivots
+    stay in range, and every kernel of the call ends.  The same handle then
+    factors normally, matching the oracle."""
+    a = workloads.lu_uniform(n, seed=91)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        h = cdf.handle()
+        h.set_param("lu_nb", nb)
+        h.set_param("leaf_wait_us", 200)
+        h.set_param("test_exchange_fail", 1)
+        A = cdf.to_device(a)
+        ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        cdf.dgetrf(A, ipiv, info, h)
+        assert cdf.device_status(h) == cdf.CDF_ERR_TIMEOUT
+        assert int(info.item()) == cdf.CDF_INFO_TIMEOUT
+        ip = ipiv.cpu().numpy()
+        assert np.all((ip >= np.arange(1, n + 1)) & (ip <= n))
+        h.set_param("test_exchange_fail", 0)
+        h.set_param("leaf_wait_us", 0)
+        A = cdf.to_device(a)
+        info.fill_(-7)
+        cdf.dgetrf(A, ipiv, info, h)
+        assert cdf.device_status(h) == cdf.CDF_OK
+        lu, ip = cdf.to_host(A), ipiv.cpu().numpy()
+        h.set_param("lu_nb", 0)
+    assert int(info.item()) == 0
+    lu_or, ip_or, _ = oracle_mod.dgetrf(a)
+    assert np.array_equal(ip, ip_or)
+    tol = gpu_util.lu_parity_tolerance(lu_or)
+    assert np.all(np.abs(lu - lu_or) <= tol)
+
+
+def test_lu_exchange_timeout_mixed_lu():
+    """The mixed-precision LU runs the same leaf: a forced exchange timeout
+    comes back from the solver as CDF_ERR_TIMEOUT."""
+    n = 700
+    a = workloads.diag_dominant(n, seed=3)
+    b = workloads.rhs_uniform(n, 1, seed=4)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        h = cdf.handle()
+        h.set_param("leaf_wait_us", 200)
+        h.set_param("test_exchange_fail", 1)
+        A, B = cdf.to_device(a), cdf.to_device(b)
+        X = torch.empty_like(B)
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        with pytest.raises(cdf.CdfError) as e:
+            cdf.dgesv_mixed("bf16", A, B, X, info, h=h)
+        assert e.value.status == cdf.CDF_ERR_TIMEOUT
+        h.set_param("test_exchange_fail", 0)
+        h.set_param("leaf_wait_us", 0)
+        r = cdf.dgesv_mixed("bf16", A, B, X, info, h=h)
+    assert r["converged"] and r["scaled_resid"] <= 16
+
+
 @pytest.mark.parametrize("nb", [64, 256])
 def test_lu_exact_factors(oracle_mod, nb):
     """A = L U with small dyadic L and integer U (identity pivots): formed by
