@@ -52,47 +52,65 @@ def perm_from_ipiv(ipiv, n):
     return p
 
 
-def lu_backward_error_torch(torch, A0, LU, ipiv, strip=4096):
-    """||P A - L U||_F / (||A||_F n eps) in FP64 on the GPU, by row strips.
+def lu_backward_error_torch(torch, A0, LU, ipiv, bs=8192):
+    """||P A - L U||_F / (||A||_F n eps) in FP64 on the GPU, in bs x bs blocks
+    (masks by broadcasting; no single kernel touches more than one block).
 
     A0, LU: n x n device tensors (any strides), ipiv: host int array."""
     n = A0.shape[0]
-    perm = torch.from_numpy(perm_from_ipiv(ipiv, n)).to(A0.device)
-    U = torch.triu(LU).contiguous()
-    ss = torch.zeros((), dtype=torch.float64, device=A0.device)
-    for r0 in range(0, n, strip):
-        r1 = min(n, r0 + strip)
-        Ls = LU[r0:r1, :r1].contiguous()
-        rows = torch.arange(r0, r1, device=A0.device)[:, None]
-        cols = torch.arange(0, r1, device=A0.device)[None, :]
-        Ls = torch.where(cols < rows, Ls, torch.where(cols == rows, torch.ones_like(Ls), torch.zeros_like(Ls)))
-        R = A0[perm[r0:r1], :] - Ls @ U[:r1, :]
-        ss += (R * R).sum()
-        del Ls, R
-    del U
-    an = torch.linalg.norm(A0.contiguous() if not A0.is_contiguous() else A0)
-    return float(torch.sqrt(ss) / (an * n * EPS))
+    dev = A0.device
+    perm = torch.from_numpy(perm_from_ipiv(ipiv, n)).to(dev)
+    ss = torch.zeros((), dtype=torch.float64, device=dev)
+    an = torch.zeros((), dtype=torch.float64, device=dev)
+    zero = torch.zeros((), dtype=torch.float64, device=dev)
+    one = torch.ones((), dtype=torch.float64, device=dev)
+    for c0 in range(0, n, bs):
+        c1 = min(n, c0 + bs)
+        # U[:c1, c0:c1]: entries with row <= col
+        Uj = torch.where(torch.arange(0, c1, device=dev)[:, None] <= torch.arange(c0, c1, device=dev)[None, :],
+                         LU[:c1, c0:c1], zero).contiguous()
+        for r0 in range(0, n, bs):
+            r1 = min(n, r0 + bs)
+            kk = min(r1, c1)  # L[i, p] = 0 for p > i, U[p, j] = 0 for p > j
+            rr = torch.arange(r0, r1, device=dev)[:, None]
+            pp = torch.arange(0, kk, device=dev)[None, :]
+            Ls = torch.where(pp < rr, LU[r0:r1, :kk], torch.where(pp == rr, one, zero)).contiguous()
+            Ab = A0[:, c0:c1][perm[r0:r1]]
+            R = Ab - Ls @ Uj[:kk]
+            ss += (R * R).sum()
+            an += (Ab * Ab).sum()
+            del Ls, Ab, R
+        del Uj
+    return float(torch.sqrt(ss) / (torch.sqrt(an) * n * EPS))
 
 
-def chol_backward_error_torch(torch, A0, L, strip=4096):
+def chol_backward_error_torch(torch, A0, L, bs=8192):
     """||A - L L^T||_F / (||A||_F n eps) on the lower triangle's symmetric
-    extension (as the oracle defines it), FP64 on the GPU, by row strips."""
+    extension (as the oracle defines it), FP64 on the GPU, in bs x bs blocks
+    of the lower triangle (off-diagonal entries weighted twice)."""
     n = A0.shape[0]
-    ss = torch.zeros((), dtype=torch.float64, device=A0.device)
-    an = torch.zeros((), dtype=torch.float64, device=A0.device)
-    for r0 in range(0, n, strip):
-        r1 = min(n, r0 + strip)
-        rows = torch.arange(r0, r1, device=A0.device)[:, None]
-        cols = torch.arange(0, r1, device=A0.device)[None, :]
-        low = cols <= rows
-        w = torch.where(cols == rows, 1.0, 2.0).to(torch.float64) * low  # symmetric extension weights
-        Ls = torch.where(low, L[r0:r1, :r1], 0.0).contiguous()
-        Lt = torch.tril(L[:r1, :r1]).contiguous()
-        R = torch.where(low, A0[r0:r1, :r1], 0.0) - Ls @ Lt.t()
-        ss += (w * R * R).sum()
-        a = torch.where(low, A0[r0:r1, :r1], 0.0)
-        an += (w * a * a).sum()
-        del Ls, Lt, R, a, w
+    dev = A0.device
+    ss = torch.zeros((), dtype=torch.float64, device=dev)
+    an = torch.zeros((), dtype=torch.float64, device=dev)
+    zero = torch.zeros((), dtype=torch.float64, device=dev)
+    for c0 in range(0, n, bs):
+        c1 = min(n, c0 + bs)
+        cj = torch.arange(c0, c1, device=dev)[:, None]
+        pj = torch.arange(0, c1, device=dev)[None, :]
+        Lj = torch.where(pj <= cj, L[c0:c1, :c1], zero).contiguous()  # rows c0:c1 of lower L
+        for r0 in range(c0, n, bs):
+            r1 = min(n, r0 + bs)
+            ri = torch.arange(r0, r1, device=dev)[:, None]
+            Li = torch.where(pj <= ri, L[r0:r1, :c1], zero).contiguous()
+            cc = torch.arange(c0, c1, device=dev)[None, :]
+            low = cc <= ri
+            w = torch.where(cc == ri, 1.0, 2.0).to(torch.float64) * low
+            Ab = torch.where(low, A0[r0:r1, c0:c1], zero)
+            R = Ab - Li @ Lj.t()
+            ss += (w * R * R).sum()
+            an += (w * Ab * Ab).sum()
+            del Li, Ab, R, w
+        del Lj
     return float(torch.sqrt(ss) / (torch.sqrt(an) * n * EPS))
 
 
