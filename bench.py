@@ -18,7 +18,7 @@ Also reported (``detail``):
   * batched: 4096 LU/Cholesky problems, N log-uniform in [16, 512], one
     graph replay, FP64 and FP32, aggregate TFLOP/s.
 
-``roofline``: the FP64 Schur-complement update GEMM (dgemm_dl_kernel<0, false>,
+``roofline``: the FP64 Schur-complement update GEMM (dgemm_dl_kernel<0, false, 0>,
 the dominant kernel): every launch of it inside the first timed LU step is
 bracketed by HIP events on the stream it runs on (the library's kernel-timing
 hook); achieved = algorithmic flops per launch / average launch duration.
@@ -205,7 +205,7 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
     roofline = {"bound": "mfma", "achieved": None if achieved is None else round(achieved, 3), "peak": FP64_PEAK,
                 "unit": "TFLOP/s", "frac": None if achieved is None else round(achieved / FP64_PEAK, 4),
                 "traffic": traffic_per_launch(n, lu_nb),
-                "kernel": "dgemm_dl_kernel<0, false> (FP64 Schur-complement update C -= A B, direct-to-LDS "
+                "kernel": "dgemm_dl_kernel<0, false, 0> (FP64 Schur-complement update C -= A B, direct-to-LDS "
                           "operands; dgemm_kernel<0,0,false> where its shape conditions fail)",
                 "launches": prof_nn["launches"], "avg_launch_us": round(avg * 1e6, 2),
                 "flops_per_launch": round(fpl, 1),

@@ -243,7 +243,10 @@ inline size_t dl_pad_bytes(int wg_per_cu) {
     return (size_t)(160 * 1024 / w) / 512 * 512 - 32 * 1024;
 }
 
-template <int TB, bool LOWER>
+// TAG only names the launch (0: the Schur-complement updates, 1: the
+// products forming L11^-1 and U12 = L11^-1 A12), so that kernel traces and
+// counter runs report the two apart; the code is the same.
+template <int TB, bool LOWER, int TAG = 0>
 __global__ __launch_bounds__(NT, 5) void dgemm_dl_kernel(int m, int n, int k, double alpha,
                                                          const double *__restrict__ A, int lda,
                                                          const double *__restrict__ B, int ldb, double beta,
@@ -364,8 +367,14 @@ hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double
         if (nwg <= 0) return hipSuccess;
         if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
         const int slot = cdf::prof_begin(ctx.prof, s, kind, flops);
-        hipLaunchKernelGGL((dgemm_dl_kernel<TB, LOWER>), dim3((unsigned)nwg), dim3(NT), dl_pad_bytes(ctx.wg_per_cu), s,
-                           m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tm64, tn64, stop);
+        if (TB == 0 && !LOWER && ctx.tag == cdf::PROF_U12)
+            hipLaunchKernelGGL((dgemm_dl_kernel<TB, LOWER, 1>), dim3((unsigned)nwg), dim3(NT),
+                               dl_pad_bytes(ctx.wg_per_cu), s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tm64,
+                               tn64, stop);
+        else
+            hipLaunchKernelGGL((dgemm_dl_kernel<TB, LOWER>), dim3((unsigned)nwg), dim3(NT),
+                               dl_pad_bytes(ctx.wg_per_cu), s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tm64,
+                               tn64, stop);
         const hipError_t e = hipGetLastError();
         cdf::prof_end(ctx.prof, s, slot);
         return e;
