@@ -201,14 +201,18 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
     launches = max(prof_nn["launches"], 1)
     avg = prof_nn["total_ms"] * 1e-3 / launches
     fpl = prof_nn["flops"] / launches
+    bpl = prof_nn.get("bytes", 0.0) / launches
     achieved = fpl / avg / 1e12 if avg > 0 else None
+    traffic = traffic_per_launch(n, h.get_param("lu_nb") or 512)
     roofline = {"bound": "mfma", "achieved": None if achieved is None else round(achieved, 3), "peak": FP64_PEAK,
                 "unit": "TFLOP/s", "frac": None if achieved is None else round(achieved / FP64_PEAK, 4),
-                "traffic": traffic_per_launch(n, lu_nb),
+                "traffic": traffic,
                 "kernel": "dgemm_dl_kernel<0, false, 0> (FP64 Schur-complement update C -= A B, direct-to-LDS "
                           "operands; dgemm_kernel<0,0,false> where its shape conditions fail)",
                 "launches": prof_nn["launches"], "avg_launch_us": round(avg * 1e6, 2),
                 "flops_per_launch": round(fpl, 1),
+                "algorithmic_bytes_per_launch": round(bpl, 1),
+                "traffic_over_algorithmic": None if not traffic or not bpl else round(traffic / bpl, 3),
                 "u12_products": {"launches": prof_u12["launches"], "gflop": round(prof_u12["flops"] * 1e-9, 1),
                                  "ms": round(prof_u12["total_ms"], 2),
                                  "note": "L11^-1 and U12 = L11^-1 A12 as matrix products: work beyond the "

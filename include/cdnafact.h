@@ -325,13 +325,15 @@ CDF_API double cdf_io_lower_bound_elems(int kind, double n, double m_elems);
  *   launches number of launches of that kernel (host)
  *   total_ms sum of their event-measured durations in ms (host)
  *   flops    sum of their algorithmic flops 2mnk (m(m+1)k for SYRK) (host)
+ *   bytes    sum of their algorithmic bytes: C read and written once and each
+ *            operand read once, 8(2mn + mk + kn) (8(m(m+1) + 2mk) for SYRK) (host)
  * cdf_profile_end synchronizes the recorded events and stops recording;
  * the records stay readable (one call per kernel kind) until the next
  * cdf_profile_begin.  Without a cdf_profile_begin it returns zeros.
  */
 CDF_API cdf_status_t cdf_profile_begin(cdf_handle_t h);
 CDF_API cdf_status_t cdf_profile_end(cdf_handle_t h, int kernel, long long *launches, double *total_ms,
-                                     double *flops);
+                                     double *flops, double *bytes);
 
 #ifdef __cplusplus
 }

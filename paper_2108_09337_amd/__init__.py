@@ -84,7 +84,7 @@ def lib() -> ctypes.CDLL:
         "cdf_vbatch_plan_destroy": (_i, [_vp]),
         "cdf_io_lower_bound_elems": (ctypes.c_double, [_i, ctypes.c_double, ctypes.c_double]),
         "cdf_profile_begin": (_i, [_vp]),
-        "cdf_profile_end": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_longlong), _c_double_p, _c_double_p]),
+        "cdf_profile_end": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_longlong), _c_double_p, _c_double_p, _c_double_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -257,14 +257,15 @@ def profile_begin(h: Handle | None = None) -> None:
 
 
 def profile_end(kernel: str = "nn", h: Handle | None = None) -> dict:
-    """Stop timing; launches, summed event time (ms) and algorithmic flops of one GEMM kernel."""
+    """Stop timing; launches, summed event time (ms), algorithmic flops and bytes of one GEMM kernel."""
     h = h or handle()
     n = ctypes.c_longlong(0)
     ms = ctypes.c_double(0.0)
     fl = ctypes.c_double(0.0)
+    by = ctypes.c_double(0.0)
     _check("cdf_profile_end", lib().cdf_profile_end(h.ptr, GEMM_KERNELS[kernel], ctypes.byref(n), ctypes.byref(ms),
-                                                    ctypes.byref(fl)), h.ptr)
-    return {"launches": int(n.value), "total_ms": float(ms.value), "flops": float(fl.value)}
+                                                    ctypes.byref(fl), ctypes.byref(by)), h.ptr)
+    return {"launches": int(n.value), "total_ms": float(ms.value), "flops": float(fl.value), "bytes": float(by.value)}
 
 
 # ---------------------------------------------------------------- mixed precision

@@ -454,14 +454,16 @@ cdf_status_t cdf_profile_begin(cdf_handle_t h) {
     return CDF_OK;
 }
 
-cdf_status_t cdf_profile_end(cdf_handle_t h, int kernel, long long *launches, double *total_ms, double *flops) {
+cdf_status_t cdf_profile_end(cdf_handle_t h, int kernel, long long *launches, double *total_ms, double *flops,
+                             double *bytes) {
     if (!h) return CDF_ERR_INVALID_ARG;
     h->bad_arg = 0;
     if (kernel < 0 || kernel >= cdf::PROF_KINDS) { h->bad_arg = 2; return CDF_ERR_INVALID_ARG; }
     if (!launches) { h->bad_arg = 3; return CDF_ERR_INVALID_ARG; }
     if (!total_ms) { h->bad_arg = 4; return CDF_ERR_INVALID_ARG; }
     if (!flops) { h->bad_arg = 5; return CDF_ERR_INVALID_ARG; }
-    CDF_HIP_TRY(cdf::prof_collect(h->prof, kernel, launches, total_ms, flops));
+    if (!bytes) { h->bad_arg = 6; return CDF_ERR_INVALID_ARG; }
+    CDF_HIP_TRY(cdf::prof_collect(h->prof, kernel, launches, total_ms, flops, bytes));
     return CDF_OK;
 }
 

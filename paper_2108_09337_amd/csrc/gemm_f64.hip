@@ -19,9 +19,6 @@
 // 8 tile-rows so the A and B panels an XCD touches stay in its L2.
 #include "internal.h"
 
-#include <mutex>
-#include <new>
-#include <vector>
 
 namespace {
 
@@ -360,13 +357,15 @@ hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double
     constexpr int BM = Shape<TB>::B, BN = Shape<TB>::B;
     const int kind = ctx.tag >= 0 ? ctx.tag : (LOWER ? cdf::PROF_SYRK : TA * 2 + TB);
     const double flops = LOWER ? (double)m * (m + 1) * k : 2.0 * m * n * k;
+    // algorithmic bytes: C read and written once, each operand read once
+    const double bytes = 8.0 * (LOWER ? (double)m * (m + 1) + 2.0 * m * k : 2.0 * m * n + (double)m * k + (double)k * n);
     if (TA == 0 && dl_ok(TB, m, n, k, A, lda, B, ldb)) {
         // direct-to-LDS kernel, 64 x 64 tiles
         const int tm64 = (m + 63) / 64, tn64 = (n + 63) / 64;
         const long long nwg = LOWER ? (long long)tm64 * (tm64 + 1) / 2 : (long long)tm64 * tn64;
         if (nwg <= 0) return hipSuccess;
         if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
-        const int slot = cdf::prof_begin(ctx.prof, s, kind, flops);
+        const int slot = cdf::prof_begin(ctx.prof, s, kind, flops, bytes);
         if (TB == 0 && !LOWER && ctx.tag == cdf::PROF_U12)
             hipLaunchKernelGGL((dgemm_dl_kernel<TB, LOWER, 1>), dim3((unsigned)nwg), dim3(NT),
                                dl_pad_bytes(ctx.wg_per_cu), s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tm64,
@@ -384,7 +383,7 @@ hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double
     long long nwg = LOWER ? (long long)tiles_m * (tiles_m + 1) / 2 : (long long)tiles_m * tiles_n;
     if (nwg <= 0) return hipSuccess;
     if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
-    const int slot = cdf::prof_begin(ctx.prof, s, kind, flops);
+    const int slot = cdf::prof_begin(ctx.prof, s, kind, flops, bytes);
     hipLaunchKernelGGL((dgemm_kernel<TA, TB, LOWER>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k,
                        alpha, A, lda, B, ldb, beta, C, ldc, tiles_m, tiles_n, stop);
     const hipError_t e = hipGetLastError();
@@ -395,89 +394,6 @@ hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double
 }  // namespace
 
 namespace cdf {
-
-struct ProfRec {
-    hipEvent_t a, b;
-    int kind;
-    double flops;
-};
-struct ProfState {
-    std::mutex mu;
-    bool on = false;
-    std::vector<ProfRec> recs;  // recs[0, used) are live; events reused across sessions
-    size_t used = 0;
-};
-
-int prof_begin(ProfState *st, hipStream_t s, int kind, double flops) {
-    if (!st) return -1;
-    std::lock_guard<std::mutex> lk(st->mu);
-    if (!st->on) return -1;
-    if (st->used == st->recs.size()) {
-        ProfRec r{nullptr, nullptr, 0, 0.0};
-        if (hipEventCreate(&r.a) != hipSuccess) return -1;
-        if (hipEventCreate(&r.b) != hipSuccess) { (void)hipEventDestroy(r.a); return -1; }
-        st->recs.push_back(r);
-    }
-    ProfRec &r = st->recs[st->used];
-    r.kind = kind;
-    r.flops = flops;
-    if (hipEventRecord(r.a, s) != hipSuccess) return -1;
-    return (int)st->used++;
-}
-
-void prof_end(ProfState *st, hipStream_t s, int slot) {
-    if (!st || slot < 0) return;
-    std::lock_guard<std::mutex> lk(st->mu);
-    if ((size_t)slot < st->used) (void)hipEventRecord(st->recs[slot].b, s);
-}
-
-hipError_t prof_enable(ProfState **pst) {
-    if (!*pst) {
-        *pst = new (std::nothrow) ProfState();
-        if (!*pst) return hipErrorOutOfMemory;
-    }
-    std::lock_guard<std::mutex> lk((*pst)->mu);
-    (*pst)->on = true;
-    (*pst)->used = 0;
-    return hipSuccess;
-}
-
-hipError_t prof_collect(ProfState *st, int kind, long long *launches, double *total_ms, double *flops) {
-    *launches = 0;
-    *total_ms = 0.0;
-    *flops = 0.0;
-    if (!st) return hipSuccess;
-    std::lock_guard<std::mutex> lk(st->mu);
-    long long cnt = 0;
-    double ms = 0.0, fl = 0.0;
-    hipError_t err = hipSuccess;
-    for (size_t i = 0; i < st->used; ++i) {
-        const ProfRec &r = st->recs[i];
-        if (r.kind != kind) continue;
-        float t = 0.0f;
-        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
-            err = hipErrorUnknown;
-            continue;
-        }
-        ++cnt;
-        ms += t;
-        fl += r.flops;
-    }
-    st->on = false;  // records stay readable until the next prof_enable
-    *launches = cnt;
-    *total_ms = ms;
-    *flops = fl;
-    return err;
-}
-
-void prof_free(ProfState *st) {
-    if (!st) return;
-    for (auto &r : st->recs) {
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
-    }
-    delete st;
-}
 
 GemmCtx gemm_ctx(cdf_handle_t h, int tag) {
     GemmCtx c;

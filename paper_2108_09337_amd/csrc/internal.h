@@ -59,10 +59,11 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Kernel-timing records of a handle (cdf_profile_begin / _end) and the kinds
 // they are filed under.
 enum ProfKind { PROF_NN = 0, PROF_NT = 1, PROF_TN = 2, PROF_TT = 3, PROF_SYRK = 4, PROF_U12 = 5, PROF_KINDS = 6 };
-int prof_begin(ProfState *st, hipStream_t s, int kind, double flops);  // -1 when not timing
+int prof_begin(ProfState *st, hipStream_t s, int kind, double flops, double bytes);  // -1 when not timing
 void prof_end(ProfState *st, hipStream_t s, int slot);
 hipError_t prof_enable(ProfState **st);  // creates the records on first use
-hipError_t prof_collect(ProfState *st, int kind, long long *launches, double *total_ms, double *flops);
+hipError_t prof_collect(ProfState *st, int kind, long long *launches, double *total_ms, double *flops,
+                        double *bytes);
 void prof_free(ProfState *st);
 
 // Per-call options of the FP64 GEMM: update-GEMM workgroups resident per CU
