@@ -143,6 +143,29 @@ CDF_API int cdf_get_param(cdf_handle_t h, cdf_param_t p);
 CDF_API cdf_status_t cdf_dgetrf(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info);
 
 /*
+ * For callers that cannot allocate device memory (work under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the LU of
+ * cdf_dgetrf, same arguments, outputs and info, allocating nothing.
+ *   - Its scratch (the panel leaf's exchange area, the panels' pivots and
+ *     interchange pairs; 576 KB) is a static device array, one copy per GPU,
+ *     held until the process ends; its address is looked up when a handle is
+ *     created on that GPU.  The handle's workspace is not used or grown.
+ *   - n <= CDF_NOALLOC_MAX_N (the exchange area's 256 workgroup slots of
+ *     512 rows); larger n returns CDF_ERR_INVALID_ARG (argument 2).
+ *   - U12 = L11^-1 A12 is solved in place (as CDF_PARAM_LU_U12 = 1), and
+ *     everything runs on the handle's stream (no look-ahead streams, no
+ *     events), so the factors equal those of cdf_dgetrf with
+ *     CDF_PARAM_LU_U12 = 1 bit for bit.
+ *   - Every call on a GPU uses that GPU's one scratch array and leaves its
+ *     last contents there (each call zeroes what must start at zero): calls
+ *     that overlap in time on one GPU, from any handle or stream, race and
+ *     must not be issued.
+ *   - CDF_ERR_HIP if the scratch could not be located on this device.
+ */
+#define CDF_NOALLOC_MAX_N 131072
+CDF_API cdf_status_t cdf_dgetrf_noalloc(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info);
+
+/*
  * Solve A X = B with the factors of cdf_dgetrf: B <- P B, then the unit
  * lower and upper triangular solves.  trans must be 'N'.
  *   A, ipiv  device, as left by cdf_dgetrf; B device n x nrhs, ldb >= n;

@@ -68,6 +68,7 @@ def lib() -> ctypes.CDLL:
         "cdf_set_param": (_i, [_vp, _i, _i]),
         "cdf_get_param": (_i, [_vp, _i]),
         "cdf_dgetrf": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
+        "cdf_dgetrf_noalloc": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
         "cdf_dgetrs": (_i, [_vp, ctypes.c_char, _i, _i, _vp, _i, _vp, _vp, _i]),
         "cdf_dpotrf": (_i, [_vp, ctypes.c_char, _i, _vp, _i, _vp]),
         "cdf_dpotrs": (_i, [_vp, ctypes.c_char, _i, _i, _vp, _i, _vp, _i]),
@@ -209,6 +210,14 @@ def dgetrf(A: torch.Tensor, ipiv: torch.Tensor, info: torch.Tensor, h: Handle | 
     h = h or handle(A.device)
     n = A.shape[0]
     _check("cdf_dgetrf", lib().cdf_dgetrf(h.bind_stream(), n, _p(A), _ld(A), _p(ipiv), _p(info)), h.ptr)
+
+
+def dgetrf_noalloc(A: torch.Tensor, ipiv: torch.Tensor, info: torch.Tensor, h: Handle | None = None) -> None:
+    """In-place LU that allocates nothing (see cdf_dgetrf_noalloc)."""
+    h = h or handle(A.device)
+    n = A.shape[0]
+    _check("cdf_dgetrf_noalloc", lib().cdf_dgetrf_noalloc(h.bind_stream(), n, _p(A), _ld(A), _p(ipiv), _p(info)),
+           h.ptr)
 
 
 def dgetrs(A: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor, trans: str = "N", h: Handle | None = None) -> None:

@@ -76,15 +76,15 @@ namespace cdf {
 // interchanges to every other column of the region inside the leaf kernel,
 // so the region stays consistently permuted.  Pivots are written relative to the region's row 0;
 // info values are offset by info_off.
-hipError_t lu_panel(cdf_handle_t h, hipStream_t s, int m, int ncols, double *A, int lda, int *ipiv, int *info,
-                    int c0, int w, int info_off) {
+hipError_t lu_panel(cdf_handle_t h, const LeafArea &la, hipStream_t s, int m, int ncols, double *A, int lda,
+                    int *ipiv, int *info, int c0, int w, int info_off) {
     if (w <= 32) {
-        return lu_leaf(h, s, m - c0, w, A + c0 + (size_t)c0 * lda, lda, ipiv + c0, c0, info, info_off + c0,
+        return lu_leaf(h, la, s, m - c0, w, A + c0 + (size_t)c0 * lda, lda, ipiv + c0, c0, info, info_off + c0,
                        h->params[CDF_PARAM_LU_LEAF_ROWS], A, m, ncols, c0);
     }
     const int n1 = ((w / 2 + 31) / 32) * 32;
     const int n2 = w - n1;
-    CDF_HIP_RET(lu_panel(h, s, m, ncols, A, lda, ipiv, info, c0, n1, info_off));
+    CDF_HIP_RET(lu_panel(h, la, s, m, ncols, A, lda, ipiv, info, c0, n1, info_off));
     double *a11 = A + c0 + (size_t)c0 * lda;
     double *a12 = A + c0 + (size_t)(c0 + n1) * lda;
     double *a21 = A + (c0 + n1) + (size_t)c0 * lda;
@@ -92,7 +92,7 @@ hipError_t lu_panel(cdf_handle_t h, hipStream_t s, int m, int ncols, double *A, 
     const GemmCtx gc = gemm_ctx(h);
     CDF_HIP_RET(trsm_blocked(s, TRSM_LLNU, n1, n2, a11, lda, a12, lda, 64, &gc));
     CDF_HIP_RET(dgemm(s, 0, 0, m - c0 - n1, n2, n1, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false, nullptr, &gc));
-    return lu_panel(h, s, m, ncols, A, lda, ipiv, info, c0 + n1, n2, info_off);
+    return lu_panel(h, la, s, m, ncols, A, lda, ipiv, info, c0 + n1, n2, info_off);
 }
 
 // Blocked right-looking lower Cholesky of the n x n matrix A: potrf of each
@@ -130,6 +130,7 @@ hipError_t potrf_blocked(cdf_handle_t h, int n, double *A, int lda, int *info, i
 namespace {
 
 struct LuWs {
+    cdf::LeafArea leaf;  // the leaf's exchange area
     int *ipt;    // region-relative pivots of the current panel
     int *pairs;  // its interchange pairs (one of the two buffers below)
     int *buf[2];
@@ -174,7 +175,7 @@ hipError_t u12_and_update(cdf_handle_t h, hipStream_t s, int n, double *A, int l
 hipError_t factor_panel(cdf_handle_t h, hipStream_t s, int n, double *A, int lda, int *ipiv, int *info, int k,
                         int kb, LuWs &ws, int nb) {
     double *R = A + k + (size_t)k * lda;
-    CDF_HIP_RET(cdf::lu_panel(h, s, n - k, kb, R, lda, ws.ipt, info, 0, kb, k));
+    CDF_HIP_RET(cdf::lu_panel(h, ws.leaf, s, n - k, kb, R, lda, ws.ipt, info, 0, kb, k));
     CDF_HIP_RET(cdf::offset_pivots(s, ws.ipt, ipiv + k, kb, k));
     CDF_HIP_RET(cdf::build_pairs(s, ws.ipt, 0, kb, n - k, ws.pairs));
     // the inverse is needed only while columns remain right of the panel
@@ -192,17 +193,28 @@ hipError_t factor_panel(cdf_handle_t h, hipStream_t s, int n, double *A, int lda
 // trailing columns, only the next panel's are swapped on the handle's stream;
 // the rest are swapped on the third stream while the next panel's columns are
 // updated, and the handle's stream waits for them before updating the rest.
-hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ipt, int *pairs,
-                      double *W, double *Li) {
-    hipStream_t s0 = h->stream;
-    CDF_HIP_RET(cdf::ensure_aux(h));
-    hipStream_t s1 = h->aux, s2 = h->aux2;
+// With one_stream, the same schedule is issued in the same order on the
+// handle's stream alone (no second or third stream, no events).
+hipError_t getrf_impl(cdf_handle_t h, const cdf::LeafArea &la, bool one_stream, int n, double *A, int lda,
+                      int *ipiv, int *info, int *ipt, int *pairs, double *W, double *Li) {
+    hipStream_t s0 = h->stream, s1 = s0, s2 = s0;
+    if (!one_stream) {
+        CDF_HIP_RET(cdf::ensure_aux(h));
+        s1 = h->aux;
+        s2 = h->aux2;
+    }
+    // event record / wait between two of the streams (nothing on one stream,
+    // where submission order already orders the work)
+    auto rec = [&](hipEvent_t e, hipStream_t s) { return one_stream ? hipSuccess : hipEventRecord(e, s); };
+    auto wait = [&](hipStream_t s, hipEvent_t e) { return one_stream ? hipSuccess : hipStreamWaitEvent(s, e, 0); };
     hipEvent_t *left_done = h->ev + 3;  // per pairs buffer
     hipEvent_t rest_swapped = h->ev[5];
     CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
-    CDF_HIP_RET(cdf::leaf_reset_error(h, s0));
+    CDF_HIP_RET(cdf::leaf_reset_error(la, s0));
+    h->last_err = cdf::leaf_error_word(la);
     const int nb = lu_nb(h, n);
     LuWs ws;
+    ws.leaf = la;
     ws.ipt = ipt;
     ws.buf[0] = pairs;
     ws.buf[1] = pairs + kPairsInts;
@@ -213,8 +225,8 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
     ws.good[0] = Li ? reinterpret_cast<int *>(Li + 2 * (size_t)kMaxLuNb * kMaxLuNb) : nullptr;
     ws.good[1] = ws.good[0] ? ws.good[0] + 1 : nullptr;
     // the third stream starts after everything already queued on the handle's
-    CDF_HIP_RET(hipEventRecord(h->ev[2], s0));
-    CDF_HIP_RET(hipStreamWaitEvent(s2, h->ev[2], 0));
+    CDF_HIP_RET(rec(h->ev[2], s0));
+    CDF_HIP_RET(wait(s2, h->ev[2]));
     const int kb0 = nb < n ? nb : n;
     CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, 0, kb0, ws, nb));
     CDF_HIP_RET(cdf::apply_pairs(s0, kb0, n, A, lda, ws.pairs));
@@ -231,35 +243,35 @@ hipError_t getrf_impl(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int 
         // next panel's columns first
         CDF_HIP_RET(u12_and_update(h, s0, n, A, lda, k, kb, k1, kb1, ws, li, good));
         if (rest > kb1) {
-            CDF_HIP_RET(hipEventRecord(h->ev[0], s0));
-            CDF_HIP_RET(hipStreamWaitEvent(s1, h->ev[0], 0));
-            CDF_HIP_RET(hipStreamWaitEvent(s1, left_done[b], 0));
+            CDF_HIP_RET(rec(h->ev[0], s0));
+            CDF_HIP_RET(wait(s1, h->ev[0]));
+            CDF_HIP_RET(wait(s1, left_done[b]));
             CDF_HIP_RET(factor_panel(h, s1, n, A, lda, ipiv, info, k1, kb1, ws, nb));
-            CDF_HIP_RET(hipEventRecord(h->ev[1], s1));
+            CDF_HIP_RET(rec(h->ev[1], s1));
             const int c2 = k1 + kb1;
-            CDF_HIP_RET(hipStreamWaitEvent(s0, rest_swapped, 0));
+            CDF_HIP_RET(wait(s0, rest_swapped));
             CDF_HIP_RET(u12_and_update(h, s0, n, A, lda, k, kb, c2, n - c2, ws, li, good));
-            CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[1], 0));
+            CDF_HIP_RET(wait(s0, h->ev[1]));
         } else {
-            CDF_HIP_RET(hipStreamWaitEvent(s0, left_done[b], 0));
+            CDF_HIP_RET(wait(s0, left_done[b]));
             CDF_HIP_RET(factor_panel(h, s0, n, A, lda, ipiv, info, k1, kb1, ws, nb));
         }
         // panel k1's interchanges: columns [0, k1) (their last reader, this
         // step's update, is done) and those right of the panel after next on
         // the third stream; the next panel's columns here
         const int c2 = k1 + kb1, kb2 = nb < n - c2 ? nb : n - c2, c3 = c2 + (kb2 > 0 ? kb2 : 0);
-        CDF_HIP_RET(hipEventRecord(h->ev[2], s0));
-        CDF_HIP_RET(hipStreamWaitEvent(s2, h->ev[2], 0));
+        CDF_HIP_RET(rec(h->ev[2], s0));
+        CDF_HIP_RET(wait(s2, h->ev[2]));
         if (c3 < n) {
             CDF_HIP_RET(cdf::apply_pairs(s2, c3, n, A + k1, lda, ws.pairs));
-            CDF_HIP_RET(hipEventRecord(rest_swapped, s2));
+            CDF_HIP_RET(rec(rest_swapped, s2));
         }
         CDF_HIP_RET(cdf::apply_pairs(s2, 0, k1, A + k1, lda, ws.pairs));
-        CDF_HIP_RET(hipEventRecord(left_done[b], s2));
+        CDF_HIP_RET(rec(left_done[b], s2));
         CDF_HIP_RET(cdf::apply_pairs(s0, c2, c3 < n ? c3 : n, A + k1, lda, ws.pairs));
     }
-    CDF_HIP_RET(hipEventRecord(h->ev[2], s2));
-    CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[2], 0));
+    CDF_HIP_RET(rec(h->ev[2], s2));
+    CDF_HIP_RET(wait(s0, h->ev[2]));
     return hipSuccess;
 }
 
@@ -340,8 +352,13 @@ size_t getrf_w_doubles(int n) { return (size_t)kMaxLuNb * n + 2 * (size_t)kMaxLu
 hipError_t getrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ws_ints,
                       double *lu_w) {
     const bool inv = lu_w != nullptr && h->params[CDF_PARAM_LU_U12] == 0;
-    return getrf_impl(h, n, A, lda, ipiv, info, ws_ints, ws_ints + kMaxLuNb, inv ? lu_w : nullptr,
-                      inv ? lu_w + (size_t)kMaxLuNb * n : nullptr);
+    return getrf_impl(h, cdf::handle_leaf_area(h), false, n, A, lda, ipiv, info, ws_ints, ws_ints + kMaxLuNb,
+                      inv ? lu_w : nullptr, inv ? lu_w + (size_t)kMaxLuNb * n : nullptr);
+}
+
+hipError_t getrf_inplace_one_stream(cdf_handle_t h, const LeafArea &la, int n, double *A, int lda, int *ipiv,
+                                    int *info, int *ws_ints) {
+    return getrf_impl(h, la, true, n, A, lda, ipiv, info, ws_ints, ws_ints + kMaxLuNb, nullptr, nullptr);
 }
 
 hipError_t potrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *info) {
@@ -392,6 +409,7 @@ cdf_status_t ws_reserve(cdf_handle_t h, size_t bytes) {
         (void)hipFree(h->ws);
         h->ws = nullptr;
         h->ws_bytes = 0;
+        h->last_err = nullptr;
     }
     void *p = nullptr;
     if (hipMalloc(&p, want) != hipSuccess) {
@@ -419,6 +437,9 @@ cdf_status_t cdf_create(cdf_handle_t *h) {
         p->num_cus = cus;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) == hipSuccess && khz > 0)
         p->wall_khz = khz;
+    // the allocation-free LU's scratch address on this device (a failure
+    // only disables that entry point, which then returns CDF_ERR_HIP)
+    (void)cdf::noalloc_setup(p->device);
     *h = p;
     return CDF_OK;
 }
@@ -442,9 +463,9 @@ cdf_status_t cdf_device_status(cdf_handle_t h) {
     CDF_HIP_TRY(hipStreamSynchronize(h->stream));
     if (h->aux) CDF_HIP_TRY(hipStreamSynchronize(h->aux));
     if (h->aux2) CDF_HIP_TRY(hipStreamSynchronize(h->aux2));
-    if (!h->ws) return CDF_OK;
+    if (!h->last_err) return CDF_OK;
     int e = 0;
-    CDF_HIP_TRY(hipMemcpy(&e, cdf::leaf_error_word(h), sizeof(int), hipMemcpyDeviceToHost));
+    CDF_HIP_TRY(hipMemcpy(&e, h->last_err, sizeof(int), hipMemcpyDeviceToHost));
     return e != 0 ? CDF_ERR_TIMEOUT : CDF_OK;
 }
 
@@ -544,7 +565,7 @@ cdf_status_t cdf_dgetrf(cdf_handle_t h, int n, double *A, int lda, int *ipiv, in
         if (st != CDF_OK) return st;
     }
     char *base = static_cast<char *>(h->ws) + cdf::kLeafWsBytes;
-    CDF_HIP_TRY(getrf_impl(h, n, A, lda, ipiv, info, reinterpret_cast<int *>(base),
+    CDF_HIP_TRY(getrf_impl(h, cdf::handle_leaf_area(h), false, n, A, lda, ipiv, info, reinterpret_cast<int *>(base),
                            reinterpret_cast<int *>(base + kMaxLuNb * sizeof(int)), W, Li));
     return CDF_OK;
 }

@@ -27,6 +27,7 @@ struct cdf_handle_s {
     int params[CDF_PARAM_COUNT] = {};
     int wall_khz = 100000;       // rate of the device's constant wall clock
     int leaf_occ[2] = {0, 0};    // resident leaf workgroups per CU (R = 1, 2); 0 = not yet queried
+    int *last_err = nullptr;     // error word of the most recent LU's leaf exchange (cdf_device_status)
     cdf::ProfState *prof = nullptr;  // kernel-timing records (cdf_profile_begin / _end)
 };
 
@@ -96,6 +97,17 @@ size_t getrf_w_doubles(int n);
 hipError_t getrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *ipiv, int *info, int *ws_ints,
                       double *lu_w = nullptr);
 hipError_t potrf_fp64(cdf_handle_t h, int n, double *A, int lda, int *info);
+// The binary64 LU with U12 solved in place (no inverse, no U12 buffer), its
+// exchange in `la`, on the handle's stream alone (no look-ahead streams, no
+// events): needs only `la` and getrf_ws_ints() ints of device memory.
+struct LeafArea;
+hipError_t getrf_inplace_one_stream(cdf_handle_t h, const LeafArea &la, int n, double *A, int lda, int *ipiv,
+                                    int *info, int *ws_ints);
+
+// Looks up the device address of the allocation-free LU's scratch array on
+// `device` (the current device), once per device; later calls return the
+// first result.  Called at handle creation.
+hipError_t noalloc_setup(int device);
 
 // Creates the handle's second stream (default priority) and its two events.
 hipError_t ensure_aux(cdf_handle_t h);
@@ -108,28 +120,36 @@ constexpr double kInverseBound = 16.0;
 hipError_t unit_lower_inverse(hipStream_t s, int kb, const double *L, int ldl, double *Li, int ldi, int *good,
                               const GemmCtx *ctx = nullptr);
 
+// Device area of the leaf's grid exchange (kLeafWsBytes: tags, tagged rows,
+// and in its last 256 bytes the error word) and the host-side counter of the
+// epochs issued on it (below 64: the area is zeroed before the next leaf).
+struct LeafArea {
+    void *base;
+    unsigned *epoch;
+};
+LeafArea handle_leaf_area(cdf_handle_t h);  // the head of the handle's workspace
 // LU panel leaf: factor the m x n (n <= 32) column block at A with partial
 // pivoting; writes absolute 1-based pivots ipiv[0..n) (row offset `row0`
 // added), first zero pivot into *info (as info_base + j + 1) if *info == 0.
 // The leaf also applies its interchanges to the other columns [0, c0) and
 // [c0 + n, region_cols) of the region (region_rows rows) it belongs to; A is
-// region + c0 + c0 * lda.
-hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, int lda, int *ipiv,
-                   int row0, int *info, int info_base, int rows_per_thread, double *region, int region_rows,
-                   int region_cols, int c0);
-// The leaf's device error word (set when a wait of its exchange ran out of
+// region + c0 + c0 * lda.  Its grid exchange uses `la`.
+hipError_t lu_leaf(cdf_handle_t h, const LeafArea &la, hipStream_t stream, int m, int n, double *A, int lda,
+                   int *ipiv, int row0, int *info, int info_base, int rows_per_thread, double *region,
+                   int region_rows, int region_cols, int c0);
+// The area's device error word (set when a wait of the exchange ran out of
 // budget) and its reset, ordered on `stream`; every factorization that runs
-// leaves resets it first.  Needs the handle's workspace.
-int *leaf_error_word(cdf_handle_t h);
+// leaves resets it first.
+int *leaf_error_word(const LeafArea &la);
+hipError_t leaf_reset_error(const LeafArea &la, hipStream_t stream);
 // The leaf kernel for two rows per thread (for hipLaunchKernel / occupancy).
 const void *leaf_kernel_r2();
-hipError_t leaf_reset_error(cdf_handle_t h, hipStream_t stream);
 
 // Recursive LU panel of columns [c0, c0+w) of the m x ncols region A (rows
 // [c0, m)) on stream s; interchanges are applied to all other columns of the
 // region; pivots are relative to the region's row 0; info offset by info_off.
-hipError_t lu_panel(cdf_handle_t h, hipStream_t s, int m, int ncols, double *A, int lda, int *ipiv, int *info,
-                    int c0, int w, int info_off);
+hipError_t lu_panel(cdf_handle_t h, const LeafArea &la, hipStream_t s, int m, int ncols, double *A, int lda,
+                    int *ipiv, int *info, int c0, int w, int info_off);
 
 // Panel-wide interchanges: build (dst, src) pairs of ipiv[k1..k2) (<= 256,
 // region-relative, 1-based) once into `pairs` (pairs_ints() ints), then

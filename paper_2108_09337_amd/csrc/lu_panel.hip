@@ -156,17 +156,19 @@ __global__ __launch_bounds__(256) void apply_pairs_kernel(int ncols, T *__restri
 
 namespace cdf {
 
-int *leaf_error_word(cdf_handle_t h) {
-    return reinterpret_cast<int *>(static_cast<char *>(h->ws) + kLeafWsBytes - 256);
+LeafArea handle_leaf_area(cdf_handle_t h) { return LeafArea{h->ws, &h->leaf_epoch}; }
+
+int *leaf_error_word(const LeafArea &la) {
+    return reinterpret_cast<int *>(static_cast<char *>(la.base) + kLeafWsBytes - 256);
 }
 
-hipError_t leaf_reset_error(cdf_handle_t h, hipStream_t stream) {
-    return fill_int(stream, leaf_error_word(h), 1, 0);
+hipError_t leaf_reset_error(const LeafArea &la, hipStream_t stream) {
+    return fill_int(stream, leaf_error_word(la), 1, 0);
 }
 
-hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, int lda, int *ipiv, int row0,
-                   int *info, int info_base, int rows_per_thread, double *region, int region_rows, int region_cols,
-                   int c0) {
+hipError_t lu_leaf(cdf_handle_t h, const LeafArea &la, hipStream_t stream, int m, int n, double *A, int lda,
+                   int *ipiv, int row0, int *info, int info_base, int rows_per_thread, double *region,
+                   int region_rows, int region_cols, int c0) {
     if (m <= 0 || n <= 0) return hipSuccess;
     if (n > LW || n > m) return hipErrorInvalidValue;
     int R = rows_per_thread;
@@ -195,19 +197,20 @@ hipError_t lu_leaf(cdf_handle_t h, hipStream_t stream, int m, int n, double *A, 
     const long long cap = us * 64 + 4096;
     unsigned max_polls = cap > 0x7fffffffLL ? 0x7fffffffu : (unsigned)cap;
     unsigned skew = h->params[CDF_PARAM_TEST_EXCHANGE_FAIL] ? 32u : 0u;
-    int *err = leaf_error_word(h);
+    int *err = leaf_error_word(la);
     // Epochs are unique per launch and column; the exchange area (tags and
     // row words) is zeroed on first use of a workspace and on wrap-around,
     // and epochs below 64 are never issued, so no stale word can carry a
     // current epoch.
-    if (h->leaf_epoch < 64u || h->leaf_epoch > 0xffffff00u) {
-        CDF_HIP_RET(fill_int(stream, static_cast<int *>(h->ws), (int)(kExchBytes / sizeof(int)), 0));
-        h->leaf_epoch = 64u;
+    unsigned &epoch = *la.epoch;
+    if (epoch < 64u || epoch > 0xffffff00u) {
+        CDF_HIP_RET(fill_int(stream, static_cast<int *>(la.base), (int)(kExchBytes / sizeof(int)), 0));
+        epoch = 64u;
     }
-    unsigned e0 = h->leaf_epoch;
-    h->leaf_epoch += 64u;
-    u64 *tags = static_cast<u64 *>(h->ws);
-    u64 *rows = reinterpret_cast<u64 *>(static_cast<char *>(h->ws) + kTagBytes);
+    unsigned e0 = epoch;
+    epoch += 64u;
+    u64 *tags = static_cast<u64 *>(la.base);
+    u64 *rows = reinterpret_cast<u64 *>(static_cast<char *>(la.base) + kTagBytes);
     void *args[] = {&m, &n, &A, &lda, &ipiv, &row0, &info, &info_base, &tags, &rows, &e0, &region, &region_rows,
                     &region_cols, &c0, &err, &budget, &max_polls, &skew};
     const size_t lds = 0;  // the block lives in registers

@@ -579,7 +579,9 @@ hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *i
     hipStream_t s0 = h->stream;
     const cdf::GemmCtx gu = cdf::gemm_ctx(h, cdf::PROF_U12);
     CDF_HIP_RET(cdf::ensure_aux(h));
-    CDF_HIP_RET(cdf::leaf_reset_error(h, s0));
+    const cdf::LeafArea la = cdf::handle_leaf_area(h);
+    CDF_HIP_RET(cdf::leaf_reset_error(la, s0));
+    h->last_err = cdf::leaf_error_word(la);
     hipStream_t s1 = h->aux;
     const int kp = kpad_of(nb);
     const bool split = nb % QT == 0;
@@ -589,7 +591,7 @@ hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *i
     auto panel = [&](hipStream_t s, int k, int kb, double *P, int buf) -> hipError_t {
         const int m = n - k;
         CDF_HIP_RET(cdf::convert_s2d(s, m, kb, W + k + (size_t)k * ldw, ldw, P, m, false));
-        CDF_HIP_RET(cdf::lu_panel(h, s, m, kb, P, m, w.ipt, info, 0, kb, k));
+        CDF_HIP_RET(cdf::lu_panel(h, la, s, m, kb, P, m, w.ipt, info, 0, kb, k));
         if (inv && k + kb < n) CDF_HIP_RET(cdf::unit_lower_inverse(s, kb, P, m, w.Li[buf], nb, w.good + buf, &gu));
         hipLaunchKernelGGL(add_offset_kernel, dim3((kb + 255) / 256), dim3(256), 0, s, w.ipt, ipiv + k, kb, k);
         CDF_HIP_RET(hipGetLastError());
