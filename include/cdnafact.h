@@ -114,7 +114,13 @@ typedef enum {
     CDF_PARAM_TEST_EXCHANGE_FAIL = 9, /* testing only: 1 = the exchange waits for a tag no workgroup
                                        writes, so every wait of a multi-workgroup leaf runs out of its
                                        budget (exercises the timeout path); 0 = normal */
-    CDF_PARAM_COUNT = 10
+    CDF_PARAM_SPD_REFINE = 10,      /* refinement of cdf_dposv_mixed (low-precision formats): 0 = auto
+                                       (classical refinement; after three corrections short of the
+                                       target, or when the factorization breaks down, preconditioned
+                                       CG, see cdf_dposv_mixed), 1 = classical refinement only,
+                                       2 = preconditioned CG from the start */
+    CDF_PARAM_PCG_MAX_ITER = 11,    /* iteration cap of that preconditioned CG (0 = 400) */
+    CDF_PARAM_COUNT = 12
 } cdf_param_t;
 CDF_API cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value);
 CDF_API int cdf_get_param(cdf_handle_t h, cdf_param_t p);
@@ -222,10 +228,38 @@ CDF_API cdf_status_t cdf_dgesv_mixed(cdf_handle_t h, cdf_update_prec_t p, int n,
                              int lda, const double *B, int ldb, double *X, int ldx, int max_iter,
                              int *iters, double *scaled_resid, int *info);
 
-/* As cdf_dgesv_mixed, for symmetric positive definite A, by lower Cholesky. */
+/*
+ * As cdf_dgesv_mixed, for symmetric positive definite A, by lower Cholesky
+ * (only the lower triangle of A is read).  When classical refinement does
+ * not reach the target with the low-precision factor (CDF_PARAM_SPD_REFINE
+ * = 0), the solver falls back to the method of Higham and Pranesh (2021,
+ * "Exploiting lower precision arithmetic in solving symmetric positive
+ * definite linear systems and least squares problems"): binary64
+ * preconditioned conjugate gradients, every column on its own, with the
+ * low-precision Cholesky factor as the preconditioner; if that factorization
+ * broke down (a non-positive pivot), A + sigma diag(A) is factored instead
+ * for sigma = u, 4u, 16u, ... (u = the format's unit roundoff; six shifts at
+ * most).  The stopping test is the same HPL scaled residual <= 16 of the
+ * true residual b - A x with the original A.  max_iter caps the classical
+ * corrections; CDF_PARAM_PCG_MAX_ITER the CG iterations; iters reports
+ * both together and cdf_mixed_report the details.  info is that of the last
+ * factorization run.
+ */
 CDF_API cdf_status_t cdf_dposv_mixed(cdf_handle_t h, cdf_update_prec_t p, int n, int nrhs, const double *A,
                              int lda, const double *B, int ldb, double *X, int ldx, int max_iter,
                              int *iters, double *scaled_resid, int *info);
+
+/* Refinement methods reported by cdf_mixed_report. */
+#define CDF_REFINE_CLASSICAL 1
+#define CDF_REFINE_PCG 2
+/*
+ * What the last cdf_dgesv_mixed / cdf_dposv_mixed on this handle did (host
+ * outputs; any may be NULL): the refinement method that ran last, the
+ * diagonal shift sigma of the factorization used, the number of
+ * factorizations, classical corrections and CG iterations.
+ */
+CDF_API cdf_status_t cdf_mixed_report(cdf_handle_t h, int *method, double *shift, int *factorizations,
+                                      int *corrections, int *pcg_iterations);
 
 /*
  * The factorization step of cdf_dgesv_mixed on its own: W <- binary32(A),

@@ -435,6 +435,87 @@ def iterative_refinement(a: np.ndarray, b: np.ndarray, solve, max_iter: int = 30
 
 
 # --------------------------------------------------------------------------
+# Preconditioned conjugate gradients with a low-precision Cholesky factor
+# (the fallback when classical refinement fails on an SPD system)
+# --------------------------------------------------------------------------
+
+def shift_diagonal(a: np.ndarray, sigma: float) -> np.ndarray:
+    """A + sigma * diag(A) in binary64 (each a_ii * (1 + sigma), one rounding;
+    sigma a power of two, so 1 + sigma is exact)."""
+    out = np.array(a, dtype=np.float64, order="F", copy=True)
+    d = np.diag(out) * (1.0 + sigma)
+    out[np.diag_indices(out.shape[0])] = d
+    return out
+
+
+def pcg(a: np.ndarray, b: np.ndarray, precond, max_iter: int = 400, target: float = 16.0,
+        x0: np.ndarray | None = None, history: bool = False):
+    """Preconditioned conjugate gradients for the SPD system A X = B, every
+    column on its own, binary64 (the method of Hestenes and Stiefel with a
+    preconditioner M^-1 applied by ``precond``).
+
+      x = x0 (default M^-1 b); r = b - A x; z = M^-1 r; p = z; rho = r.z
+      repeat: q = A p; alpha = rho / p.q; x += alpha p; r -= alpha q
+              stop if the HPL scaled residual of b - A x is <= target
+              z = M^-1 r; rho' = r.z; beta = rho' / rho; p = z + beta p
+    A column whose p.q (or rho) is zero takes alpha (or beta) = 0: it has
+    converged exactly.  Returns (x, iterations, residual, converged[, the
+    iterates x_1, x_2, ... when history])."""
+    a = np.asarray(a, dtype=np.float64)
+    b2 = np.asarray(b, dtype=np.float64).reshape(a.shape[0], -1)
+    x = precond(b2.copy()) if x0 is None else np.array(x0, dtype=np.float64).reshape(b2.shape)
+    r = b2 - a @ x
+    hist = []
+    res = hpl_scaled_residual(a, x, b2)
+    if res <= target:
+        return (x.reshape(b.shape), 0, res, True) + ((hist,) if history else ())
+    z = precond(r.copy())
+    p = z.copy()
+    rho = np.sum(r * z, axis=0)
+    for it in range(1, max_iter + 1):
+        q = a @ p
+        pq = np.sum(p * q, axis=0)
+        alpha = np.divide(rho, pq, out=np.zeros_like(rho), where=pq != 0)
+        x = x + alpha * p
+        r = r - alpha * q
+        if history:
+            hist.append(x.reshape(b.shape).copy())
+        res = hpl_scaled_residual(a, x, b2)
+        if res <= target:
+            return (x.reshape(b.shape), it, res, True) + ((hist,) if history else ())
+        z = precond(r.copy())
+        rho_new = np.sum(r * z, axis=0)
+        beta = np.divide(rho_new, rho, out=np.zeros_like(rho), where=rho != 0)
+        rho = rho_new
+        p = z + beta * p
+    return (x.reshape(b.shape), max_iter, res, False) + ((hist,) if history else ())
+
+
+def shift_schedule(fmt: int, attempts: int = 6):
+    """Diagonal shifts tried after a low-precision Cholesky breaks down:
+    sigma_j = u * 4^j (j = 0, 1, ...), u the format's unit roundoff (the shift
+    of a low-precision Cholesky preconditioner scales with u)."""
+    u = {FMT_BF16: 2.0 ** -8, FMT_FP16: 2.0 ** -11, FMT_E4M3: 2.0 ** -4}[fmt]
+    return [u * 4.0 ** j for j in range(attempts)]
+
+
+def spd_solve_shifted_pcg(a: np.ndarray, b: np.ndarray, nb: int, fmt: int, tm: int, max_iter: int = 400,
+                          target: float = 16.0):
+    """The fallback for an SPD system when classical refinement with the
+    low-precision Cholesky fails: factor A + sigma diag(A) with the
+    low-precision update (mixed_potrf) for sigma = 0, then the shifts of
+    shift_schedule until one factorization completes, and solve A X = B by
+    pcg() with that factor as the preconditioner.  Returns (x, sigma,
+    factorizations, iterations, residual, converged)."""
+    for f, sigma in enumerate([0.0] + shift_schedule(fmt)):
+        w, info = mixed_potrf(shift_diagonal(a, sigma) if sigma else a, nb, fmt, tm)
+        if info == 0:
+            x, it, res, ok = pcg(a, b, lambda r: solve_with_chol32(w, r), max_iter, target)
+            return x, sigma, f + 1, it, res, ok
+    return None, None, f + 1, 0, float("inf"), False
+
+
+# --------------------------------------------------------------------------
 # I/O lower bounds (Sec. 6, one processor, in elements)
 # --------------------------------------------------------------------------
 

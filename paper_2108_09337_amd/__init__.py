@@ -28,7 +28,9 @@ CDF_OK, CDF_ERR_INVALID_ARG, CDF_ERR_HIP, CDF_ERR_ALLOC, CDF_ERR_NOT_CONVERGED, 
 CDF_INFO_TIMEOUT = -1000  # device info of an LU whose panel exchange ran out of its wait budget
 UPD = {"fp64": 0, "bf16": 1, "fp16": 2, "fp8e4m3": 3, "e4m3": 3}
 PARAM = {"lu_nb": 0, "chol_nb": 1, "lu_leaf_rows": 2, "mixed_nb": 3, "vbatch_nb": 4, "vbatch_wg_per_cu": 5,
-         "gemm_wg_per_cu": 6, "lu_u12": 7, "leaf_wait_us": 8, "test_exchange_fail": 9}
+         "gemm_wg_per_cu": 6, "lu_u12": 7, "leaf_wait_us": 8, "test_exchange_fail": 9, "spd_refine": 10,
+         "pcg_max_iter": 11}
+REFINE = {0: None, 1: "classical", 2: "pcg"}
 F64, F32 = 0, 1
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
@@ -65,6 +67,7 @@ def lib() -> ctypes.CDLL:
         "cdf_last_bad_arg": (_i, [_vp]),
         "cdf_status_string": (ctypes.c_char_p, [_i]),
         "cdf_device_status": (_i, [_vp]),
+        "cdf_mixed_report": (_i, [_vp, _c_int_p, _c_double_p, _c_int_p, _c_int_p, _c_int_p]),
         "cdf_set_param": (_i, [_vp, _i, _i]),
         "cdf_get_param": (_i, [_vp, _i]),
         "cdf_dgetrf": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
@@ -288,7 +291,13 @@ def _solve_mixed(fn_name, prec, A, B, X, max_iter, info, h):
                                  _ld(X), int(max_iter), ctypes.byref(iters), ctypes.byref(res), _p(info))
     if st not in (CDF_OK, CDF_ERR_NOT_CONVERGED):
         _check(fn_name, st, h.ptr)
-    return {"status": st, "converged": st == CDF_OK, "iters": iters.value, "scaled_resid": res.value}
+    out = {"status": st, "converged": st == CDF_OK, "iters": iters.value, "scaled_resid": res.value}
+    m, f, c, p = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    sh = ctypes.c_double(0.0)
+    lib().cdf_mixed_report(h.ptr, ctypes.byref(m), ctypes.byref(sh), ctypes.byref(f), ctypes.byref(c), ctypes.byref(p))
+    out.update({"method": REFINE.get(m.value), "shift": sh.value, "factorizations": f.value, "corrections": c.value,
+                "pcg_iterations": p.value})
+    return out
 
 
 def dgesv_mixed(prec: str, A, B, X, info, max_iter: int = 30, h: Handle | None = None) -> dict:

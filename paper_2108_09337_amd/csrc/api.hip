@@ -531,7 +531,20 @@ cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value) {
     if (p == CDF_PARAM_GEMM_WG_PER_CU && !(value == 0 || (value >= 3 && value <= 5))) return bad(h, 3);
     if (p == CDF_PARAM_LU_U12 && value > 1) return bad(h, 3);
     if (p == CDF_PARAM_TEST_EXCHANGE_FAIL && value > 1) return bad(h, 3);
+    if (p == CDF_PARAM_SPD_REFINE && value > 2) return bad(h, 3);
     h->params[p] = value;
+    return CDF_OK;
+}
+
+cdf_status_t cdf_mixed_report(cdf_handle_t h, int *method, double *shift, int *factorizations, int *corrections,
+                              int *pcg_iterations) {
+    if (!h) return CDF_ERR_INVALID_ARG;
+    const cdf::MixedReport &r = h->mixed_report;
+    if (method) *method = r.method;
+    if (shift) *shift = r.shift;
+    if (factorizations) *factorizations = r.factorizations;
+    if (corrections) *corrections = r.corrections;
+    if (pcg_iterations) *pcg_iterations = r.pcg_iterations;
     return CDF_OK;
 }
 

@@ -10,6 +10,14 @@
 
 namespace cdf {
 struct ProfState;
+// What the last mixed-precision solve on a handle did (cdf_mixed_report).
+struct MixedReport {
+    int method = 0;          // CDF_REFINE_CLASSICAL or CDF_REFINE_PCG (0: none)
+    double shift = 0.0;      // sigma of the factorization used (A + sigma diag(A))
+    int factorizations = 0;  // low-precision factorizations run
+    int corrections = 0;     // classical corrections applied
+    int pcg_iterations = 0;  // PCG iterations
+};
 }
 
 struct cdf_handle_s {
@@ -29,6 +37,7 @@ struct cdf_handle_s {
     int leaf_occ[2] = {0, 0};    // resident leaf workgroups per CU (R = 1, 2); 0 = not yet queried
     int *last_err = nullptr;     // error word of the most recent LU's leaf exchange (cdf_device_status)
     cdf::ProfState *prof = nullptr;  // kernel-timing records (cdf_profile_begin / _end)
+    cdf::MixedReport mixed_report;    // what the last mixed-precision solve did
 };
 
 namespace cdf {

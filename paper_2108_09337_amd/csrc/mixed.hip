@@ -393,6 +393,88 @@ __global__ __launch_bounds__(256) void residual_gemv_kernel(int n, int nrhs, con
         }
 }
 
+// -------------------------------------------- preconditioned CG (SPD)
+// The fallback of the SPD solver when classical refinement fails: block PCG,
+// every right-hand side its own CG recurrence (Hestenes-Stiefel with the
+// low-precision Cholesky factor as preconditioner), binary64.  The per-column
+// scalars stay on the device; dot products are reduced in a fixed order.
+
+// W(i, i) = binary32(A(i, i) * (1 + sigma)): the diagonal of the shifted
+// matrix A + sigma diag(A) (sigma a power of two, so 1 + sigma is exact).
+__global__ void shift_diag_kernel(int n, const double *__restrict__ a, int lda, float *__restrict__ w, int ldw,
+                                  double sigma) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w[(size_t)i + (size_t)i * ldw] = (float)(a[(size_t)i + (size_t)i * lda] * (1.0 + sigma));
+}
+
+constexpr int kDotBlocks = 64;  // partial sums per column
+constexpr int kMaxShifts = 6;   // shifted factorizations tried after a breakdown
+
+// part[c * kDotBlocks + b] = sum over the rows block b visits of x(i, c) y(i, c)
+__global__ __launch_bounds__(256) void dot_partial_kernel(int n, const double *__restrict__ x, int ldx,
+                                                          const double *__restrict__ y, int ldy,
+                                                          double *__restrict__ part) {
+    __shared__ double red[4];
+    const int c = blockIdx.y, b = blockIdx.x;
+    double v = 0.0;
+    for (int i = b * 256 + threadIdx.x; i < n; i += kDotBlocks * 256)
+        v = fma(x[(size_t)i + (size_t)c * ldx], y[(size_t)i + (size_t)c * ldy], v);
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(size_t)c * kDotBlocks + b] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ void dot_finish_kernel(int nrhs, const double *__restrict__ part, double *__restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nrhs) return;
+    double s = 0.0;
+    for (int b = 0; b < kDotBlocks; ++b) s += part[(size_t)c * kDotBlocks + b];
+    out[c] = s;
+}
+
+// alpha = rho / (p.q) (0 where p.q = 0); x += alpha p; r -= alpha q
+__global__ void pcg_xr_kernel(int n, int nrhs, const double *__restrict__ rho, const double *__restrict__ pq,
+                              const double *__restrict__ p, const double *__restrict__ q, double *__restrict__ x,
+                              int ldx, double *__restrict__ r) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= n || c >= nrhs) return;
+    const double d = pq[c];
+    const double alpha = d != 0.0 ? rho[c] / d : 0.0;
+    const size_t o = (size_t)i + (size_t)c * n;
+    x[(size_t)i + (size_t)c * ldx] += alpha * p[o];
+    r[o] -= alpha * q[o];
+}
+
+// beta = rho_new / rho_old (0 where rho_old = 0); p = z + beta p
+__global__ void pcg_p_kernel(int n, int nrhs, const double *__restrict__ rho_new, const double *__restrict__ rho_old,
+                             const double *__restrict__ z, double *__restrict__ p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= n || c >= nrhs) return;
+    const double d = rho_old[c];
+    const double beta = d != 0.0 ? rho_new[c] / d : 0.0;
+    const size_t o = (size_t)i + (size_t)c * n;
+    p[o] = z[o] + beta * p[o];
+}
+
+// out[3 c + slot] = max |x(i, c)| over i (out zeroed beforehand)
+__global__ __launch_bounds__(256) void col_absmax_kernel(int n, const double *__restrict__ x, int ldx,
+                                                         double *__restrict__ out, int slot) {
+    __shared__ double red[4];
+    const int c = blockIdx.y;
+    double v = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+        v = fmax(v, fabs(x[(size_t)i + (size_t)c * ldx]));
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(reinterpret_cast<unsigned long long *>(out + 3 * c + slot),
+                  (unsigned long long)__double_as_longlong(fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))));
+}
+
 __global__ void zero_d_kernel(double *p, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = 0.0;
@@ -506,6 +588,9 @@ struct MixedWs {
     double *lu_w = nullptr;    // its U12 / L11^-1 area (fp64 mode)
     int *tsync = nullptr;      // flags of the single-launch triangular solves
     double *R = nullptr, *red = nullptr;
+    // SPD fallback (block PCG): z, p, q (n x nrhs each), the per-column
+    // scalars (two rho buffers by parity, p.q) and the dot partial sums
+    double *Z = nullptr, *Pv = nullptr, *Q = nullptr, *scal = nullptr, *part = nullptr;
 };
 
 
@@ -537,6 +622,10 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     const size_t ots = take(cdf::trsv_sync_ints(n) * sizeof(int));
     const size_t oR = take((size_t)n * nrhs * sizeof(double));
     const size_t ored = take(((size_t)n + 4 * (size_t)nrhs + 8) * sizeof(double));
+    const bool pcg = chol && !factor_only;
+    const size_t oZ = pcg ? take(3 * (size_t)n * nrhs * sizeof(double)) : 0;
+    const size_t oscal = pcg ? take(4 * (size_t)nrhs * sizeof(double)) : 0;
+    const size_t opart = pcg ? take((size_t)kDotBlocks * nrhs * sizeof(double)) : 0;
     cdf_status_t st = cdf::ws_reserve(h, off);
     if (st != CDF_OK) return st;
     char *base = static_cast<char *>(h->ws);
@@ -561,6 +650,13 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     w.tsync = reinterpret_cast<int *>(base + ots);
     w.R = reinterpret_cast<double *>(base + oR);
     w.red = reinterpret_cast<double *>(base + ored);
+    if (pcg) {
+        w.Z = reinterpret_cast<double *>(base + oZ);
+        w.Pv = w.Z + (size_t)n * nrhs;
+        w.Q = w.Pv + (size_t)n * nrhs;
+        w.scal = reinterpret_cast<double *>(base + oscal);
+        w.part = reinterpret_cast<double *>(base + opart);
+    }
     return CDF_OK;
 }
 
@@ -683,6 +779,11 @@ double hpl_from_norms(const std::vector<double> &v, int nrhs, double anorm, int 
     return worst;
 }
 
+// Unit roundoff of the update format (the first shift of the fallback).
+double unit_roundoff(int fmt) {
+    return fmt == FMT_E4M3 ? std::ldexp(1.0, -4) : (fmt == FMT_FP16 ? std::ldexp(1.0, -11) : std::ldexp(1.0, -8));
+}
+
 cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, const double *A, int lda,
                          const double *B, int ldb, double *X, int ldx, int max_iter, int *iters, double *resid,
                          int *info) {
@@ -691,6 +792,11 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
     MixedWs w;
     cdf_status_t st = mixed_layout(h, n, nrhs, nb, fmt == 0 ? FMT_BF16 : fmt, chol, w, false, fmt == 0 && !chol);
     if (st != CDF_OK) return st;
+    cdf::MixedReport &rep = h->mixed_report;
+    rep = cdf::MixedReport();
+    // refinement mode of the SPD solver: 0 auto, 1 classical only, 2 PCG
+    const int mode = (chol && fmt != 0) ? h->params[CDF_PARAM_SPD_REFINE] : 1;
+    const int pcg_max = h->params[CDF_PARAM_PCG_MAX_ITER] > 0 ? h->params[CDF_PARAM_PCG_MAX_ITER] : 400;
     CDF_HIP_TRY(cdf::fill_int(s, info, 1, 0));
     // binary64 ||A||_inf and the matrix the residual is computed with
     const double *Ares = A;
@@ -709,26 +815,37 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
                        rs, slab);
     hipLaunchKernelGGL(vec_absmax_kernel, dim3(256), dim3(256), 0, s, n, rs, w.red);
     CDF_HIP_TRY(hipGetLastError());
-    // factorization of the working copy
-    if (fmt == 0) {
-        CDF_HIP_TRY(cdf::copy_cols(s, n, n, A, lda, w.Wd, n));
-        if (chol) CDF_HIP_TRY(cdf::potrf_fp64(h, n, w.Wd, n, info));
-        else CDF_HIP_TRY(cdf::getrf_fp64(h, n, w.Wd, n, w.ipiv, info, w.lu_ws, w.lu_w));
-    } else {
-        CDF_HIP_TRY(cdf::convert_d2s(s, n, n, A, lda, w.W, n, chol));
-        if (chol) CDF_HIP_TRY(mixed_potrf(h, fmt, n, w.W, n, w, nb, info));
-        else CDF_HIP_TRY(mixed_getrf(h, fmt, n, w.W, n, w.ipiv, w, nb, info));
-        CDF_HIP_TRY(cdf::convert_s2d(s, n, n, w.W, n, w.Wd, n, chol));
-    }
+    // factorization of the working copy, A + sigma diag(A) for sigma > 0
+    auto factor = [&](double sigma, int *hinfo) -> cdf_status_t {
+        if (fmt == 0) {
+            CDF_HIP_TRY(cdf::copy_cols(s, n, n, A, lda, w.Wd, n));
+            if (chol) CDF_HIP_TRY(cdf::potrf_fp64(h, n, w.Wd, n, info));
+            else CDF_HIP_TRY(cdf::getrf_fp64(h, n, w.Wd, n, w.ipiv, info, w.lu_ws, w.lu_w));
+        } else {
+            CDF_HIP_TRY(cdf::fill_int(s, info, 1, 0));
+            CDF_HIP_TRY(cdf::convert_d2s(s, n, n, A, lda, w.W, n, chol));
+            if (sigma > 0.0) {
+                hipLaunchKernelGGL(shift_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, A, lda, w.W, n, sigma);
+                CDF_HIP_TRY(hipGetLastError());
+            }
+            if (chol) CDF_HIP_TRY(mixed_potrf(h, fmt, n, w.W, n, w, nb, info));
+            else CDF_HIP_TRY(mixed_getrf(h, fmt, n, w.W, n, w.ipiv, w, nb, info));
+            CDF_HIP_TRY(cdf::convert_s2d(s, n, n, w.W, n, w.Wd, n, chol));
+        }
+        ++rep.factorizations;
+        rep.shift = sigma;
+        CDF_HIP_TRY(hipMemcpyAsync(hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
+        CDF_HIP_TRY(hipStreamSynchronize(s));
+        return CDF_OK;
+    };
     int hinfo = 0;
     double anorm = 0.0;
-    CDF_HIP_TRY(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
+    if ((st = factor(0.0, &hinfo)) != CDF_OK) return st;
     CDF_HIP_TRY(hipMemcpyAsync(&anorm, w.red, sizeof(double), hipMemcpyDeviceToHost, s));
     CDF_HIP_TRY(hipStreamSynchronize(s));
     *iters = 0;
     *resid = INFINITY;
     if (hinfo == CDF_INFO_TIMEOUT) return CDF_ERR_TIMEOUT;
-    if (hinfo != 0) return CDF_ERR_NOT_CONVERGED;
     auto tri = [&](cdf::TrsmKind kind, double *Y, int ldy) -> hipError_t {
         return nrhs <= 4 ? cdf::trsv_blocked(s, kind, n, nrhs, w.Wd, n, Y, ldy, w.tsync)
                          : cdf::trsm_blocked(s, kind, n, nrhs, w.Wd, n, Y, ldy);
@@ -742,39 +859,124 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
         CDF_HIP_RET(tri(cdf::TRSM_LLNU, Y, ldy));
         return tri(cdf::TRSM_LUNN, Y, ldy);
     };
-    CDF_HIP_TRY(cdf::copy_cols(s, n, nrhs, B, ldb, X, ldx));
-    CDF_HIP_TRY(solve(X, ldx));
-    std::vector<double> hist, norms(3 * nrhs);
+    std::vector<double> norms(3 * nrhs);
     double *nrm = w.red + 1;
-    for (int it = 0;; ++it) {
-        // r = b - A x (binary64, original A)
-        if (nrhs <= 4) {
-            hipLaunchKernelGGL(residual_gemv_kernel, dim3((n + 63) / 64), dim3(256), 0, s, n, nrhs, Ares, ldres, X, ldx,
-                               B, ldb, w.R, n);
-            CDF_HIP_TRY(hipGetLastError());
-        } else {
-            CDF_HIP_TRY(cdf::copy_cols(s, n, nrhs, B, ldb, w.R, n));
-            CDF_HIP_TRY(cdf::dgemm(s, 0, 0, n, nrhs, n, -1.0, Ares, ldres, X, ldx, 1.0, w.R, n, false));
-        }
-        hipLaunchKernelGGL(zero_d_kernel, dim3(1), dim3(256), 0, s, nrm, 3 * nrhs);
-        for (int c = 0; c < nrhs; ++c) {
-            hipLaunchKernelGGL(vec_absmax_kernel, dim3(64), dim3(256), 0, s, n, w.R + (size_t)c * n, nrm + 3 * c);
-            hipLaunchKernelGGL(vec_absmax_kernel, dim3(64), dim3(256), 0, s, n, X + (size_t)c * ldx, nrm + 3 * c + 1);
-            hipLaunchKernelGGL(vec_absmax_kernel, dim3(64), dim3(256), 0, s, n, B + (size_t)c * ldb, nrm + 3 * c + 2);
-        }
+    // per-column inf-norms of (R, X, B) into nrm and the HPL scaled residual
+    auto scaled = [&](const double *Rm, double *res) -> cdf_status_t {
+        hipLaunchKernelGGL(zero_d_kernel, dim3((3 * nrhs + 255) / 256), dim3(256), 0, s, nrm, 3 * nrhs);
+        const int gb = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
+        hipLaunchKernelGGL(col_absmax_kernel, dim3(gb, nrhs), dim3(256), 0, s, n, Rm, n, nrm, 0);
+        hipLaunchKernelGGL(col_absmax_kernel, dim3(gb, nrhs), dim3(256), 0, s, n, X, ldx, nrm, 1);
+        hipLaunchKernelGGL(col_absmax_kernel, dim3(gb, nrhs), dim3(256), 0, s, n, B, ldb, nrm, 2);
         CDF_HIP_TRY(hipGetLastError());
         CDF_HIP_TRY(hipMemcpyAsync(norms.data(), nrm, 3 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
         CDF_HIP_TRY(hipStreamSynchronize(s));
-        const double res = hpl_from_norms(norms, nrhs, anorm, n);
-        hist.push_back(res);
-        *iters = it;
-        *resid = res;
-        if (res <= 16.0) return CDF_OK;
-        const size_t q = hist.size();
-        if (it >= max_iter || (q > 3 && res > 0.5 * hist[q - 4])) return CDF_ERR_NOT_CONVERGED;
-        CDF_HIP_TRY(solve(w.R, n));
-        CDF_HIP_TRY(cdf::axpy_cols(s, n, nrhs, w.R, n, X, ldx));
+        *res = hpl_from_norms(norms, nrhs, anorm, n);
+        return CDF_OK;
+    };
+    // R = B - A X (binary64, original A)
+    auto residual = [&](double *Rm) -> hipError_t {
+        if (nrhs <= 4) {
+            hipLaunchKernelGGL(residual_gemv_kernel, dim3((n + 63) / 64), dim3(256), 0, s, n, nrhs, Ares, ldres, X, ldx,
+                               B, ldb, Rm, n);
+            return hipGetLastError();
+        }
+        CDF_HIP_RET(cdf::copy_cols(s, n, nrhs, B, ldb, Rm, n));
+        return cdf::dgemm(s, 0, 0, n, nrhs, n, -1.0, Ares, ldres, X, ldx, 1.0, Rm, n, false);
+    };
+    bool need_pcg = false;
+    if (hinfo == 0 && mode != 2) {
+        // classical refinement: x0 = solve(b); r = b - A x; x += solve(r)
+        rep.method = CDF_REFINE_CLASSICAL;
+        CDF_HIP_TRY(cdf::copy_cols(s, n, nrhs, B, ldb, X, ldx));
+        CDF_HIP_TRY(solve(X, ldx));
+        std::vector<double> hist;
+        for (int it = 0;; ++it) {
+            CDF_HIP_TRY(residual(w.R));
+            double res = 0.0;
+            if ((st = scaled(w.R, &res)) != CDF_OK) return st;
+            hist.push_back(res);
+            *iters = it;
+            *resid = res;
+            rep.corrections = it;
+            if (res <= 16.0) return CDF_OK;
+            const size_t q = hist.size();
+            const bool stagnated = q > 3 && res > 0.5 * hist[q - 4];
+            // auto: after three corrections without reaching the target, the
+            // SPD solver continues with PCG on the same factor
+            if (mode == 0 && it >= 3) { need_pcg = true; break; }
+            if (it >= max_iter || stagnated) return CDF_ERR_NOT_CONVERGED;
+            CDF_HIP_TRY(solve(w.R, n));
+            CDF_HIP_TRY(cdf::axpy_cols(s, n, nrhs, w.R, n, X, ldx));
+        }
+    } else if (hinfo != 0 && mode == 1) {
+        return CDF_ERR_NOT_CONVERGED;  // the factorization broke down (info > 0)
     }
+    if (!chol || mode == 1) return CDF_ERR_NOT_CONVERGED;
+    // ---- SPD fallback: shifted low-precision Cholesky as the preconditioner
+    // of binary64 PCG.  On breakdown, A + sigma diag(A) is factored for
+    // sigma = u, 4u, 16u, ... (u: the format's unit roundoff).
+    bool fresh_x = !need_pcg;
+    if (hinfo != 0) {
+        double sigma = unit_roundoff(fmt);
+        for (int a = 0; a < kMaxShifts && hinfo != 0; ++a, sigma *= 4.0)
+            if ((st = factor(sigma, &hinfo)) != CDF_OK) return st;
+        if (hinfo == CDF_INFO_TIMEOUT) return CDF_ERR_TIMEOUT;
+        if (hinfo != 0) return CDF_ERR_NOT_CONVERGED;
+        fresh_x = true;
+    }
+    rep.method = CDF_REFINE_PCG;
+    if (fresh_x) {  // x0 = M^-1 b
+        CDF_HIP_TRY(cdf::copy_cols(s, n, nrhs, B, ldb, X, ldx));
+        CDF_HIP_TRY(solve(X, ldx));
+    }
+    double *rho[2] = {w.scal, w.scal + nrhs};
+    double *pq = w.scal + 2 * nrhs;
+    const dim3 eg((n + 255) / 256, nrhs);
+    auto dot = [&](const double *x, const double *y, double *out) -> hipError_t {
+        hipLaunchKernelGGL(dot_partial_kernel, dim3(kDotBlocks, nrhs), dim3(256), 0, s, n, x, n, y, n, w.part);
+        hipLaunchKernelGGL(dot_finish_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, s, nrhs, w.part, out);
+        return hipGetLastError();
+    };
+    // r = b - A x; stop if converged already; z = M^-1 r; p = z; rho = r.z
+    CDF_HIP_TRY(residual(w.R));
+    double res = 0.0;
+    if ((st = scaled(w.R, &res)) != CDF_OK) return st;
+    *resid = res;
+    if (res <= 16.0) return CDF_OK;
+    CDF_HIP_TRY(cdf::copy_cols(s, n, nrhs, w.R, n, w.Z, n));
+    CDF_HIP_TRY(solve(w.Z, n));
+    CDF_HIP_TRY(cdf::copy_cols(s, n, nrhs, w.Z, n, w.Pv, n));
+    CDF_HIP_TRY(dot(w.R, w.Z, rho[0]));
+    for (int it = 1; it <= pcg_max; ++it) {
+        double *rho_old = rho[(it + 1) & 1], *rho_new = rho[it & 1];
+        // q = A p; alpha = rho / p.q; x += alpha p; r -= alpha q
+        CDF_HIP_TRY(cdf::dgemm(s, 0, 0, n, nrhs, n, 1.0, Ares, ldres, w.Pv, n, 0.0, w.Q, n, false));
+        CDF_HIP_TRY(dot(w.Pv, w.Q, pq));
+        hipLaunchKernelGGL(pcg_xr_kernel, eg, dim3(256), 0, s, n, nrhs, rho_old, pq, w.Pv, w.Q, X, ldx, w.R);
+        CDF_HIP_TRY(hipGetLastError());
+        rep.pcg_iterations = it;
+        *iters = rep.corrections + it;
+        // the recurrence's residual estimates the scaled residual; once it is
+        // below the target, the true residual b - A x decides
+        double est = 0.0;
+        if ((st = scaled(w.R, &est)) != CDF_OK) return st;
+        if (!(est == est)) return CDF_ERR_NOT_CONVERGED;  // NaN
+        *resid = est;
+        if (est <= 16.0) {
+            CDF_HIP_TRY(residual(w.Q));  // Q is free until the next A p
+            if ((st = scaled(w.Q, &res)) != CDF_OK) return st;
+            *resid = res;
+            if (res <= 16.0) return CDF_OK;
+        }
+        // z = M^-1 r; rho' = r.z; p = z + (rho' / rho) p
+        CDF_HIP_TRY(cdf::copy_cols(s, n, nrhs, w.R, n, w.Z, n));
+        CDF_HIP_TRY(solve(w.Z, n));
+        CDF_HIP_TRY(dot(w.R, w.Z, rho_new));
+        hipLaunchKernelGGL(pcg_p_kernel, eg, dim3(256), 0, s, n, nrhs, rho_new, rho_old, w.Z, w.Pv);
+        CDF_HIP_TRY(hipGetLastError());
+    }
+    return CDF_ERR_NOT_CONVERGED;
 }
 
 cdf_status_t check_mixed_args(cdf_handle_t h, cdf_update_prec_t p, int n, int nrhs, const double *A, int lda,

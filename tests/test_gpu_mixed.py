@@ -294,20 +294,62 @@ def test_dposv_mixed_spd(oracle_mod, fmt):
 
 @pytest.mark.parametrize("fmt", FMTS)
 def test_dposv_mixed_kernel_matrix(oracle_mod, fmt):
-    """Exponential-kernel SPD matrix (nrhs = 64): BF16/FP16 refine to the
-    target; E4M3 either refines or reports failure (factor breakdown or no
-    convergence) through info / the status, never a wrong 'converged'."""
+    """Exponential-kernel SPD matrix (nrhs = 64), default (auto) refinement:
+    every format reaches the target, E4M3 through the preconditioned-CG
+    continuation (classical refinement alone needs about 28 corrections)."""
     n = 1024
     x_pts = workloads.kernel_points(n)
     a = workloads.exp_kernel_matrix(x_pts)
     b = workloads.rhs_uniform(n, 64, seed=workloads.SEED_POINTS_RHS)
     x, r = _solve_mixed("chol", fmt, a, b, max_iter=50)
-    if fmt in ("bf16", "fp16"):
-        assert r["converged"], r
-    if r["converged"]:
-        assert oracle_mod.hpl_scaled_residual(a, x, b) <= 16
-    else:
-        assert r["status"] == cdf.CDF_ERR_NOT_CONVERGED
+    assert r["converged"], r
+    assert oracle_mod.hpl_scaled_residual(a, x, b) <= 16
+    l, _ = oracle_mod.dpotrf(a)
+    x_or = oracle_mod.dpotrs(l, b)
+    kappa = np.linalg.cond(a, np.inf)
+    assert np.max(np.abs(x - x_or)) <= 2 * 16 * n * oracle_mod.EPS * kappa * np.max(np.abs(x_or))
+
+
+def _solve_spd_mode(fmt, a, b, mode, max_iter=30):
+    h = cdf.handle()
+    h.set_param("spd_refine", mode)
+    try:
+        return _solve_mixed("chol", fmt, a, b, max_iter=max_iter)
+    finally:
+        h.set_param("spd_refine", 0)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_dposv_mixed_shifted_pcg_density_matched(oracle_mod, fmt):
+    """The full-size kernel workload's density at n = 1024 (length 0.4 for
+    1024 points instead of 0.1 for 65536; kappa ~ 1e4).  E4M3's Cholesky
+    breaks down, so classical refinement alone fails; the fallback (shifted
+    low-precision factor, binary64 PCG) reaches the target.  Shift, number of
+    factorizations and the CG iteration count follow the oracle's fallback
+    (spd_solve_shifted_pcg) on the same matrix; the solution meets the HPL
+    residual and the forward-error bound against the FP64 oracle solution."""
+    n, nrhs = 1024, 8
+    a = workloads.exp_kernel_matrix(workloads.kernel_points(n), length=0.4)
+    b = workloads.rhs_uniform(n, nrhs, seed=workloads.SEED_POINTS_RHS)
+    f = oracle_mod.FMT_NAMES[fmt]
+    if fmt == "e4m3":
+        _, r1 = _solve_spd_mode(fmt, a, b, 1)
+        assert not r1["converged"] and r1["info"] > 0, r1
+    x, r = _solve_spd_mode(fmt, a, b, 2)
+    assert r["converged"] and r["method"] == "pcg", r
+    assert oracle_mod.hpl_scaled_residual(a, x, b) <= 16
+    x_o, sigma_o, nf_o, it_o, res_o, ok_o = oracle_mod.spd_solve_shifted_pcg(a, b, 256, f, 128)
+    assert ok_o
+    assert r["shift"] == sigma_o and r["factorizations"] == nf_o, (r, sigma_o, nf_o)
+    assert abs(r["pcg_iterations"] - it_o) <= max(3, it_o // 10), (r, it_o)
+    l, _ = oracle_mod.dpotrf(a)
+    x_or = oracle_mod.dpotrs(l, b)
+    kappa = np.linalg.cond(a, np.inf)
+    assert np.max(np.abs(x - x_or)) <= 2 * 16 * n * oracle_mod.EPS * kappa * np.max(np.abs(x_or))
+    # the default (auto) mode gets there too
+    x2, r2 = _solve_spd_mode(fmt, a, b, 0)
+    assert r2["converged"], r2
+    assert oracle_mod.hpl_scaled_residual(a, x2, b) <= 16
 
 
 def test_mixed_reports_non_convergence(oracle_mod):
