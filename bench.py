@@ -52,7 +52,7 @@ def parse():
     p.add_argument("--n", type=int, default=65536)
     p.add_argument("--detail-n", type=int, nargs="*", default=[8192, 32768],
                    help="extra sizes measured once each (LU and Cholesky), reported in detail")
-    p.add_argument("--mixed-n", type=int, default=65536)
+    p.add_argument("--mixed-n", type=int, default=65536, help="order of the diagonally dominant mixed LU solve (0 = skip)")
     p.add_argument("--batch", type=int, default=4096)
     p.add_argument("--kernel-n", type=int, default=65536,
                    help="points of the exponential-kernel Cholesky solve (0 = skip)")
@@ -284,6 +284,8 @@ def size_detail(args, torch, cdf, workloads, h, tuned):
 
 def mixed_section(args, torch, cdf, workloads, h, tuned):
     n = args.mixed_n
+    if n <= 0:  # only the exponential-kernel solve
+        return {"kernel_chol": kernel_chol_section(args, torch, cdf, workloads, h, tuned)} if args.kernel_n else {}
     log(f"mixed: generating diagonally dominant n={n}")
     A = workloads.diag_dominant_torch(n)
     b = workloads.rhs_uniform_torch(n)
