@@ -212,6 +212,20 @@ size_t trsv_sync_ints(int n);
 hipError_t trsv_blocked(hipStream_t s, TrsmKind kind, int n, int ncols, const double *T, int ldt, double *B,
                         int ldb, int *sync = nullptr);
 
+// Solves through inverted diagonal blocks (many right-hand sides, one factor
+// applied many times).  inv_lower_blocks: Tinv block q (bs x bs, leading
+// dimension bs, at Tinv + q bs^2; inv_blocks_doubles(n, bs) doubles) =
+// inverse of the diagonal block q of the lower non-unit triangle of T
+// (bs <= 512).  symmetrize_lower: the strict upper triangle of A receives the
+// transpose of its strict lower one.  trsm_inv_lower: Y <- L^-1 X
+// (transposed = false) or Y <- L^-T X (transposed = true, reading L^T from
+// T's upper triangle as symmetrize_lower leaves it); X is overwritten.
+size_t inv_blocks_doubles(int n, int bs);
+hipError_t inv_lower_blocks(hipStream_t s, int n, const double *T, int ldt, int bs, double *Tinv);
+hipError_t symmetrize_lower(hipStream_t s, int n, double *A, int lda);
+hipError_t trsm_inv_lower(hipStream_t s, bool transposed, int n, int nrhs, const double *T, int ldt,
+                          const double *Tinv, int bs, double *X, int ldx, double *Y, int ldy);
+
 // Cholesky of one diagonal block (n <= 128) held in LDS; stops at the first
 // non-positive pivot, writing info_base + j + 1 into *info if *info == 0.
 // *info != 0 on entry makes the kernel return without touching A.

@@ -591,7 +591,12 @@ struct MixedWs {
     // SPD fallback (block PCG): z, p, q (n x nrhs each), the per-column
     // scalars (two rho buffers by parity, p.q) and the dot partial sums
     double *Z = nullptr, *Pv = nullptr, *Q = nullptr, *scal = nullptr, *part = nullptr;
+    // SPD solves with more than four right-hand sides: inverted diagonal
+    // blocks of the factor and an n x nrhs intermediate
+    double *Tinv = nullptr, *Yv = nullptr;
 };
+
+constexpr int kInvBs = 512;  // diagonal block of the inverse-based triangular solves
 
 
 cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool chol, MixedWs &w,
@@ -626,6 +631,9 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
     const size_t oZ = pcg ? take(3 * (size_t)n * nrhs * sizeof(double)) : 0;
     const size_t oscal = pcg ? take(4 * (size_t)nrhs * sizeof(double)) : 0;
     const size_t opart = pcg ? take((size_t)kDotBlocks * nrhs * sizeof(double)) : 0;
+    const bool inv = pcg && nrhs > 4;
+    const size_t oTinv = inv ? take(cdf::inv_blocks_doubles(n, kInvBs) * sizeof(double)) : 0;
+    const size_t oYv = inv ? take((size_t)n * nrhs * sizeof(double)) : 0;
     cdf_status_t st = cdf::ws_reserve(h, off);
     if (st != CDF_OK) return st;
     char *base = static_cast<char *>(h->ws);
@@ -656,6 +664,10 @@ cdf_status_t mixed_layout(cdf_handle_t h, int n, int nrhs, int nb, int fmt, bool
         w.Q = w.Pv + (size_t)n * nrhs;
         w.scal = reinterpret_cast<double *>(base + oscal);
         w.part = reinterpret_cast<double *>(base + opart);
+    }
+    if (inv) {
+        w.Tinv = reinterpret_cast<double *>(base + oTinv);
+        w.Yv = reinterpret_cast<double *>(base + oYv);
     }
     return CDF_OK;
 }
@@ -832,6 +844,10 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
             else CDF_HIP_TRY(mixed_getrf(h, fmt, n, w.W, n, w.ipiv, w, nb, info));
             CDF_HIP_TRY(cdf::convert_s2d(s, n, n, w.W, n, w.Wd, n, chol));
         }
+        if (w.Tinv) {  // L^T beside L, and the inverted diagonal blocks, for the solves
+            CDF_HIP_TRY(cdf::symmetrize_lower(s, n, w.Wd, n));
+            CDF_HIP_TRY(cdf::inv_lower_blocks(s, n, w.Wd, n, kInvBs, w.Tinv));
+        }
         ++rep.factorizations;
         rep.shift = sigma;
         CDF_HIP_TRY(hipMemcpyAsync(hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -851,6 +867,10 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
                          : cdf::trsm_blocked(s, kind, n, nrhs, w.Wd, n, Y, ldy);
     };
     auto solve = [&](double *Y, int ldy) -> hipError_t {
+        if (chol && w.Tinv) {  // Y <- L^-T L^-1 Y through the inverted diagonal blocks
+            CDF_HIP_RET(cdf::trsm_inv_lower(s, false, n, nrhs, w.Wd, n, w.Tinv, kInvBs, Y, ldy, w.Yv, n));
+            return cdf::trsm_inv_lower(s, true, n, nrhs, w.Wd, n, w.Tinv, kInvBs, w.Yv, n, Y, ldy);
+        }
         if (chol) {
             CDF_HIP_RET(tri(cdf::TRSM_LLNN, Y, ldy));
             return tri(cdf::TRSM_LLTN, Y, ldy);
