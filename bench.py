@@ -65,6 +65,8 @@ def parse():
     p.add_argument("--no-mixed", action="store_true")
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--no-tune-cache", action="store_true", help="ignore the autotuner cache")
+    p.add_argument("--gemm-tile", type=int, default=0, choices=[0, 64, 128],
+                   help="tile of the FP64 update GEMM (0 = the library's choice by size)")
     p.add_argument("--lu-leaf-rows", type=int, default=0, choices=[0, 1, 2],
                    help="force the LU panel leaf's rows per thread (counter-collection runs: 2 halves its grid)")
     p.add_argument("--no-kernel-timing", action="store_true",
@@ -468,6 +470,8 @@ def main():
 
     torch.cuda.set_device(0)
     h = cdf.handle()
+    if args.gemm_tile:
+        h.set_param("gemm_tile", args.gemm_tile)
     cache = {} if args.no_tune_cache else tune.load_cache()
 
     def tuned(hh, op, n, dtype="f64"):

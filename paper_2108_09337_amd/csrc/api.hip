@@ -532,6 +532,7 @@ cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value) {
     if (p == CDF_PARAM_LU_U12 && value > 1) return bad(h, 3);
     if (p == CDF_PARAM_TEST_EXCHANGE_FAIL && value > 1) return bad(h, 3);
     if (p == CDF_PARAM_SPD_REFINE && value > 2) return bad(h, 3);
+    if (p == CDF_PARAM_GEMM_TILE && !(value == 0 || value == 64 || value == 128)) return bad(h, 3);
     h->params[p] = value;
     return CDF_OK;
 }

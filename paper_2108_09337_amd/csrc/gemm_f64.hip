@@ -345,6 +345,113 @@ __global__ __launch_bounds__(NT, 5) void dgemm_dl_kernel(int m, int n, int k, do
         }
 }
 
+// C = beta C + alpha A B with 128 x 128 tiles (op(B) = B, the LU's update):
+// the same direct-to-LDS operand path, each wave computing a 64 x 64 block
+// (4 x 4 MFMA blocks, 16 independent accumulators).  Per K step a workgroup
+// brings 32 KB into LDS for 0.5 MFLOP, half the bytes per flop of the 64 x 64
+// tile, whose loads (16 KB per 0.13 MFLOP, four or five workgroups per CU)
+// press on the CU's load path.  Two stages of 34 KB: two workgroups per CU.
+// A instruction i of a wave brings k-column 4 wave + i (128 rows; lane l
+// rows 2l, 2l + 1); the k-columns sit 144 doubles apart in LDS so that the
+// two 16-lane groups of a half-wave reading neighbouring k fall in different
+// banks.  B as in the 64 x 64 kernel: 8 columns x 16 k per instruction, k
+// pairs XOR-swizzled; wave w brings columns 32 w .. 32 w + 31.
+template <int TAG = 0>
+__global__ __launch_bounds__(NT, 2) void dgemm_dl128_kernel(int m, int n, int k, double alpha,
+                                                            const double *__restrict__ A, int lda,
+                                                            const double *__restrict__ B, int ldb, double beta,
+                                                            double *__restrict__ C, int ldc, int tiles_m,
+                                                            int tiles_n, const int *stop) {
+    if (stop != nullptr && *stop != 0) return;
+    constexpr int W = 4, BT = 128, AKS = 144;            // A: k-column stride in LDS (doubles)
+    constexpr int ASZ = BK * AKS, STAGE = ASZ + BT * BK;  // doubles per stage (A then B)
+    __shared__ __attribute__((aligned(16))) double S[2 * STAGE];
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    int tm, tn;
+    grouped_tile(L, tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BT, n0 = tn * BT;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave & 1, wn = wave >> 1, lrow = lane & 15, lk = lane >> 4;
+    const double *asrc = A + min(m0 + 2 * lane, m - 2);
+    const int bq = (lane & 7) ^ (lane >> 3);
+    const double *bsrc = B + 2 * bq;
+    int bcol[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) bcol[u] = min(n0 + 32 * wave + 8 * u + (lane >> 3), n - 1);
+    auto issue = [&](int kt) {
+        double *st = S + (kt & 1) * STAGE;
+        const size_t k0 = (size_t)kt * BK;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kk = 4 * wave + u;
+            __builtin_amdgcn_global_load_lds((glob_void *)(asrc + (k0 + kk) * lda), (lds_void *)(st + kk * AKS), 16, 0,
+                                             0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            __builtin_amdgcn_global_load_lds((glob_void *)(bsrc + k0 + (size_t)bcol[u] * ldb),
+                                             (lds_void *)(st + ASZ + (4 * wave + u) * 128), 16, 0, 0);
+    };
+    v4d acc[W][W];
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+#pragma unroll
+        for (int j = 0; j < W; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int nk = k / BK;
+    if (nk > 0) issue(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): this stage's loads have landed in LDS
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();       // ... for every wave; the other stage is free
+        asm volatile("" ::: "memory");
+        if (kt + 1 < nk) issue(kt + 1);
+        const double *As = S + (kt & 1) * STAGE;
+        const double *Bs = As + ASZ;
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            const int kk = ks * 4 + lk;
+            double af[W], bf[W];
+#pragma unroll
+            for (int i = 0; i < W; ++i) af[i] = As[kk * AKS + wm * 64 + i * 16 + lrow];
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                const int cc = wn * 64 + j * 16 + lrow;
+                bf[j] = Bs[cc * BK + (((kk >> 1) ^ (cc & 7)) << 1) + (kk & 1)];
+            }
+#pragma unroll
+            for (int i = 0; i < W; ++i)
+#pragma unroll
+                for (int j = 0; j < W; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const int col = n0 + wn * 64 + j * 16 + lrow;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 64 + i * 16 + v * 4 + lk;
+                if (row < m && col < n) {
+                    double *p = C + (size_t)row + (size_t)col * ldc;
+                    const double c0 = beta == 0.0 ? 0.0 : beta * *p;
+                    *p = fma(alpha, acc[i][j][v], c0);
+                }
+            }
+        }
+}
+
+// 128 x 128 tiles for the NN update when the handle asks for them
+// (CDF_PARAM_GEMM_TILE = 128), or by default when the product is large enough
+// to give every CU several tiles (and is at least one tile wide each way).
+inline bool use_tile128(const cdf::GemmCtx &ctx, int m, int n) {
+    if (ctx.tile == 64) return false;
+    if (m < 128 || n < 128) return false;
+    if (ctx.tile == 128) return true;
+    return (long long)((m + 127) / 128) * ((n + 127) / 128) >= 1024;
+}
+
 bool dl_ok(int tb, int m, int n, int k, const double *A, int lda, const double *B, int ldb) {
     return k % BK == 0 && m >= 2 && m % 2 == 0 && lda % 2 == 0 && ldb % 2 == 0 && (tb == 0 || (n >= 2 && n % 2 == 0)) &&
            (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
@@ -359,6 +466,22 @@ hipError_t launch(hipStream_t s, int m, int n, int k, double alpha, const double
     const double flops = LOWER ? (double)m * (m + 1) * k : 2.0 * m * n * k;
     // algorithmic bytes: C read and written once, each operand read once
     const double bytes = 8.0 * (LOWER ? (double)m * (m + 1) + 2.0 * m * k : 2.0 * m * n + (double)m * k + (double)k * n);
+    if (TA == 0 && TB == 0 && !LOWER && dl_ok(TB, m, n, k, A, lda, B, ldb) && use_tile128(ctx, m, n)) {
+        // direct-to-LDS kernel, 128 x 128 tiles
+        const int tm = (m + 127) / 128, tn = (n + 127) / 128;
+        const long long nwg = (long long)tm * tn;
+        if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
+        const int slot = cdf::prof_begin(ctx.prof, s, kind, flops, bytes);
+        if (ctx.tag == cdf::PROF_U12)
+            hipLaunchKernelGGL((dgemm_dl128_kernel<1>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k, alpha, A, lda, B,
+                               ldb, beta, C, ldc, tm, tn, stop);
+        else
+            hipLaunchKernelGGL((dgemm_dl128_kernel<0>), dim3((unsigned)nwg), dim3(NT), 0, s, m, n, k, alpha, A, lda, B,
+                               ldb, beta, C, ldc, tm, tn, stop);
+        const hipError_t e = hipGetLastError();
+        cdf::prof_end(ctx.prof, s, slot);
+        return e;
+    }
     if (TA == 0 && dl_ok(TB, m, n, k, A, lda, B, ldb)) {
         // direct-to-LDS kernel, 64 x 64 tiles
         const int tm64 = (m + 63) / 64, tn64 = (n + 63) / 64;
@@ -400,6 +523,7 @@ GemmCtx gemm_ctx(cdf_handle_t h, int tag) {
     c.wg_per_cu = h->params[CDF_PARAM_GEMM_WG_PER_CU];
     c.prof = h->prof;
     c.tag = tag;
+    c.tile = h->params[CDF_PARAM_GEMM_TILE];
     return c;
 }
 

@@ -83,6 +83,7 @@ struct GemmCtx {
     int wg_per_cu = 0;
     ProfState *prof = nullptr;
     int tag = -1;
+    int tile = 0;  // NN update tile: 0 = by size, 64, 128
 };
 GemmCtx gemm_ctx(cdf_handle_t h, int tag = -1);
 

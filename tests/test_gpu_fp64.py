@@ -445,6 +445,45 @@ def test_dgemm_update_fast_path_matches_general_path(m, n, k):
     assert np.max(np.abs(cdf.to_host(C1) - ref)) <= 4 * k * gpu_util.EPS * (np.abs(a) @ np.abs(b) + np.abs(c)).max()
 
 
+@pytest.mark.parametrize("m,n,k", [(1000, 700, 512), (130, 258, 48), (2050, 130, 16), (384, 384, 64)])
+def test_dgemm_tile128_matches_tile64(m, n, k):
+    """The 128 x 128-tile update GEMM accumulates every entry in the same
+    order as the 64 x 64 one (K steps of 16, MFMA k-groups of 4): results
+    agree bit for bit, on ragged shapes too."""
+    rng = np.random.default_rng(m + 7 * n + k)
+    a = np.asfortranarray(rng.uniform(-1, 1, (m, k)))
+    b = np.asfortranarray(rng.uniform(-1, 1, (k, n)))
+    c = np.asfortranarray(rng.uniform(-1, 1, (m, n)))
+    h = cdf.handle()
+    out = {}
+    try:
+        for tile in (64, 128):
+            h.set_param("gemm_tile", tile)
+            C = cdf.to_device(c)
+            cdf.dgemm_update(cdf.to_device(a), cdf.to_device(b), C)
+            torch.cuda.synchronize()
+            out[tile] = C
+    finally:
+        h.set_param("gemm_tile", 0)
+    assert torch.equal(out[64], out[128])
+    ref = c - a @ b
+    assert np.max(np.abs(cdf.to_host(out[128]) - ref)) <= 4 * k * gpu_util.EPS * (np.abs(a) @ np.abs(b) + np.abs(c)).max()
+
+
+@pytest.mark.parametrize("n,nb", [(2100, 512), (1500, 256)])
+def test_lu_parity_tile128(oracle_mod, n, nb):
+    """LU with every large-enough update on 128 x 128 tiles."""
+    a = workloads.lu_uniform(n, seed=4000 + n)
+    lu_or, ip_or, info_or = oracle_mod.dgetrf(a)
+    lu, ip, info = _lu_gpu(a, lu_nb=nb, gemm_tile=128)
+    assert info == info_or == 0
+    if not np.array_equal(ip, ip_or):
+        pytest.fail(gpu_util.first_pivot_mismatch(ip, ip_or, a, oracle_mod))
+    tol = gpu_util.lu_parity_tolerance(lu_or)
+    assert np.all(np.abs(lu - lu_or) <= tol), float(np.max(np.abs(lu - lu_or) / tol))
+    assert oracle_mod.lu_backward_error(a, lu, ip) <= 10.0
+
+
 def test_invalid_arguments():
     h = cdf.handle()
     L = cdf.lib()
