@@ -120,8 +120,9 @@ typedef enum {
                                        CG, see cdf_dposv_mixed), 1 = classical refinement only,
                                        2 = preconditioned CG from the start */
     CDF_PARAM_PCG_MAX_ITER = 11,    /* iteration cap of that preconditioned CG (0 = 400) */
-    CDF_PARAM_GEMM_TILE = 12,       /* tile of the FP64 update GEMM C -= A B: 64, 128, or 0 = 128 x 128
-                                       when the product has at least 1024 such tiles, else 64 x 64 */
+    CDF_PARAM_GEMM_TILE = 12,       /* tile of the FP64 update GEMM C -= A B: 0 or 64 = 64 x 64, 128 =
+                                       128 x 128 (faster alone on large square products, slower inside
+                                       the LU beside its panel kernels) */
     CDF_PARAM_COUNT = 13
 } cdf_param_t;
 CDF_API cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value);

@@ -442,14 +442,15 @@ __global__ __launch_bounds__(NT, 2) void dgemm_dl128_kernel(int m, int n, int k,
         }
 }
 
-// 128 x 128 tiles for the NN update when the handle asks for them
-// (CDF_PARAM_GEMM_TILE = 128), or by default when the product is large enough
-// to give every CU several tiles (and is at least one tile wide each way).
+// 128 x 128 tiles for the NN update only when the handle asks for them
+// (CDF_PARAM_GEMM_TILE = 128).  Measured on one MI355X: alone, on a 32768 x
+// 32768 x 512 product, 62.4 TF/s against 59.8 for 64 x 64 tiles, but 49 against
+// 55 TF/s on the LU's 65024 x 512 x 512 next-panel product and 49.7 against
+// 54 on K = 256; inside the N = 65536 LU the update launches averaged 51.5
+// TF/s against 53.6 (two large workgroups per CU leave the panel kernels on
+// the second stream less room).  So 64 x 64 stays the default.
 inline bool use_tile128(const cdf::GemmCtx &ctx, int m, int n) {
-    if (ctx.tile == 64) return false;
-    if (m < 128 || n < 128) return false;
-    if (ctx.tile == 128) return true;
-    return (long long)((m + 127) / 128) * ((n + 127) / 128) >= 1024;
+    return ctx.tile == 128 && m >= 128 && n >= 128;
 }
 
 bool dl_ok(int tb, int m, int n, int k, const double *A, int lda, const double *B, int ldb) {
