@@ -8,7 +8,8 @@
 // columns held in LDS:
 //   LU       : panel with partial pivoting (argmax by wave shuffles), row
 //              interchanges on the other columns, U12 = L11^-1 A12 in
-//              registers, trailing update A22 -= L21 U12 from LDS;
+//              registers, trailing update A22 -= L21 U12 on the matrix cores
+//              with both operands from LDS;
 //   Cholesky : panel = potrf of the diagonal block and L21 in one pass
 //              (Sec. 6.2 statements on the panel), trailing lower update.
 // Every workgroup exits once the counter passes the batch size.
@@ -44,11 +45,12 @@ struct VPlanDev {
 template <typename T>
 __device__ inline T tabs(T x) { return x < T(0) ? -x : x; }
 
-// Panel width for an n x n problem: 32 if n x 32 fits in 96 KB, else 16.
+// Panel width for an n x n problem: 32 if the n x 32 panel fits in 128 KB
+// (with a 32 x 64 U12 chunk beside it: the kernel's 144 KB), else 16.
 template <typename T>
 __host__ __device__ inline int panel_nb(int n, int nb_pref) {
     if (nb_pref == 16) return 16;
-    return (size_t)n * 32 * sizeof(T) <= 96 * 1024 ? 32 : 16;
+    return (size_t)n * 32 * sizeof(T) <= 128 * 1024 ? 32 : 16;
 }
 
 // Row interchanges of one panel (pivots pv[0..kb), relative to row k0,
@@ -124,41 +126,99 @@ __device__ void block_argmax(T v, int idx, T *rv, int *ri, int *out) {
 }
 
 // Trailing update C (rows x cols at C, ldc) -= L (rows x kb, LDS, ld ldl) *
-// U (kb x cols, LDS, ld ldu); lower: only entries with row >= col + diag.
-// Each thread accumulates 4 x 4 blocks of a 64 x 64 macro tile.
+// U (kb x cols, LDS, U(k, c) at U[k * ldu + c]); lower: only entries with
+// row + diag >= col.  On the matrix cores (FP64 16x16x4 / FP32 16x16x4
+// MFMA): the product is formed transposed, D = -(U^T) (L^T), so that a
+// lane's results lie down a column of C (16 consecutive rows: coalesced).
+// Each wave takes 32 x 32 blocks of C in turn (2 x 2 MFMA blocks, four
+// independent accumulators) and loads the next block's C while it works on
+// the current one.
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 op(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    // result register v of lane (li + 16 lk) holds D row 4 v + lk
+    __device__ static int drow(int v, int lk) { return 4 * v + lk; }
+};
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    // result register v of lane (li + 16 lk) holds D row 4 lk + v
+    __device__ static int drow(int v, int lk) { return 4 * lk + v; }
+};
+
 template <typename T>
 __device__ void lds_update(T *C, int ldc, int rows, int cols, int kb, const T *L, int ldl, const T *U, int ldu,
                            bool lower, int diag) {
-    const int t = threadIdx.x;
-    const int tx = t & 15, ty = t >> 4;
-    for (int r0 = 0; r0 < rows; r0 += 64)
-        for (int c0 = 0; c0 < cols; c0 += 64) {
-            if (lower && r0 + 63 + diag < c0) continue;
-            T acc[4][4];
+    typedef typename Mfma<T>::v4 v4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nbr = (rows + 31) / 32, nbc = (cols + 31) / 32, nblk = nbr * nbc;
+    // block b covers rows [32 (b % nbr), +32), columns [32 (b / nbr), +32);
+    // those wholly above the diagonal are skipped
+    auto skip = [&](int b) { return lower && 32 * (b % nbr) + 31 + diag < 32 * (b / nbr); };
+    auto next_block = [&](int b) {
+        do b += NT / 64; while (b < nblk && skip(b));
+        return b;
+    };
+    // C entry of result register v, MFMA block (i, j), of block b: row
+    // r0 + 16 i + li, column c0 + 16 j + D row
+    auto load = [&](int b, v4 (&acc)[2][2]) {
+        const int r0 = 32 * (b % nbr), c0 = 32 * (b / nbr);
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-            const int rr = r0 + 4 * tx, cc = c0 + 4 * ty;
-            for (int j = 0; j < kb; ++j) {
-                T l[4], u[4];
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-                for (int a = 0; a < 4; ++a) l[a] = rr + a < rows ? L[(size_t)j * ldl + rr + a] : T(0);
+                for (int v = 0; v < 4; ++v) {
+                    const int r = r0 + 16 * i + li, c = c0 + 16 * j + Mfma<T>::drow(v, lk);
+                    acc[i][j][v] = (b < nblk && r < rows && c < cols) ? C[(size_t)r + (size_t)c * ldc] : T(0);
+                }
+    };
+    int b = wave;
+    if (b < nblk && skip(b)) b = next_block(b);
+    v4 cur[2][2], nxt[2][2];
+    load(b, cur);
+    while (b < nblk) {
+        const int bn = next_block(b);
+        load(bn, nxt);
+        const int r0 = 32 * (b % nbr), c0 = 32 * (b / nbr);
+        for (int k0 = 0; k0 < kb; k0 += 4) {
+            const int kk = k0 + lk;
+            T a[2], bb[2];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) u[b] = cc + b < cols ? U[(size_t)j * ldu + cc + b] : T(0);
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] = fma(l[a], u[b], acc[a][b]);
+            for (int j = 0; j < 2; ++j) {  // A operand: -(U^T)[c][k], c = column of C
+                const int c = c0 + 16 * j + li;
+                a[j] = (kk < kb && c < cols) ? -U[(size_t)kk * ldu + c] : T(0);
             }
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int i = 0; i < 2; ++i) {  // B operand: (L^T)[k][r], r = row of C
+                const int r = r0 + 16 * i + li;
+                bb[i] = (kk < kb && r < rows) ? L[(size_t)kk * ldl + r] : T(0);
+            }
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int r = rr + a, c = cc + b;
-                    if (r < rows && c < cols && (!lower || r + diag >= c)) C[(size_t)r + (size_t)c * ldc] -= acc[a][b];
-                }
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) cur[i][j] = Mfma<T>::op(a[j], bb[i], cur[i][j]);
         }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = r0 + 16 * i + li, c = c0 + 16 * j + Mfma<T>::drow(v, lk);
+                    if (r < rows && c < cols && (!lower || r + diag >= c)) C[(size_t)r + (size_t)c * ldc] = cur[i][j][v];
+                }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) cur[i][j] = nxt[i][j];
+        b = bn;
+    }
 }
 
 template <typename T, int NB>
