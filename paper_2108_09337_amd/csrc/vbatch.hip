@@ -14,15 +14,17 @@
 //              (Sec. 6.2 statements on the panel), trailing lower update.
 // Every workgroup exits once the counter passes the batch size.
 #include "internal.h"
+#include "pairs.h"
 
 #include <algorithm>
+#include <climits>
 #include <new>
 #include <numeric>
 #include <vector>
 
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 512;  // threads per workgroup: the panels keep one row per thread up to n = 512
 constexpr int UC = 64;          // U12 columns staged in LDS per chunk
 constexpr size_t LDS_BYTES = 144 * 1024;
 
@@ -51,58 +53,6 @@ template <typename T>
 __host__ __device__ inline int panel_nb(int n, int nb_pref) {
     if (nb_pref == 16) return 16;
     return (size_t)n * 32 * sizeof(T) <= 128 * 1024 ? 32 : 16;
-}
-
-// Row interchanges of one panel (pivots pv[0..kb), relative to row k0,
-// 0-based) on columns [c0, c1) of A: (dst, src) pairs built by one thread,
-// then all reads before all writes, 64 columns at a time.
-template <typename T>
-__device__ void swap_rows(T *A, int lda, int k0, const int *pv, int kb, int c0, int c1, int *pos, int *cont,
-                          int *dst, int *src, int *s_np) {
-    const int t = threadIdx.x;
-    if (t == 0) {
-        int np = 0;
-        for (int j = 0; j < kb; ++j) {
-            const int p = pv[j];
-            if (p == j) continue;
-            int ij = -1, ip = -1;
-            for (int q = 0; q < np; ++q) {
-                if (pos[q] == j) ij = q;
-                if (pos[q] == p) ip = q;
-            }
-            if (ij < 0) { pos[np] = j; cont[np] = j; ij = np++; }
-            if (ip < 0) { pos[np] = p; cont[np] = p; ip = np++; }
-            const int tmp = cont[ij];
-            cont[ij] = cont[ip];
-            cont[ip] = tmp;
-        }
-        int q2 = 0;
-        for (int q = 0; q < np; ++q)
-            if (cont[q] != pos[q]) { dst[q2] = k0 + pos[q]; src[q2] = k0 + cont[q]; ++q2; }
-        *s_np = q2;
-    }
-    __syncthreads();
-    const int np = *s_np;
-    if (np > 0) {
-        for (int cb = c0; cb < c1; cb += 64) {
-            const int cols = min(64, c1 - cb);
-            const int total = np * cols;
-            T v[16];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int e = t + NT * r;
-                if (e < total) v[r] = A[(size_t)src[e % np] + (size_t)(cb + e / np) * lda];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int e = t + NT * r;
-                if (e < total) A[(size_t)dst[e % np] + (size_t)(cb + e / np) * lda] = v[r];
-            }
-            __syncthreads();
-        }
-    }
-    __syncthreads();
 }
 
 template <typename T>
@@ -221,72 +171,183 @@ __device__ void lds_update(T *C, int ldc, int rows, int cols, int kb, const T *L
     }
 }
 
+template <typename T>
+__device__ inline void better(T &bv, int &bi, T ov, int oi) {
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+}
+
+// LU of the panel [k0, k0 + kb) over rows [k0, n), m = n - k0 <= NT rows:
+// thread t owns panel row t, its kb columns in registers (the column loop is
+// unrolled at compile time).  One barrier per column: before it, every wave
+// reduces its best candidate (largest |a|, lowest row on ties; NaN never
+// wins) and the candidate's owner writes the whole row to the wave's slot,
+// and the owner of row j writes row j (slots by column parity); after it,
+// every thread picks the winner among the slots and swaps, scales (division)
+// and updates its own row.  pv[j] = 1 + pivot row relative to k0.
 template <typename T, int NB>
-__device__ void lu_one(int n, T *A, int lda, int *ipiv, int *info, char *smem) {
+__device__ void lu_panel_regs(int m, int kb, T *A, int lda, int k0, int *pv, int *ipiv, int &first_zero, T *P) {
+    constexpr int NW = NT / 64;
+    __shared__ T cand[2][NW][NB];
+    __shared__ T rowj[2][NB];
+    __shared__ T wv[2][NW];
+    __shared__ int wi[2][NW];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    T x[NB];
+    cdf::static_for<0, NB>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        x[c] = (t < m && c < kb) ? A[(size_t)(k0 + t) + (size_t)(k0 + c) * lda] : T(0);
+    });
+    cdf::static_for<0, NB>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j >= kb) return;
+        const int par = j & 1;
+        T bv = T(-1);
+        int bi = INT_MAX;
+        if (t >= j && t < m) better(bv, bi, tabs(x[j]), t);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) better(bv, bi, __shfl_xor(bv, off), __shfl_xor(bi, off));
+        if (t == bi) cdf::static_for<0, NB>([&](auto cc) { cand[par][wave][decltype(cc)::value] = x[decltype(cc)::value]; });
+        if (t == j) cdf::static_for<0, NB>([&](auto cc) { rowj[par][decltype(cc)::value] = x[decltype(cc)::value]; });
+        if (lane == 0) { wv[par][wave] = bv; wi[par][wave] = bi; }
+        __syncthreads();
+        T v = wv[par][0];
+        int p = wi[par][0], w = 0;
+#pragma unroll
+        for (int q = 1; q < NW; ++q)
+            if (wv[par][q] > v || (wv[par][q] == v && wi[par][q] < p)) { v = wv[par][q]; p = wi[par][q]; w = q; }
+        const T *prow = p == INT_MAX ? rowj[par] : cand[par][w];
+        if (p == INT_MAX) p = j;  // no ordered candidate (NaN column): no interchange
+        const T piv = prow[j];
+        if (t == 0) { pv[j] = p + 1; ipiv[k0 + j] = k0 + p + 1; }
+        if (piv == T(0) && !first_zero) first_zero = k0 + j + 1;
+        if (t == j) {
+            cdf::static_for<0, NB>([&](auto cc) { x[decltype(cc)::value] = prow[decltype(cc)::value]; });
+        } else if (t > j && t < m) {
+            if (t == p) cdf::static_for<0, NB>([&](auto cc) { x[decltype(cc)::value] = rowj[par][decltype(cc)::value]; });
+            if (piv != T(0)) {
+                const T l = x[j] / piv;
+                x[j] = l;
+                cdf::static_for<j + 1, NB>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    x[c] = fma(-l, prow[c], x[c]);
+                });
+            }
+        }
+    });
+    cdf::static_for<0, NB>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        if (t < m && c < kb) {
+            A[(size_t)(k0 + t) + (size_t)(k0 + c) * lda] = x[c];
+            P[(size_t)c * m + t] = x[c];
+        }
+    });
+}
+
+// The same panel for m > NT rows, in LDS (orders up to 1024).
+template <typename T, int NB>
+__device__ void lu_panel_lds(int m, int kb, T *A, int lda, int k0, int *pv, int *ipiv, int &first_zero, T *P) {
     __shared__ T rv[NT / 64];
     __shared__ int ri[NT / 64];
-    __shared__ int s_p, s_np;
+    __shared__ int s_p;
+    const int t = threadIdx.x;
+    for (int e = t; e < m * kb; e += NT) P[e] = A[(size_t)(k0 + e % m) + (size_t)(k0 + e / m) * lda];
+    __syncthreads();
+    for (int j = 0; j < kb; ++j) {
+        T bv = T(-1);
+        int bi = INT_MAX;
+        for (int r = j + t; r < m; r += NT) better(bv, bi, tabs(P[(size_t)j * m + r]), r);
+        block_argmax<T>(bv, bi, rv, ri, &s_p);
+        const int p = s_p == INT_MAX ? j : s_p;
+        if (t == 0) { pv[j] = p + 1; ipiv[k0 + j] = k0 + p + 1; }
+        if (p != j)
+            for (int c = t; c < kb; c += NT) {
+                const T tmp = P[(size_t)c * m + j];
+                P[(size_t)c * m + j] = P[(size_t)c * m + p];
+                P[(size_t)c * m + p] = tmp;
+            }
+        __syncthreads();
+        const T piv = P[(size_t)j * m + j];
+        if (piv == T(0)) {
+            if (!first_zero) first_zero = k0 + j + 1;
+            continue;
+        }
+        for (int r = j + 1 + t; r < m; r += NT) P[(size_t)j * m + r] /= piv;
+        __syncthreads();
+        for (int c = j + 1; c < kb; ++c)
+            for (int r = j + 1 + t; r < m; r += NT)
+                P[(size_t)c * m + r] = fma(-P[(size_t)j * m + r], P[(size_t)c * m + j], P[(size_t)c * m + r]);
+        __syncthreads();
+    }
+    for (int e = t; e < m * kb; e += NT) A[(size_t)(k0 + e % m) + (size_t)(k0 + e / m) * lda] = P[e];
+}
+
+template <typename T, int NB>
+__device__ void lu_one(int n, T *A, int lda, int *ipiv, int *info, char *smem) {
     __shared__ int pv[NB];
-    __shared__ int pos[2 * NB], cont[2 * NB], dst[2 * NB], src[2 * NB];
+    __shared__ int pdst[2 * NB], psrc[2 * NB];
+    __shared__ int s_np;
     const int t = threadIdx.x;
     T *P = reinterpret_cast<T *>(smem);                      // panel, m x kb, ld m
     T *Uc = P + (size_t)n * NB;                              // U12 chunk, kb x UC, ld UC
     int first_zero = 0;
     for (int k0 = 0; k0 < n; k0 += NB) {
         const int kb = min(NB, n - k0), m = n - k0;
-        for (int e = t; e < m * kb; e += NT) P[e] = A[(size_t)(k0 + e % m) + (size_t)(k0 + e / m) * lda];
+        if (m <= NT) lu_panel_regs<T, NB>(m, kb, A, lda, k0, pv, ipiv, first_zero, P);
+        else lu_panel_lds<T, NB>(m, kb, A, lda, k0, pv, ipiv, first_zero, P);
         __syncthreads();
-        for (int j = 0; j < kb; ++j) {
-            T bv = T(-1);
-            int bi = 0x7fffffff;
-            for (int r = j + t; r < m; r += NT) {
-                const T v = tabs(P[(size_t)j * m + r]);
-                if (v > bv) { bv = v; bi = r; }
-            }
-            block_argmax<T>(bv, bi, rv, ri, &s_p);
-            const int p = s_p == 0x7fffffff ? j : s_p;
-            if (t == 0) { pv[j] = p; ipiv[k0 + j] = k0 + p + 1; }
-            if (p != j)
-                for (int c = t; c < kb; c += NT) {
-                    const T tmp = P[(size_t)c * m + j];
-                    P[(size_t)c * m + j] = P[(size_t)c * m + p];
-                    P[(size_t)c * m + p] = tmp;
+        // the panel's interchanges on the other columns [0, k0) and [k0 + kb, n):
+        // (dst, src) pairs by one wave, then every moved row read before any is written
+        if (t < 64) {
+            const int np = build_pairs_wave(pv, 0, kb, m, pdst, psrc, 0);
+            if (t == 0) s_np = np;
+        }
+        __syncthreads();
+        const int np = s_np, others = n - kb;
+        for (int cb = 0; cb < others && np > 0; cb += 64) {
+            const int cols = min(64, others - cb), total = np * cols;
+            constexpr int PER = 2 * NB * 64 / NT + 1;
+            T v[PER];
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                const int e = t + NT * r;
+                if (e < total) {
+                    const int q = cb + e / np, c = q < k0 ? q : q + kb;
+                    v[r] = A[(size_t)(k0 + psrc[e % np]) + (size_t)c * lda];
                 }
-            __syncthreads();
-            const T piv = P[(size_t)j * m + j];
-            if (piv == T(0)) {
-                if (!first_zero) first_zero = k0 + j + 1;
-                continue;
             }
-            for (int r = j + 1 + t; r < m; r += NT) P[(size_t)j * m + r] /= piv;
             __syncthreads();
-            for (int e = t; e < (m - j - 1) * (kb - j - 1); e += NT) {
-                const int r = j + 1 + e % (m - j - 1), c = j + 1 + e / (m - j - 1);
-                P[(size_t)c * m + r] = fma(-P[(size_t)j * m + r], P[(size_t)c * m + j], P[(size_t)c * m + r]);
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                const int e = t + NT * r;
+                if (e < total) {
+                    const int q = cb + e / np, c = q < k0 ? q : q + kb;
+                    A[(size_t)(k0 + pdst[e % np]) + (size_t)c * lda] = v[r];
+                }
             }
             __syncthreads();
         }
-        for (int e = t; e < m * kb; e += NT) A[(size_t)(k0 + e % m) + (size_t)(k0 + e / m) * lda] = P[e];
-        __syncthreads();
-        swap_rows<T>(A, lda, k0, pv, kb, 0, k0, pos, cont, dst, src, &s_np);
-        swap_rows<T>(A, lda, k0, pv, kb, k0 + kb, n, pos, cont, dst, src, &s_np);
         const int rest = n - k0 - kb;
+        // U12 = L11^-1 A12 (unit lower), one column per thread, in registers
+        for (int c = t; c < rest; c += NT) {
+            T x[NB];
+            T *col = A + k0 + (size_t)(k0 + kb + c) * lda;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) x[i] = i < kb ? col[i] : T(0);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int i = j + 1; i < NB; ++i)
+                    if (i < kb) x[i] = fma(-P[(size_t)j * m + i], x[j], x[i]);
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (i < kb) col[i] = x[i];
+        }
+        __syncthreads();
         for (int cb = 0; cb < rest; cb += UC) {
             const int cols = min(UC, rest - cb);
-            // U12 chunk = L11^-1 A12 (unit lower), one column per thread, in registers
-            if (t < cols) {
-                T x[NB];
-                T *col = A + k0 + (size_t)(k0 + kb + cb + t) * lda;
-#pragma unroll
-                for (int i = 0; i < NB; ++i) x[i] = i < kb ? col[i] : T(0);
-#pragma unroll
-                for (int j = 0; j < NB; ++j)
-#pragma unroll
-                    for (int i = j + 1; i < NB; ++i)
-                        if (i < kb) x[i] = fma(-P[(size_t)j * m + i], x[j], x[i]);
-#pragma unroll
-                for (int i = 0; i < NB; ++i)
-                    if (i < kb) { col[i] = x[i]; Uc[(size_t)i * UC + t] = x[i]; }
+            for (int e = t; e < kb * cols; e += NT) {
+                const int i = e % kb, c = e / kb;
+                Uc[(size_t)i * UC + c] = A[(size_t)(k0 + i) + (size_t)(k0 + kb + cb + c) * lda];
             }
             __syncthreads();
             lds_update<T>(A + (k0 + kb) + (size_t)(k0 + kb + cb) * lda, lda, rest, cols, kb, P + kb, m, Uc, UC, false,
@@ -297,50 +358,111 @@ __device__ void lu_one(int n, T *A, int lda, int *ipiv, int *info, char *smem) {
     if (t == 0) *info = first_zero;
 }
 
+// Cholesky of the panel [k0, k0 + kb) over rows [k0, n), m <= NT: thread t
+// owns panel row t (its columns c <= t in registers).  One barrier per
+// column: the rows of the diagonal block publish their column-j entries
+// (by column parity); after the barrier every thread has the pivot and
+// the multipliers l_cj = a_cj / l_jj it needs (the same division thread c
+// does), so it scales and updates its own row.  Returns false at a pivot
+// that is not > 0 (fail = its 1-based column).
 template <typename T, int NB>
-__device__ void chol_one(int n, T *A, int lda, int *info, char *smem) {
+__device__ bool chol_panel_regs(int m, int kb, T *A, int lda, int k0, int &fail, T *P) {
+    __shared__ T colj[2][NB];
+    const int t = threadIdx.x;
+    T x[NB];
+    cdf::static_for<0, NB>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        x[c] = (t < m && c < kb && c <= t) ? A[(size_t)(k0 + t) + (size_t)(k0 + c) * lda] : T(0);
+    });
+    bool ok = true;
+    cdf::static_for<0, NB>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j >= kb || !ok) return;
+        const int par = j & 1;
+        if (t >= j && t < kb) colj[par][t] = x[j];
+        __syncthreads();
+        const T d = colj[par][j];
+        if (!(d > T(0))) {  // uniform
+            ok = false;
+            fail = k0 + j + 1;
+            return;
+        }
+        const T ljj = sqrt(d);
+        if (t == j) {
+            x[j] = ljj;
+        } else if (t > j && t < m) {
+            const T l = x[j] / ljj;
+            x[j] = l;
+            cdf::static_for<j + 1, NB>([&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                if (c < kb && c <= t) x[c] = fma(-l, colj[par][c] / ljj, x[c]);
+            });
+        }
+    });
+    cdf::static_for<0, NB>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        if (t < m && c < kb && c <= t) {
+            A[(size_t)(k0 + t) + (size_t)(k0 + c) * lda] = x[c];
+            P[(size_t)c * m + t] = x[c];
+        }
+    });
+    return ok;
+}
+
+// The same panel for m > NT rows, in LDS.
+template <typename T, int NB>
+__device__ bool chol_panel_lds(int m, int kb, T *A, int lda, int k0, int &fail, T *P) {
     __shared__ int s_fail;
     const int t = threadIdx.x;
-    T *P = reinterpret_cast<T *>(smem);  // panel, m x kb, ld m (lower part used)
     if (t == 0) s_fail = 0;
+    for (int e = t; e < m * kb; e += NT) {
+        const int r = e % m, c = e / m;
+        P[e] = r >= c ? A[(size_t)(k0 + r) + (size_t)(k0 + c) * lda] : T(0);
+    }
     __syncthreads();
-    for (int k0 = 0; k0 < n; k0 += NB) {
-        const int kb = min(NB, n - k0), m = n - k0;
-        for (int e = t; e < m * kb; e += NT) {
-            const int r = e % m, c = e / m;
-            P[e] = r >= c ? A[(size_t)(k0 + r) + (size_t)(k0 + c) * lda] : T(0);
-        }
-        __syncthreads();
-        for (int j = 0; j < kb; ++j) {
-            if (t == 0) {
-                const T d = P[(size_t)j * m + j];
-                if (!(d > T(0))) s_fail = k0 + j + 1;
-                else P[(size_t)j * m + j] = sqrt(d);
-            }
-            __syncthreads();
-            if (s_fail) break;
-            const T ljj = P[(size_t)j * m + j];
-            for (int r = j + 1 + t; r < m; r += NT) P[(size_t)j * m + r] /= ljj;
-            __syncthreads();
-            for (int e = t; e < (m - j - 1) * (kb - j - 1); e += NT) {
-                const int r = j + 1 + e % (m - j - 1), c = j + 1 + e / (m - j - 1);
-                if (r >= c) P[(size_t)c * m + r] = fma(-P[(size_t)j * m + r], P[(size_t)j * m + c], P[(size_t)c * m + r]);
-            }
-            __syncthreads();
-        }
-        for (int e = t; e < m * kb; e += NT) {
-            const int r = e % m, c = e / m;
-            if (r >= c) A[(size_t)(k0 + r) + (size_t)(k0 + c) * lda] = P[e];
+    for (int j = 0; j < kb; ++j) {
+        if (t == 0) {
+            const T d = P[(size_t)j * m + j];
+            if (!(d > T(0))) s_fail = k0 + j + 1;
+            else P[(size_t)j * m + j] = sqrt(d);
         }
         __syncthreads();
         if (s_fail) break;
+        const T ljj = P[(size_t)j * m + j];
+        for (int r = j + 1 + t; r < m; r += NT) P[(size_t)j * m + r] /= ljj;
+        __syncthreads();
+        for (int c = j + 1; c < kb; ++c)
+            for (int r = c + t; r < m; r += NT)
+                P[(size_t)c * m + r] = fma(-P[(size_t)j * m + r], P[(size_t)j * m + c], P[(size_t)c * m + r]);
+        __syncthreads();
+    }
+    for (int e = t; e < m * kb; e += NT) {
+        const int r = e % m, c = e / m;
+        if (r >= c) A[(size_t)(k0 + r) + (size_t)(k0 + c) * lda] = P[e];
+    }
+    __syncthreads();
+    if (s_fail) fail = s_fail;
+    return s_fail == 0;
+}
+
+template <typename T, int NB>
+__device__ void chol_one(int n, T *A, int lda, int *info, char *smem) {
+    const int t = threadIdx.x;
+    T *P = reinterpret_cast<T *>(smem);  // panel, m x kb, ld m (lower part used)
+    int fail = 0;
+    for (int k0 = 0; k0 < n; k0 += NB) {
+        const int kb = min(NB, n - k0), m = n - k0;
+        const bool ok = m <= NT ? chol_panel_regs<T, NB>(m, kb, A, lda, k0, fail, P)
+                                : chol_panel_lds<T, NB>(m, kb, A, lda, k0, fail, P);
+        __syncthreads();
+        if (!ok) break;
         const int rest = n - k0 - kb;
         // lower(A22) -= L21 L21^T with L21 = rows [kb, m) of the panel
         if (rest > 0) lds_update<T>(A + (k0 + kb) + (size_t)(k0 + kb) * lda, lda, rest, rest, kb, P + kb, m, P + kb, m,
                                     true, 0);
         __syncthreads();
     }
-    if (t == 0) *info = s_fail;
+    if (t == 0) *info = fail;
 }
 
 template <typename T>
