@@ -176,11 +176,47 @@ __device__ inline void better(T &bv, int &bi, T ov, int oi) {
     if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
 }
 
+typedef unsigned long long u64;
+
+// Pivot key of a candidate: 1 + the bit pattern of |a| (the patterns of
+// non-negative floating-point values order like the values), 0 for a row
+// that takes no part and for NaN (which never wins).
+__device__ inline u64 pivot_key(double a) {
+    return a == a ? (u64)__double_as_longlong(fabs(a)) + 1ull : 0ull;
+}
+__device__ inline u64 pivot_key(float a) { return a == a ? (u64)__float_as_uint(fabsf(a)) + 1ull : 0ull; }
+
+// One step of the wave maximum: v = max(v, v of the lane the DPP control
+// selects); lanes without a source see 0.
+template <int CTRL, int ROW_MASK>
+__device__ inline u64 dpp_max_step(u64 v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROW_MASK, 0xf, false);
+    const u64 o = ((u64)(unsigned)hi << 32) | (unsigned)lo;
+    return o > v ? o : v;
+}
+
+// Largest key over the wave, in every lane: row shifts by 1, 2, 4, 8 leave
+// each row's maximum in its lane 15, two row broadcasts bring all four to
+// lane 63 (DPP data movement: no LDS round trips).
+__device__ inline u64 wave_max_key(u64 v) {
+    v = dpp_max_step<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_max_step<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_max_step<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_max_step<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_max_step<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_max_step<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, 63);
+    const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+    return ((u64)hi << 32) | lo;
+}
+
 // LU of the panel [k0, k0 + kb) over rows [k0, n), m = n - k0 <= NT rows:
 // thread t owns panel row t, its kb columns in registers (the column loop is
 // unrolled at compile time).  One barrier per column: before it, every wave
 // reduces its best candidate (largest |a|, lowest row on ties; NaN never
-// wins) and the candidate's owner writes the whole row to the wave's slot,
+// wins; a DPP maximum of the keys and a ballot for the lowest lane holding
+// it) and the candidate's owner writes the whole row to the wave's slot,
 // and the owner of row j writes row j (slots by column parity); after it,
 // every thread picks the winner among the slots and swaps, scales (division)
 // and updates its own row.  pv[j] = 1 + pivot row relative to k0.
@@ -189,7 +225,7 @@ __device__ void lu_panel_regs(int m, int kb, T *A, int lda, int k0, int *pv, int
     constexpr int NW = NT / 64;
     __shared__ T cand[2][NW][NB];
     __shared__ T rowj[2][NB];
-    __shared__ T wv[2][NW];
+    __shared__ u64 wv[2][NW];
     __shared__ int wi[2][NW];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     T x[NB];
@@ -201,16 +237,16 @@ __device__ void lu_panel_regs(int m, int kb, T *A, int lda, int k0, int *pv, int
         constexpr int j = decltype(jc)::value;
         if (j >= kb) return;
         const int par = j & 1;
-        T bv = T(-1);
-        int bi = INT_MAX;
-        if (t >= j && t < m) better(bv, bi, tabs(x[j]), t);
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) better(bv, bi, __shfl_xor(bv, off), __shfl_xor(bi, off));
+        // the wave's best row: largest key, then the lowest lane (= row)
+        const u64 key = (t >= j && t < m) ? pivot_key(x[j]) : 0ull;
+        const u64 wk = wave_max_key(key);
+        const u64 hit = __ballot(key == wk && wk != 0ull);
+        const int bi = hit ? (t & ~63) + __builtin_ctzll(hit) : INT_MAX;
         if (t == bi) cdf::static_for<0, NB>([&](auto cc) { cand[par][wave][decltype(cc)::value] = x[decltype(cc)::value]; });
         if (t == j) cdf::static_for<0, NB>([&](auto cc) { rowj[par][decltype(cc)::value] = x[decltype(cc)::value]; });
-        if (lane == 0) { wv[par][wave] = bv; wi[par][wave] = bi; }
+        if (lane == 0) { wv[par][wave] = wk; wi[par][wave] = bi; }
         __syncthreads();
-        T v = wv[par][0];
+        u64 v = wv[par][0];
         int p = wi[par][0], w = 0;
 #pragma unroll
         for (int q = 1; q < NW; ++q)
@@ -303,9 +339,9 @@ __device__ void lu_one(int n, T *A, int lda, int *ipiv, int *info, char *smem) {
         }
         __syncthreads();
         const int np = s_np, others = n - kb;
-        for (int cb = 0; cb < others && np > 0; cb += 64) {
-            const int cols = min(64, others - cb), total = np * cols;
-            constexpr int PER = 2 * NB * 64 / NT + 1;
+        for (int cb = 0; cb < others && np > 0; cb += 128) {
+            const int cols = min(128, others - cb), total = np * cols;
+            constexpr int PER = 2 * NB * 128 / NT + 1;
             T v[PER];
 #pragma unroll
             for (int r = 0; r < PER; ++r) {
@@ -359,15 +395,16 @@ __device__ void lu_one(int n, T *A, int lda, int *ipiv, int *info, char *smem) {
 }
 
 // Cholesky of the panel [k0, k0 + kb) over rows [k0, n), m <= NT: thread t
-// owns panel row t (its columns c <= t in registers).  One barrier per
-// column: the rows of the diagonal block publish their column-j entries
-// (by column parity); after the barrier every thread has the pivot and
-// the multipliers l_cj = a_cj / l_jj it needs (the same division thread c
-// does), so it scales and updates its own row.  Returns false at a pivot
-// that is not > 0 (fail = its 1-based column).
+// owns panel row t (its columns c <= t in registers).  Two barriers per
+// column: after the first every thread has the pivot a_jj (published by
+// row j) and divides its own entry (the multiplier l_tj); the rows of the
+// diagonal block publish theirs (by column parity), and after the second
+// every row updates its entries with them.  Returns false at a pivot that
+// is not > 0 (fail = its 1-based column).
 template <typename T, int NB>
 __device__ bool chol_panel_regs(int m, int kb, T *A, int lda, int k0, int &fail, T *P) {
-    __shared__ T colj[2][NB];
+    __shared__ T djj[2];
+    __shared__ T lcol[2][NB];
     const int t = threadIdx.x;
     T x[NB];
     cdf::static_for<0, NB>([&](auto cc) {
@@ -379,25 +416,29 @@ __device__ bool chol_panel_regs(int m, int kb, T *A, int lda, int k0, int &fail,
         constexpr int j = decltype(jc)::value;
         if (j >= kb || !ok) return;
         const int par = j & 1;
-        if (t >= j && t < kb) colj[par][t] = x[j];
+        if (t == j) djj[par] = x[j];
         __syncthreads();
-        const T d = colj[par][j];
+        const T d = djj[par];
         if (!(d > T(0))) {  // uniform
             ok = false;
             fail = k0 + j + 1;
             return;
         }
         const T ljj = sqrt(d);
+        T l = T(0);
         if (t == j) {
             x[j] = ljj;
         } else if (t > j && t < m) {
-            const T l = x[j] / ljj;
+            l = x[j] / ljj;
             x[j] = l;
+            if (t < kb) lcol[par][t] = l;  // the diagonal block's multipliers, for every row's update
+        }
+        __syncthreads();
+        if (t > j && t < m)
             cdf::static_for<j + 1, NB>([&](auto cc) {
                 constexpr int c = decltype(cc)::value;
-                if (c < kb && c <= t) x[c] = fma(-l, colj[par][c] / ljj, x[c]);
+                if (c < kb && c <= t) x[c] = fma(-l, lcol[par][c], x[c]);
             });
-        }
     });
     cdf::static_for<0, NB>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
