@@ -338,7 +338,8 @@ typedef struct cdf_vbatch_plan_s *cdf_vbatch_plan_t;
 /*
  * Plan a batch of independent small factorizations of uneven sizes, run as
  * one persistent kernel launch (problems handed out largest first from a
- * device work counter) captured in a HIP graph.
+ * device work counter), preceded by a small kernel that gathers the
+ * problems' descriptors.
  *   batch      number of problems (>= 0)
  *   n_host     host int[batch], orders 1 <= n <= 1024
  *   kind_host  host int[batch]: 0 = LU with partial pivoting, 1 = lower Cholesky
@@ -348,7 +349,8 @@ typedef struct cdf_vbatch_plan_s *cdf_vbatch_plan_t;
 CDF_API cdf_status_t cdf_vbatch_plan_create(cdf_handle_t h, int batch, const int *n_host, const int *kind_host,
                                     cdf_dtype_t dt, cdf_vbatch_plan_t *plan);
 /*
- * Run a planned batch (graph replay on the handle's stream).
+ * Run a planned batch on the handle's stream.  Runs of one plan share its
+ * work counter and descriptors: runs of a plan that overlap in time race.
  *   A_array    device array of device pointers to the matrices (double* or float*)
  *   lda_array  device int[batch]
  *   ipiv_array device array of device int* (LU problems; may hold NULL for Cholesky)

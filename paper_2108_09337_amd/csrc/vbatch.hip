@@ -1,11 +1,12 @@
 // Batched small factorizations of uneven sizes in one persistent launch.
 //
 // The plan sorts the problems by estimated cost, largest first (longest-
-// processing-time order), and captures one launch of the persistent kernel
-// (preceded by a kernel that clears the work counter) in a HIP graph.  Each
-// workgroup repeatedly takes the next problem from the device counter and
-// factors it alone, blocked right-looking as in Sec. 7 with a panel of NB
-// columns held in LDS:
+// processing-time order).  A run is two launches: a gather kernel writes one
+// descriptor per problem in that order (pointer, order, leading dimension,
+// pivots, info) from the caller's arrays and clears the work counter, then
+// the persistent kernel's workgroups repeatedly take the next problem from
+// the counter (claiming the following one while they factor) and factor it
+// alone, blocked right-looking as in Sec. 7 with a panel of NB columns:
 //   LU       : panel with partial pivoting (argmax by wave shuffles), row
 //              interchanges on the other columns, U12 = L11^-1 A12 in
 //              registers, trailing update A22 -= L21 U12 on the matrix cores
@@ -20,6 +21,7 @@
 #include <climits>
 #include <new>
 #include <numeric>
+#include <type_traits>
 #include <vector>
 
 namespace {
@@ -28,24 +30,25 @@ constexpr int NT = 512;  // threads per workgroup: the panels keep one row per t
 constexpr int UC = 64;          // U12 columns staged in LDS per chunk
 constexpr size_t LDS_BYTES = 144 * 1024;
 
-struct VArgs {                   // pointer arrays, rewritten before each replay
-    void *const *A;
-    const int *lda;
-    int *const *ipiv;
+// One problem as the persistent kernel sees it, in schedule order: built
+// from the caller's pointer arrays by a gather kernel before each run, so a
+// workgroup reaches its next problem with one uniform load.
+struct __align__(16) VDesc {
+    void *A;
+    int *ipiv;  // null for Cholesky
     int *info;
-};
-
-struct VPlanDev {
-    int batch;
-    const int *n;
-    const int *kind;
-    const int *order;
-    int *counter;
-    VArgs *args;
+    int n, kind, lda, pad;
 };
 
 template <typename T>
 __device__ inline T tabs(T x) { return x < T(0) ? -x : x; }
+
+// Global-memory view of the problems' pointers, which the kernel reads from
+// memory (generic pointers otherwise): their loads and stores then count only
+// against the vector-memory counter, and an LDS wait before a barrier does
+// not also wait for them.
+template <typename T>
+using G = __attribute__((address_space(1))) T;
 
 // Panel width for an n x n problem: 32 if the n x 32 panel fits in 128 KB
 // (with a 32 x 64 U12 chunk beside it: the kernel's 144 KB), else 16.
@@ -56,7 +59,7 @@ __host__ __device__ inline int panel_nb(int n, int nb_pref) {
 }
 
 template <typename T>
-__device__ void block_argmax(T v, int idx, T *rv, int *ri, int *out) {
+__device__ __attribute__((always_inline)) void block_argmax(T v, int idx, T *rv, int *ri, int *out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int off = 32; off >= 1; off >>= 1) {
         const T ov = __shfl_xor(v, off);
@@ -100,9 +103,9 @@ struct Mfma<float> {
     __device__ static int drow(int v, int lk) { return 4 * lk + v; }
 };
 
-template <typename T>
-__device__ void lds_update(T *C, int ldc, int rows, int cols, int kb, const T *L, int ldl, const T *U, int ldu,
-                           bool lower, int diag) {
+template <typename T, int NB>
+__device__ __attribute__((always_inline)) void lds_update(G<T> *C, int ldc, int rows, int cols, int kb, const T *L,
+                                                          int ldl, const T *U, int ldu, bool lower, int diag) {
     typedef typename Mfma<T>::v4 v4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
@@ -116,8 +119,12 @@ __device__ void lds_update(T *C, int ldc, int rows, int cols, int kb, const T *L
     };
     // C entry of result register v, MFMA block (i, j), of block b: row
     // r0 + 16 i + li, column c0 + 16 j + D row
+    // Every load is issued (out-of-range ones read C[0] and are discarded):
+    // no load sits in a branch, so the wait counts stay exact and the next
+    // block's loads are not waited for by this block's products.
     auto load = [&](int b, v4 (&acc)[2][2]) {
-        const int r0 = 32 * (b % nbr), c0 = 32 * (b / nbr);
+        const bool live = b < nblk;
+        const int r0 = live ? 32 * (b % nbr) : 0, c0 = live ? 32 * (b / nbr) : 0;
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -125,7 +132,9 @@ __device__ void lds_update(T *C, int ldc, int rows, int cols, int kb, const T *L
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = r0 + 16 * i + li, c = c0 + 16 * j + Mfma<T>::drow(v, lk);
-                    acc[i][j][v] = (b < nblk && r < rows && c < cols) ? C[(size_t)r + (size_t)c * ldc] : T(0);
+                    const bool ok = live && r < rows && c < cols;
+                    const T val = C[ok ? (size_t)r + (size_t)c * ldc : 0];
+                    acc[i][j][v] = ok ? -val : T(0);
                 }
     };
     int b = wave;
@@ -136,24 +145,46 @@ __device__ void lds_update(T *C, int ldc, int rows, int cols, int kb, const T *L
         const int bn = next_block(b);
         load(bn, nxt);
         const int r0 = 32 * (b % nbr), c0 = 32 * (b / nbr);
-        for (int k0 = 0; k0 < kb; k0 += 4) {
-            const int kk = k0 + lk;
-            T a[2], bb[2];
+        // the accumulators hold -C: D = (U^T)(L^T) - C^T, stored negated.
+        // All NB / 4 steps, unrolled; a block inside the matrix with a full
+        // panel reads its operands without checks, an edge block reads them
+        // clamped to element 0 and zeroes what lies outside.
+        auto steps = [&](auto edge_tag) {
+            constexpr bool EDGE = decltype(edge_tag)::value;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {  // A operand: -(U^T)[c][k], c = column of C
-                const int c = c0 + 16 * j + li;
-                a[j] = (kk < kb && c < cols) ? -U[(size_t)kk * ldu + c] : T(0);
+            for (int k0 = 0; k0 < NB; k0 += 4) {
+                const int kk = k0 + lk;
+                T a[2], bb[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {  // A operand: (U^T)[c][k], c = column of C
+                    const int c = c0 + 16 * j + li;
+                    if (EDGE) {
+                        const bool ok = kk < kb && c < cols;
+                        const T u = U[ok ? kk * ldu + c : 0];
+                        a[j] = ok ? u : T(0);
+                    } else {
+                        a[j] = U[kk * ldu + c];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {  // B operand: (L^T)[k][r], r = row of C
+                    const int r = r0 + 16 * i + li;
+                    if (EDGE) {
+                        const bool ok = kk < kb && r < rows;
+                        const T l = L[ok ? kk * ldl + r : 0];
+                        bb[i] = ok ? l : T(0);
+                    } else {
+                        bb[i] = L[kk * ldl + r];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) cur[i][j] = Mfma<T>::op(a[j], bb[i], cur[i][j]);
             }
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {  // B operand: (L^T)[k][r], r = row of C
-                const int r = r0 + 16 * i + li;
-                bb[i] = (kk < kb && r < rows) ? L[(size_t)kk * ldl + r] : T(0);
-            }
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) cur[i][j] = Mfma<T>::op(a[j], bb[i], cur[i][j]);
-        }
+        };
+        if (kb < NB || r0 + 32 > rows || c0 + 32 > cols) steps(std::true_type());
+        else steps(std::false_type());
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -161,7 +192,7 @@ __device__ void lds_update(T *C, int ldc, int rows, int cols, int kb, const T *L
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = r0 + 16 * i + li, c = c0 + 16 * j + Mfma<T>::drow(v, lk);
-                    if (r < rows && c < cols && (!lower || r + diag >= c)) C[(size_t)r + (size_t)c * ldc] = cur[i][j][v];
+                    if (r < rows && c < cols && (!lower || r + diag >= c)) C[(size_t)r + (size_t)c * ldc] = -cur[i][j][v];
                 }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -177,6 +208,12 @@ __device__ inline void better(T &bv, int &bi, T ov, int oi) {
 }
 
 typedef unsigned long long u64;
+
+// A wave's pivot candidate (key, row) as one 16-byte LDS slot.
+struct __align__(16) Slot {
+    u64 key;
+    int idx, pad;
+};
 
 // Pivot key of a candidate: 1 + the bit pattern of |a| (the patterns of
 // non-negative floating-point values order like the values), 0 for a row
@@ -221,13 +258,16 @@ __device__ inline u64 wave_max_key(u64 v) {
 // every thread picks the winner among the slots and swaps, scales (division)
 // and updates its own row.  pv[j] = 1 + pivot row relative to k0.
 template <typename T, int NB>
-__device__ void lu_panel_regs(int m, int kb, T *A, int lda, int k0, int *pv, int *ipiv, int &first_zero, T *P) {
+__device__ __attribute__((always_inline)) int lu_panel_regs(int m, int kb, G<T> *A, int lda, int k0, int *pv, G<int> *ipiv, int first_zero, T *P) {
     constexpr int NW = NT / 64;
     __shared__ T cand[2][NW][NB];
     __shared__ T rowj[2][NB];
-    __shared__ u64 wv[2][NW];
-    __shared__ int wi[2][NW];
+    __shared__ Slot ws[2][NW];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // a wave past the panel's last row only keeps the barriers: its slots
+    // say "no candidate" for the whole panel
+    const bool wact = wave * 64 < m;
+    if (!wact && lane == 0) ws[0][wave] = ws[1][wave] = Slot{0ull, INT_MAX, 0};
     T x[NB];
     cdf::static_for<0, NB>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
@@ -237,20 +277,32 @@ __device__ void lu_panel_regs(int m, int kb, T *A, int lda, int k0, int *pv, int
         constexpr int j = decltype(jc)::value;
         if (j >= kb) return;
         const int par = j & 1;
-        // the wave's best row: largest key, then the lowest lane (= row)
-        const u64 key = (t >= j && t < m) ? pivot_key(x[j]) : 0ull;
-        const u64 wk = wave_max_key(key);
-        const u64 hit = __ballot(key == wk && wk != 0ull);
-        const int bi = hit ? (t & ~63) + __builtin_ctzll(hit) : INT_MAX;
-        if (t == bi) cdf::static_for<0, NB>([&](auto cc) { cand[par][wave][decltype(cc)::value] = x[decltype(cc)::value]; });
-        if (t == j) cdf::static_for<0, NB>([&](auto cc) { rowj[par][decltype(cc)::value] = x[decltype(cc)::value]; });
-        if (lane == 0) { wv[par][wave] = wk; wi[par][wave] = bi; }
+        if (wact) {
+            // the wave's best row: largest key, then the lowest lane (= row)
+            const u64 key = (t >= j && t < m) ? pivot_key(x[j]) : 0ull;
+            const u64 wk = wave_max_key(key);
+            const u64 hit = __ballot(key == wk && wk != 0ull);
+            const int bi = hit ? (t & ~63) + __builtin_ctzll(hit) : INT_MAX;
+            if (t == bi) cdf::static_for<0, NB>([&](auto cc) { cand[par][wave][decltype(cc)::value] = x[decltype(cc)::value]; });
+            if (t == j) cdf::static_for<0, NB>([&](auto cc) { rowj[par][decltype(cc)::value] = x[decltype(cc)::value]; });
+            if (lane == 0) ws[par][wave] = Slot{wk, bi, 0};
+        }
         __syncthreads();
-        u64 v = wv[par][0];
-        int p = wi[par][0], w = 0;
+        if (!wact) return;
+        // all slots read at once, then a branchless maximum; a later wave
+        // holds higher rows, so strictly greater keeps the lowest row on ties
+        Slot sl[NW];
 #pragma unroll
-        for (int q = 1; q < NW; ++q)
-            if (wv[par][q] > v || (wv[par][q] == v && wi[par][q] < p)) { v = wv[par][q]; p = wi[par][q]; w = q; }
+        for (int q = 0; q < NW; ++q) sl[q] = ws[par][q];
+        u64 v = sl[0].key;
+        int p = sl[0].idx, w = 0;
+#pragma unroll
+        for (int q = 1; q < NW; ++q) {
+            const bool gt = sl[q].key > v;
+            v = gt ? sl[q].key : v;
+            p = gt ? sl[q].idx : p;
+            w = gt ? q : w;
+        }
         const T *prow = p == INT_MAX ? rowj[par] : cand[par][w];
         if (p == INT_MAX) p = j;  // no ordered candidate (NaN column): no interchange
         const T piv = prow[j];
@@ -277,11 +329,12 @@ __device__ void lu_panel_regs(int m, int kb, T *A, int lda, int k0, int *pv, int
             P[(size_t)c * m + t] = x[c];
         }
     });
+    return first_zero;
 }
 
 // The same panel for m > NT rows, in LDS (orders up to 1024).
 template <typename T, int NB>
-__device__ void lu_panel_lds(int m, int kb, T *A, int lda, int k0, int *pv, int *ipiv, int &first_zero, T *P) {
+__device__ __attribute__((always_inline)) int lu_panel_lds(int m, int kb, G<T> *A, int lda, int k0, int *pv, G<int> *ipiv, int first_zero, T *P) {
     __shared__ T rv[NT / 64];
     __shared__ int ri[NT / 64];
     __shared__ int s_p;
@@ -315,10 +368,11 @@ __device__ void lu_panel_lds(int m, int kb, T *A, int lda, int k0, int *pv, int 
         __syncthreads();
     }
     for (int e = t; e < m * kb; e += NT) A[(size_t)(k0 + e % m) + (size_t)(k0 + e / m) * lda] = P[e];
+    return first_zero;
 }
 
 template <typename T, int NB>
-__device__ void lu_one(int n, T *A, int lda, int *ipiv, int *info, char *smem) {
+__device__ __attribute__((always_inline)) void lu_one(int n, G<T> *A, int lda, G<int> *ipiv, G<int> *info, char *smem) {
     __shared__ int pv[NB];
     __shared__ int pdst[2 * NB], psrc[2 * NB];
     __shared__ int s_np;
@@ -328,8 +382,8 @@ __device__ void lu_one(int n, T *A, int lda, int *ipiv, int *info, char *smem) {
     int first_zero = 0;
     for (int k0 = 0; k0 < n; k0 += NB) {
         const int kb = min(NB, n - k0), m = n - k0;
-        if (m <= NT) lu_panel_regs<T, NB>(m, kb, A, lda, k0, pv, ipiv, first_zero, P);
-        else lu_panel_lds<T, NB>(m, kb, A, lda, k0, pv, ipiv, first_zero, P);
+        first_zero = m <= NT ? lu_panel_regs<T, NB>(m, kb, A, lda, k0, pv, ipiv, first_zero, P)
+                             : lu_panel_lds<T, NB>(m, kb, A, lda, k0, pv, ipiv, first_zero, P);
         __syncthreads();
         // the panel's interchanges on the other columns [0, k0) and [k0 + kb, n):
         // (dst, src) pairs by one wave, then every moved row read before any is written
@@ -366,7 +420,7 @@ __device__ void lu_one(int n, T *A, int lda, int *ipiv, int *info, char *smem) {
         // U12 = L11^-1 A12 (unit lower), one column per thread, in registers
         for (int c = t; c < rest; c += NT) {
             T x[NB];
-            T *col = A + k0 + (size_t)(k0 + kb + c) * lda;
+            G<T> *col = A + k0 + (size_t)(k0 + kb + c) * lda;
 #pragma unroll
             for (int i = 0; i < NB; ++i) x[i] = i < kb ? col[i] : T(0);
 #pragma unroll
@@ -386,7 +440,7 @@ __device__ void lu_one(int n, T *A, int lda, int *ipiv, int *info, char *smem) {
                 Uc[(size_t)i * UC + c] = A[(size_t)(k0 + i) + (size_t)(k0 + kb + cb + c) * lda];
             }
             __syncthreads();
-            lds_update<T>(A + (k0 + kb) + (size_t)(k0 + kb + cb) * lda, lda, rest, cols, kb, P + kb, m, Uc, UC, false,
+            lds_update<T, NB>(A + (k0 + kb) + (size_t)(k0 + kb + cb) * lda, lda, rest, cols, kb, P + kb, m, Uc, UC, false,
                           0);
             __syncthreads();
         }
@@ -402,7 +456,7 @@ __device__ void lu_one(int n, T *A, int lda, int *ipiv, int *info, char *smem) {
 // every row updates its entries with them.  Returns false at a pivot that
 // is not > 0 (fail = its 1-based column).
 template <typename T, int NB>
-__device__ bool chol_panel_regs(int m, int kb, T *A, int lda, int k0, int &fail, T *P) {
+__device__ __attribute__((always_inline)) bool chol_panel_regs(int m, int kb, G<T> *A, int lda, int k0, int &fail, T *P) {
     __shared__ T djj[2];
     __shared__ T lcol[2][NB];
     const int t = threadIdx.x;
@@ -412,6 +466,9 @@ __device__ bool chol_panel_regs(int m, int kb, T *A, int lda, int k0, int &fail,
         x[c] = (t < m && c < kb && c <= t) ? A[(size_t)(k0 + t) + (size_t)(k0 + c) * lda] : T(0);
     });
     bool ok = true;
+    // waves past the panel's last row only keep the barriers (rows j and
+    // the diagonal block's rows lie in wave 0)
+    const bool wact = (t >> 6) * 64 < m;
     cdf::static_for<0, NB>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         if (j >= kb || !ok) return;
@@ -424,17 +481,19 @@ __device__ bool chol_panel_regs(int m, int kb, T *A, int lda, int k0, int &fail,
             fail = k0 + j + 1;
             return;
         }
-        const T ljj = sqrt(d);
         T l = T(0);
-        if (t == j) {
-            x[j] = ljj;
-        } else if (t > j && t < m) {
-            l = x[j] / ljj;
-            x[j] = l;
-            if (t < kb) lcol[par][t] = l;  // the diagonal block's multipliers, for every row's update
+        if (wact) {
+            const T ljj = sqrt(d);
+            if (t == j) {
+                x[j] = ljj;
+            } else if (t > j && t < m) {
+                l = x[j] / ljj;
+                x[j] = l;
+                if (t < kb) lcol[par][t] = l;  // the diagonal block's multipliers, for every row's update
+            }
         }
         __syncthreads();
-        if (t > j && t < m)
+        if (wact && t > j && t < m)
             cdf::static_for<j + 1, NB>([&](auto cc) {
                 constexpr int c = decltype(cc)::value;
                 if (c < kb && c <= t) x[c] = fma(-l, lcol[par][c], x[c]);
@@ -452,7 +511,7 @@ __device__ bool chol_panel_regs(int m, int kb, T *A, int lda, int k0, int &fail,
 
 // The same panel for m > NT rows, in LDS.
 template <typename T, int NB>
-__device__ bool chol_panel_lds(int m, int kb, T *A, int lda, int k0, int &fail, T *P) {
+__device__ __attribute__((always_inline)) bool chol_panel_lds(int m, int kb, G<T> *A, int lda, int k0, int &fail, T *P) {
     __shared__ int s_fail;
     const int t = threadIdx.x;
     if (t == 0) s_fail = 0;
@@ -487,7 +546,7 @@ __device__ bool chol_panel_lds(int m, int kb, T *A, int lda, int k0, int &fail, 
 }
 
 template <typename T, int NB>
-__device__ void chol_one(int n, T *A, int lda, int *info, char *smem) {
+__device__ __attribute__((always_inline)) void chol_one(int n, G<T> *A, int lda, G<int> *info, char *smem) {
     const int t = threadIdx.x;
     T *P = reinterpret_cast<T *>(smem);  // panel, m x kb, ld m (lower part used)
     int fail = 0;
@@ -499,7 +558,7 @@ __device__ void chol_one(int n, T *A, int lda, int *info, char *smem) {
         if (!ok) break;
         const int rest = n - k0 - kb;
         // lower(A22) -= L21 L21^T with L21 = rows [kb, m) of the panel
-        if (rest > 0) lds_update<T>(A + (k0 + kb) + (size_t)(k0 + kb) * lda, lda, rest, rest, kb, P + kb, m, P + kb, m,
+        if (rest > 0) lds_update<T, NB>(A + (k0 + kb) + (size_t)(k0 + kb) * lda, lda, rest, rest, kb, P + kb, m, P + kb, m,
                                     true, 0);
         __syncthreads();
     }
@@ -507,40 +566,56 @@ __device__ void chol_one(int n, T *A, int lda, int *info, char *smem) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void vbatch_kernel(const VPlanDev *__restrict__ pd, int nb_pref) {
+__global__ __launch_bounds__(NT) void vbatch_kernel(const VDesc *__restrict__ desc, int batch, int *counter,
+                                                    int nb_pref) {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_idx;
-    const int batch = pd->batch;
+    if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
+    __syncthreads();
+    int idx = s_idx;
     for (;;) {
-        if (threadIdx.x == 0) s_idx = atomicAdd(pd->counter, 1);
-        __syncthreads();
-        const int idx = s_idx;
-        __syncthreads();
+        idx = __builtin_amdgcn_readfirstlane(idx);
         if (idx >= batch) break;
-        const int p = pd->order[idx];
-        const int n = pd->n[p];
-        T *A = static_cast<T *>(pd->args->A[p]);
-        const int lda = pd->args->lda[p];
-        int *info = pd->args->info + p;
-        if (pd->kind[p] == 0) {
-            int *ipiv = pd->args->ipiv[p];
-            if (panel_nb<T>(n, nb_pref) == 32) lu_one<T, 32>(n, A, lda, ipiv, info, smem);
-            else lu_one<T, 16>(n, A, lda, ipiv, info, smem);
+        // the next problem is claimed now: the atomic's round trip overlaps
+        // with this one's factorization
+        int next = 0;
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        const VDesc d = desc[idx];
+        G<T> *A = (G<T> *)d.A;
+        G<int> *info = (G<int> *)d.info;
+        if (d.kind == 0) {
+            G<int> *ipiv = (G<int> *)d.ipiv;
+            if (panel_nb<T>(d.n, nb_pref) == 32) lu_one<T, 32>(d.n, A, d.lda, ipiv, info, smem);
+            else lu_one<T, 16>(d.n, A, d.lda, ipiv, info, smem);
         } else {
-            if (panel_nb<T>(n, nb_pref) == 32) chol_one<T, 32>(n, A, lda, info, smem);
-            else chol_one<T, 16>(n, A, lda, info, smem);
+            if (panel_nb<T>(d.n, nb_pref) == 32) chol_one<T, 32>(d.n, A, d.lda, info, smem);
+            else chol_one<T, 16>(d.n, A, d.lda, info, smem);
         }
         __syncthreads();
+        if (threadIdx.x == 0) s_idx = next;
+        __syncthreads();
+        idx = s_idx;
     }
 }
 
-__global__ void reset_counter_kernel(int *c) { *c = 0; }
-
-__global__ void set_args_kernel(VArgs *a, void *const *A, const int *lda, int *const *ipiv, int *info) {
-    a->A = A;
-    a->lda = lda;
-    a->ipiv = ipiv;
-    a->info = info;
+// desc[i] = problem order[i] of the caller's arrays; thread 0 also clears
+// the work counter.
+__global__ void gather_desc_kernel(int batch, const int *__restrict__ order, const int *__restrict__ n,
+                                   const int *__restrict__ kind, void *const *A, const int *lda, int *const *ipiv,
+                                   int *info, VDesc *desc, int *counter) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *counter = 0;
+    if (i >= batch) return;
+    const int p = order[i];
+    VDesc d;
+    d.A = A[p];
+    d.kind = kind[p];
+    d.ipiv = d.kind == 0 ? ipiv[p] : nullptr;
+    d.info = info + p;
+    d.n = n[p];
+    d.lda = lda[p];
+    d.pad = 0;
+    desc[i] = d;
 }
 
 }  // namespace
@@ -551,11 +626,10 @@ struct cdf_vbatch_plan_s {
     cdf_dtype_t dt = CDF_F64;
     int grid = 0;
     int nb_pref = 0;
-    void *dev = nullptr;  // VPlanDev + arrays + counter + VArgs
-    VPlanDev *pd = nullptr;
-    VArgs *args = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    size_t lds = 0;
+    void *dev = nullptr;  // sizes, kinds, schedule, counter, descriptors
+    int *n = nullptr, *kind = nullptr, *order = nullptr, *counter = nullptr;
+    VDesc *desc = nullptr;
 };
 
 extern "C" {
@@ -592,28 +666,19 @@ cdf_status_t cdf_vbatch_plan_create(cdf_handle_t h, int batch, const int *n_host
         return ca > cb;
     });
     const size_t nb4 = cdf::align_up((size_t)std::max(batch, 1) * sizeof(int), 256);
-    const size_t bytes = cdf::align_up(sizeof(VPlanDev), 256) + 3 * nb4 + 256 + cdf::align_up(sizeof(VArgs), 256);
+    const size_t bytes = 3 * nb4 + 256 + cdf::align_up((size_t)std::max(batch, 1) * sizeof(VDesc), 256);
     if (hipMalloc(&p->dev, bytes) != hipSuccess) { delete p; return CDF_ERR_ALLOC; }
     char *base = static_cast<char *>(p->dev);
-    VPlanDev hpd;
-    hpd.batch = batch;
-    int *dn = reinterpret_cast<int *>(base + cdf::align_up(sizeof(VPlanDev), 256));
-    int *dk = reinterpret_cast<int *>(reinterpret_cast<char *>(dn) + nb4);
-    int *dord = reinterpret_cast<int *>(reinterpret_cast<char *>(dk) + nb4);
-    int *dcnt = reinterpret_cast<int *>(reinterpret_cast<char *>(dord) + nb4);
-    VArgs *dargs = reinterpret_cast<VArgs *>(reinterpret_cast<char *>(dcnt) + 256);
-    hpd.n = dn;
-    hpd.kind = dk;
-    hpd.order = dord;
-    hpd.counter = dcnt;
-    hpd.args = dargs;
-    p->pd = reinterpret_cast<VPlanDev *>(base);
-    p->args = dargs;
-    bool ok = hipMemcpy(base, &hpd, sizeof(hpd), hipMemcpyHostToDevice) == hipSuccess;
+    p->n = reinterpret_cast<int *>(base);
+    p->kind = reinterpret_cast<int *>(base + nb4);
+    p->order = reinterpret_cast<int *>(base + 2 * nb4);
+    p->counter = reinterpret_cast<int *>(base + 3 * nb4);
+    p->desc = reinterpret_cast<VDesc *>(base + 3 * nb4 + 256);
+    bool ok = true;
     if (batch > 0) {
-        ok = ok && hipMemcpy(dn, n_host, batch * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
-        ok = ok && hipMemcpy(dk, kind_host, batch * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
-        ok = ok && hipMemcpy(dord, order.data(), batch * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(p->n, n_host, batch * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(p->kind, kind_host, batch * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(p->order, order.data(), batch * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     }
     const void *fn = dt == CDF_F64 ? reinterpret_cast<const void *>(&vbatch_kernel<double>)
                                    : reinterpret_cast<const void *>(&vbatch_kernel<float>);
@@ -624,31 +689,11 @@ cdf_status_t cdf_vbatch_plan_create(cdf_handle_t h, int batch, const int *n_host
         const int nbp = dt == CDF_F64 ? panel_nb<double>(n_host[i], p->nb_pref) : panel_nb<float>(n_host[i], p->nb_pref);
         lds = std::max(lds, ((size_t)n_host[i] * nbp + (size_t)nbp * UC) * es);
     }
-    lds = cdf::align_up(lds, 256);
-    ok = ok && lds <= LDS_BYTES;
+    p->lds = cdf::align_up(lds, 256);
+    ok = ok && p->lds <= LDS_BYTES;
     ok = ok && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_BYTES) == hipSuccess;
-    // capture: counter reset + persistent launch
-    hipStream_t cs = nullptr;
-    ok = ok && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
-    if (ok && batch > 0) {
-        ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        if (ok) {
-            hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, cs, dcnt);
-            VPlanDev *pdp = p->pd;
-            int nbp = p->nb_pref;
-            if (dt == CDF_F64)
-                hipLaunchKernelGGL((vbatch_kernel<double>), dim3(p->grid), dim3(NT), lds, cs, pdp, nbp);
-            else
-                hipLaunchKernelGGL((vbatch_kernel<float>), dim3(p->grid), dim3(NT), lds, cs, pdp, nbp);
-            ok = hipStreamEndCapture(cs, &p->graph) == hipSuccess;
-        }
-        ok = ok && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
-    }
-    if (cs) (void)hipStreamDestroy(cs);
     if (!ok) {
         (void)hipGetLastError();
-        if (p->exec) (void)hipGraphExecDestroy(p->exec);
-        if (p->graph) (void)hipGraphDestroy(p->graph);
         (void)hipFree(p->dev);
         delete p;
         return CDF_ERR_HIP;
@@ -669,17 +714,22 @@ cdf_status_t cdf_vbatch_run(cdf_handle_t h, cdf_vbatch_plan_t plan, void *const 
     if (!ipiv_array) return bad(5);
     if (!info_array) return bad(6);
     if (plan->device != h->device) return bad(2);
-    hipLaunchKernelGGL(set_args_kernel, dim3(1), dim3(1), 0, h->stream, plan->args, A_array, lda_array, ipiv_array,
-                       info_array);
+    hipLaunchKernelGGL(gather_desc_kernel, dim3((plan->batch + 255) / 256), dim3(256), 0, h->stream, plan->batch,
+                       plan->order, plan->n, plan->kind, A_array, lda_array, ipiv_array, info_array, plan->desc,
+                       plan->counter);
     CDF_HIP_TRY(hipGetLastError());
-    CDF_HIP_TRY(hipGraphLaunch(plan->exec, h->stream));
+    if (plan->dt == CDF_F64)
+        hipLaunchKernelGGL((vbatch_kernel<double>), dim3(plan->grid), dim3(NT), plan->lds, h->stream, plan->desc,
+                           plan->batch, plan->counter, plan->nb_pref);
+    else
+        hipLaunchKernelGGL((vbatch_kernel<float>), dim3(plan->grid), dim3(NT), plan->lds, h->stream, plan->desc,
+                           plan->batch, plan->counter, plan->nb_pref);
+    CDF_HIP_TRY(hipGetLastError());
     return CDF_OK;
 }
 
 cdf_status_t cdf_vbatch_plan_destroy(cdf_vbatch_plan_t plan) {
     if (!plan) return CDF_ERR_INVALID_ARG;
-    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
-    if (plan->graph) (void)hipGraphDestroy(plan->graph);
     (void)hipDeviceSynchronize();
     if (plan->dev) (void)hipFree(plan->dev);
     delete plan;
