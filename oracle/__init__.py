@@ -310,6 +310,88 @@ def dequantize(fmt: int, q: np.ndarray, e: np.ndarray, tm: int, tn: int) -> np.n
 # Mixed-precision blocked factorizations (numpy, step by step)
 # --------------------------------------------------------------------------
 
+# --------------------------------------------------------------------------
+# Tournament pivoting (Sec. 7.3, "Tournament Pivoting" and "Pivoting in
+# COnfLUX"; Table 1, row "pivoting")
+# --------------------------------------------------------------------------
+
+def gepp_rows(p: np.ndarray, rows: list, v: int) -> list:
+    """The rows of ``p`` (indices) that LU with partial pivoting of the
+    stacked rows ``p[rows]`` brings to the top, in pivot order (at most v).
+    The local decomposition each participant of a tournament round runs."""
+    rows = list(rows)
+    k = min(v, len(rows), p.shape[1])
+    _, ipiv, _ = dgetrf(p[rows, :], ksteps=k)
+    order = list(rows)
+    for i in range(k):
+        q = int(ipiv[i]) - 1
+        order[i], order[q] = order[q], order[i]
+    return order[:k]
+
+
+def tournament_pivots(p: np.ndarray, v: int, block: int, fanin: int) -> list:
+    """The v pivot rows of the block column ``p`` (m x v, original values)
+    chosen by tournament pivoting: every group of ``block`` consecutive rows
+    picks v candidates by a local LU with partial pivoting; then, round by
+    round, the candidate sets are taken ``fanin`` at a time (in order,
+    stacked in order) and a local LU of their original rows keeps v of them,
+    until one set is left.  Returns row indices in pivot order."""
+    m = p.shape[0]
+    sets = [gepp_rows(p, range(s, min(m, s + block)), v) for s in range(0, m, block)]
+    while len(sets) > 1:
+        sets = [gepp_rows(p, [r for st in sets[i:i + fanin] for r in st], v)
+                for i in range(0, len(sets), fanin)]
+    return sets[0]
+
+
+def calu_panel(a: np.ndarray, leaf: int = 32, block: int = 256, fanin: int = 8):
+    """LU of an m x n block column (m >= n) whose pivots are chosen by
+    tournament pivoting on each ``leaf``-wide column block in turn.
+
+    For each leaf at column c0 (width w): the tournament over the current
+    rows [c0, m) of the leaf's columns names the w pivot rows; they are
+    interchanged into rows c0.. c0+w-1 in pivot order (LAPACK-style swap
+    sequence, applied to all columns); the leaf's columns are then
+    eliminated without further interchanges (a zero pivot is recorded in
+    info and its column left unscaled); U12 = L11^-1 A12 and A22 -= L21 U12
+    update the columns right of the leaf.  With block >= m every tournament
+    is a single local LU, so the result is LU with partial pivoting.
+    Returns (lu, ipiv 1-based, info)."""
+    from scipy.linalg import solve_triangular  # library primitive: triangular solve
+
+    lu = _f64(a)
+    m, n = lu.shape
+    kmax = min(m, n)
+    ipiv = np.zeros(kmax, dtype=np.int32)
+    info = 0
+    for c0 in range(0, kmax, leaf):
+        w = min(leaf, kmax - c0)
+        order = tournament_pivots(lu[c0:, c0:c0 + w], w, block, fanin)
+        at = list(range(m - c0))       # at[i]: original (leaf-relative) row now at position i
+        where = {r: r for r in at}     # where[r]: position of original row r
+        for j, r in enumerate(order):
+            q = where[r]
+            ipiv[c0 + j] = c0 + q + 1
+            if q != j:
+                lu[[c0 + j, c0 + q], :] = lu[[c0 + q, c0 + j], :]
+                rj = at[j]
+                at[j], at[q] = r, rj
+                where[r], where[rj] = j, q
+        for k in range(c0, c0 + w):
+            piv = lu[k, k]
+            if piv == 0.0:
+                if not info:
+                    info = k + 1
+                continue
+            lu[k + 1:, k] /= piv
+            lu[k + 1:, k + 1:c0 + w] -= np.outer(lu[k + 1:, k], lu[k, k + 1:c0 + w])
+        if c0 + w < n:
+            l11 = np.tril(lu[c0:c0 + w, c0:c0 + w], -1) + np.eye(w)
+            lu[c0:c0 + w, c0 + w:] = solve_triangular(l11, lu[c0:c0 + w, c0 + w:], lower=True, unit_diagonal=True)
+            lu[c0 + w:, c0 + w:] -= lu[c0 + w:, c0:c0 + w] @ lu[c0:c0 + w, c0 + w:]
+    return lu, ipiv, info
+
+
 def _laswp_rows(w: np.ndarray, cols: slice, k0: int, piv: np.ndarray) -> None:
     """Apply interchanges (0-based rows k0+i <-> piv[i]) in order to w[:, cols]."""
     for i, p in enumerate(piv):
@@ -320,7 +402,7 @@ def _laswp_rows(w: np.ndarray, cols: slice, k0: int, piv: np.ndarray) -> None:
             w[p, cols] = tmp
 
 
-def mixed_getrf(a: np.ndarray, nb: int, fmt: int, tm: int, tn: int):
+def mixed_getrf(a: np.ndarray, nb: int, fmt: int, tm: int, tn: int, tournament=None):
     """Blocked right-looking LU with a low-precision trailing update.
 
     Not defined by the paper (it only cites low-precision LU with refinement
@@ -333,6 +415,8 @@ def mixed_getrf(a: np.ndarray, nb: int, fmt: int, tm: int, tn: int):
         U12 = L11^-1 binary64(W[k:k+nb, k+nb:])  (binary64), W12 = binary32(U12)
         L21, U12 (binary32) tile-quantized: L21 in tm x nb tiles, U12 in nb x tn
         W22 = binary32(binary64(W22) - dq(L21) @ dq(U12))
+    With ``tournament = (leaf, block, fanin)`` the panel's pivots are chosen
+    by tournament pivoting (calu_panel) instead of partial pivoting.
     Returns (w float32, ipiv 1-based, info).
     """
     from scipy.linalg import solve_triangular  # library primitive: triangular solve
@@ -344,7 +428,7 @@ def mixed_getrf(a: np.ndarray, nb: int, fmt: int, tm: int, tn: int):
     for k in range(0, n, nb):
         kb = min(nb, n - k)
         p = w[k:, k:k + kb].astype(np.float64)
-        pl, pp, pinfo = dgetrf(p)
+        pl, pp, pinfo = dgetrf(p) if tournament is None else calu_panel(p, *tournament)
         if pinfo and not info:
             info = k + pinfo
         w[k:, k:k + kb] = pl.astype(np.float32)
