@@ -123,7 +123,14 @@ typedef enum {
     CDF_PARAM_GEMM_TILE = 12,       /* tile of the FP64 update GEMM C -= A B: 0 or 64 = 64 x 64, 128 =
                                        128 x 128 (faster alone on large square products, slower inside
                                        the LU beside its panel kernels) */
-    CDF_PARAM_COUNT = 13
+    CDF_PARAM_LU_PIVOT = 13,        /* pivot choice of the LUs (cdf_dgetrf, cdf_dgesv, the mixed LU):
+                                       0 = partial pivoting (LAPACK getrf pivots), 1 = tournament
+                                       pivoting (Sec. 7.3): every 32-column leaf of a panel picks its
+                                       pivots in rounds of local LUs over row blocks, a different but
+                                       equally valid row order (|L| may exceed 1) */
+    CDF_PARAM_TOURN_BLOCK = 14,     /* tournament: rows per first-round block, 32..256 (0 = 256) */
+    CDF_PARAM_TOURN_FANIN = 15,     /* tournament: candidate sets merged per node, 2..8 (0 = 8) */
+    CDF_PARAM_COUNT = 16
 } cdf_param_t;
 CDF_API cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value);
 CDF_API int cdf_get_param(cdf_handle_t h, cdf_param_t p);

@@ -29,7 +29,7 @@ CDF_INFO_TIMEOUT = -1000  # device info of an LU whose panel exchange ran out of
 UPD = {"fp64": 0, "bf16": 1, "fp16": 2, "fp8e4m3": 3, "e4m3": 3}
 PARAM = {"lu_nb": 0, "chol_nb": 1, "lu_leaf_rows": 2, "mixed_nb": 3, "vbatch_nb": 4, "vbatch_wg_per_cu": 5,
          "gemm_wg_per_cu": 6, "lu_u12": 7, "leaf_wait_us": 8, "test_exchange_fail": 9, "spd_refine": 10,
-         "pcg_max_iter": 11, "gemm_tile": 12}
+         "pcg_max_iter": 11, "gemm_tile": 12, "lu_pivot": 13, "tourn_block": 14, "tourn_fanin": 15}
 REFINE = {0: None, 1: "classical", 2: "pcg"}
 F64, F32 = 0, 1
 

@@ -77,14 +77,17 @@ namespace cdf {
 // so the region stays consistently permuted.  Pivots are written relative to the region's row 0;
 // info values are offset by info_off.
 hipError_t lu_panel(cdf_handle_t h, const LeafArea &la, hipStream_t s, int m, int ncols, double *A, int lda,
-                    int *ipiv, int *info, int c0, int w, int info_off) {
+                    int *ipiv, int *info, int c0, int w, int info_off, bool tourn) {
     if (w <= 32) {
+        if (tourn)
+            return tourn_leaf(h, la, s, m - c0, w, A + c0 + (size_t)c0 * lda, lda, ipiv + c0, c0, info,
+                              info_off + c0, A, m, ncols);
         return lu_leaf(h, la, s, m - c0, w, A + c0 + (size_t)c0 * lda, lda, ipiv + c0, c0, info, info_off + c0,
                        h->params[CDF_PARAM_LU_LEAF_ROWS], A, m, ncols, c0);
     }
     const int n1 = ((w / 2 + 31) / 32) * 32;
     const int n2 = w - n1;
-    CDF_HIP_RET(lu_panel(h, la, s, m, ncols, A, lda, ipiv, info, c0, n1, info_off));
+    CDF_HIP_RET(lu_panel(h, la, s, m, ncols, A, lda, ipiv, info, c0, n1, info_off, tourn));
     double *a11 = A + c0 + (size_t)c0 * lda;
     double *a12 = A + c0 + (size_t)(c0 + n1) * lda;
     double *a21 = A + (c0 + n1) + (size_t)c0 * lda;
@@ -92,7 +95,7 @@ hipError_t lu_panel(cdf_handle_t h, const LeafArea &la, hipStream_t s, int m, in
     const GemmCtx gc = gemm_ctx(h);
     CDF_HIP_RET(trsm_blocked(s, TRSM_LLNU, n1, n2, a11, lda, a12, lda, 64, &gc));
     CDF_HIP_RET(dgemm(s, 0, 0, m - c0 - n1, n2, n1, -1.0, a21, lda, a12, lda, 1.0, a22, lda, false, nullptr, &gc));
-    return lu_panel(h, la, s, m, ncols, A, lda, ipiv, info, c0 + n1, n2, info_off);
+    return lu_panel(h, la, s, m, ncols, A, lda, ipiv, info, c0 + n1, n2, info_off, tourn);
 }
 
 // Blocked right-looking lower Cholesky of the n x n matrix A: potrf of each
@@ -175,7 +178,8 @@ hipError_t u12_and_update(cdf_handle_t h, hipStream_t s, int n, double *A, int l
 hipError_t factor_panel(cdf_handle_t h, hipStream_t s, int n, double *A, int lda, int *ipiv, int *info, int k,
                         int kb, LuWs &ws, int nb) {
     double *R = A + k + (size_t)k * lda;
-    CDF_HIP_RET(cdf::lu_panel(h, ws.leaf, s, n - k, kb, R, lda, ws.ipt, info, 0, kb, k));
+    CDF_HIP_RET(cdf::lu_panel(h, ws.leaf, s, n - k, kb, R, lda, ws.ipt, info, 0, kb, k,
+                              h->params[CDF_PARAM_LU_PIVOT] == 1));
     CDF_HIP_RET(cdf::offset_pivots(s, ws.ipt, ipiv + k, kb, k));
     CDF_HIP_RET(cdf::build_pairs(s, ws.ipt, 0, kb, n - k, ws.pairs));
     // the inverse is needed only while columns remain right of the panel
@@ -533,6 +537,9 @@ cdf_status_t cdf_set_param(cdf_handle_t h, cdf_param_t p, int value) {
     if (p == CDF_PARAM_TEST_EXCHANGE_FAIL && value > 1) return bad(h, 3);
     if (p == CDF_PARAM_SPD_REFINE && value > 2) return bad(h, 3);
     if (p == CDF_PARAM_GEMM_TILE && !(value == 0 || value == 64 || value == 128)) return bad(h, 3);
+    if (p == CDF_PARAM_LU_PIVOT && value > 1) return bad(h, 3);
+    if (p == CDF_PARAM_TOURN_BLOCK && value != 0 && (value < 32 || value > 256)) return bad(h, 3);
+    if (p == CDF_PARAM_TOURN_FANIN && value != 0 && (value < 2 || value > 8)) return bad(h, 3);
     h->params[p] = value;
     return CDF_OK;
 }

@@ -158,8 +158,23 @@ const void *leaf_kernel_r2();
 // Recursive LU panel of columns [c0, c0+w) of the m x ncols region A (rows
 // [c0, m)) on stream s; interchanges are applied to all other columns of the
 // region; pivots are relative to the region's row 0; info offset by info_off.
+// tourn: the leaves choose their pivots by tournament (tourn_leaf).
 hipError_t lu_panel(cdf_handle_t h, const LeafArea &la, hipStream_t s, int m, int ncols, double *A, int lda,
-                    int *ipiv, int *info, int c0, int w, int info_off);
+                    int *ipiv, int *info, int c0, int w, int info_off, bool tourn = false);
+
+// Tournament-pivoting leaf: the same contract as lu_leaf (m x w block at A,
+// w <= 32, pivots ipiv[0..w) region-relative 1-based with row0 added, first
+// zero pivot into *info, interchanges applied to every column of the
+// region), with the pivots chosen by tournament rounds over row blocks of
+// CDF_PARAM_TOURN_BLOCK rows, CDF_PARAM_TOURN_FANIN sets per round.  Its
+// candidate sets and final block live in `la` from kTournOffset on (beyond
+// the exchange area, before the error word).
+constexpr size_t kTournOffset = 320 * 1024;
+constexpr int kTournMaxSets = 512;
+size_t tourn_ws_bytes();
+hipError_t tourn_leaf(cdf_handle_t h, const LeafArea &la, hipStream_t s, int m, int w, double *A, int lda,
+                      int *ipiv, int row0, int *info, int info_base, double *region, int region_rows,
+                      int region_cols);
 
 // Panel-wide interchanges: build (dst, src) pairs of ipiv[k1..k2) (<= 256,
 // region-relative, 1-based) once into `pairs` (pairs_ints() ints), then

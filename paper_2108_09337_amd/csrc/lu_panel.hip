@@ -154,6 +154,11 @@ __global__ __launch_bounds__(256) void apply_pairs_kernel(int ncols, T *__restri
 
 }  // namespace
 
+static_assert(kExchBytes <= cdf::kTournOffset, "tournament area overlaps the exchange");
+static_assert(cdf::kTournOffset + 2 * cdf::kTournMaxSets * 33 * sizeof(int) + 32 * 32 * sizeof(double) <=
+                  cdf::kLeafWsBytes - 256,
+              "tournament area overlaps the error word");
+
 namespace cdf {
 
 LeafArea handle_leaf_area(cdf_handle_t h) { return LeafArea{h->ws, &h->leaf_epoch}; }

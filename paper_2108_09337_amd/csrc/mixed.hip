@@ -696,10 +696,11 @@ hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *i
     // panel of width kb at column k: binary64 copy in P, factored there,
     // pivots to w.ipt (relative) and ipiv (absolute), copied back to W
     const bool inv = h->params[CDF_PARAM_LU_U12] == 0 && w.Li[0] != nullptr;
+    const bool tourn = h->params[CDF_PARAM_LU_PIVOT] == 1;
     auto panel = [&](hipStream_t s, int k, int kb, double *P, int buf) -> hipError_t {
         const int m = n - k;
         CDF_HIP_RET(cdf::convert_s2d(s, m, kb, W + k + (size_t)k * ldw, ldw, P, m, false));
-        CDF_HIP_RET(cdf::lu_panel(h, la, s, m, kb, P, m, w.ipt, info, 0, kb, k));
+        CDF_HIP_RET(cdf::lu_panel(h, la, s, m, kb, P, m, w.ipt, info, 0, kb, k, tourn));
         if (inv && k + kb < n) CDF_HIP_RET(cdf::unit_lower_inverse(s, kb, P, m, w.Li[buf], nb, w.good + buf, &gu));
         hipLaunchKernelGGL(add_offset_kernel, dim3((kb + 255) / 256), dim3(256), 0, s, w.ipt, ipiv + k, kb, k);
         CDF_HIP_RET(hipGetLastError());
