@@ -618,3 +618,90 @@ def io_lower_bound_elems(kind: int, n: float, m: float) -> float:
 def chi_closed_form(x: float) -> float:
     """Largest S2 subcomputation |H| = (X/3)^(3/2) for dominator size X (Sec. 6.1)."""
     return (x / 3.0) ** 1.5
+
+
+# --------------------------------------------------------------------------
+# General I/O lower bound of a DAAP statement or program (Sec. 3 and 4)
+# --------------------------------------------------------------------------
+
+def daap_chi(nvars: int, accesses, weights, x: float):
+    """chi(X) of Sec. 3.2: the largest subcomputation prod_t |D^t| whose
+    dominator set sum_j w_j prod_{t in access j} |D^t| fits in X, every
+    |D^t| >= 1 (continuous relaxation).  ``accesses`` lists, per input
+    access, the indices of its distinct iteration variables; ``weights``
+    the factor of each access (1, or 1/rho_S for the output of a producer
+    S, Corollary of Sec. 4.2).  Solved in logarithms y_t = ln |D^t| (a convex
+    program) with scipy's SLSQP.  Returns (chi, [|D^t|])."""
+    from scipy.optimize import minimize
+
+    a = np.zeros((len(accesses), nvars))
+    for j, vs in enumerate(accesses):
+        for t in vs:
+            a[j, t] = 1.0
+    w = np.asarray(weights, dtype=np.float64)
+    lx = math.log(x)
+
+    def h(y):
+        return float(np.log(np.sum(w * np.exp(a @ y))))
+
+    def hgrad(y):
+        e = w * np.exp(a @ y)
+        return (e / e.sum()) @ a
+
+    y0 = np.zeros(nvars)
+    res = minimize(lambda y: -float(np.sum(y)), y0, jac=lambda y: -np.ones(nvars), method="SLSQP",
+                   bounds=[(0.0, None)] * nvars,
+                   constraints=[{"type": "ineq", "fun": lambda y: lx - h(y), "jac": lambda y: -hgrad(y)}],
+                   options={"ftol": 1e-14, "maxiter": 500})
+    y = np.maximum(res.x, 0.0)
+    return float(math.exp(np.sum(y))), [float(math.exp(v)) for v in y]
+
+
+def daap_statement_bound(nvars: int, accesses, weights, nvertices: float, m: float, u: int = 0) -> dict:
+    """I/O lower bound of one statement (Sec. 3.2): rho = min over X > M of
+    chi(X) / (X - M) (Lemma of Sec. 3, X_0 its argmin), capped at 1/u when
+    every compute vertex has u out-degree-one input predecessors (Lemma of
+    Sec. 3.2); Q >= |V| / rho.  The search runs over ln X (bounded scalar
+    minimization) between the smallest feasible X and 2^40 M."""
+    from scipy.optimize import minimize_scalar
+
+    lo = max(m, float(np.sum(weights))) * (1 + 1e-9)
+    hi = m * 2.0 ** 40
+
+    def rho_of(lx):
+        x = math.exp(lx)
+        return daap_chi(nvars, accesses, weights, x)[0] / (x - m)
+
+    r = minimize_scalar(rho_of, bounds=(math.log(lo), math.log(hi)), method="bounded",
+                        options={"xatol": 1e-10})
+    x0 = math.exp(r.x)
+    chi, tiles = daap_chi(nvars, accesses, weights, x0)
+    rho = chi / (x0 - m)
+    if u > 0:
+        rho = min(rho, 1.0 / u)
+    sizes = [w * math.prod(tiles[t] for t in vs) for vs, w in zip(accesses, weights)]
+    return {"rho": rho, "x0": x0, "chi": chi, "tiles": tiles, "access_sizes": sizes, "q": nvertices / rho}
+
+
+def daap_program_bound(statements, m: float) -> float:
+    """I/O lower bound of a program of several statements (Sec. 4): the sum
+    of the statements' bounds minus, for every input array shared by several
+    statements (Case I), the loads that can be shared: each statement alone
+    loads |A(R_max(X_0))| |V| / |V_max| elements of the array in its optimal
+    schedule, and at least the largest of these loads remain, so the sum
+    minus that maximum is subtracted (for two statements: the minimum).
+    Output reuse (Case II) enters through the access weights.  Each statement
+    is a dict with keys nvars, accesses, weights, nvertices, u and arrays
+    (the array id of each access)."""
+    total = 0.0
+    loads = {}
+    for s in statements:
+        r = daap_statement_bound(s["nvars"], s["accesses"], s["weights"], s["nvertices"], m, s.get("u", 0))
+        total += r["q"]
+        nsub = s["nvertices"] / r["chi"]
+        for arr, size in zip(s["arrays"], r["access_sizes"]):
+            loads.setdefault(arr, []).append(size * nsub)
+    for arr, ls in loads.items():
+        if len(ls) > 1:
+            total -= sum(ls) - max(ls)
+    return total
