@@ -306,6 +306,22 @@ def mixed_section(args, torch, cdf, workloads, h, tuned):
         log(f"mixed {prec}: {t:.3f} s, iters {r['iters']}, resid {r['scaled_resid']:.3f}")
     for prec in ("bf16", "fp16"):
         res[prec]["speedup_vs_fp64"] = round(res["fp64"]["seconds"] / res[prec]["seconds"], 3)
+    # the BF16 solve again with tournament pivoting in the panel leaves
+    h.set_param("lu_pivot", 1)
+    try:
+        cdf.dgesv_mixed("bf16", A, b, X, info, max_iter=30, h=h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = cdf.dgesv_mixed("bf16", A, b, X, info, max_iter=30, h=h)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+    finally:
+        h.set_param("lu_pivot", 0)
+    res["bf16_tournament"] = {"seconds": round(t, 4), "iters": r["iters"], "scaled_resid": round(r["scaled_resid"], 4),
+                              "converged": r["converged"], "info": int(info.item()),
+                              "speedup_vs_fp64": round(res["fp64"]["seconds"] / t, 3),
+                              "speedup_vs_partial_pivoting": round(res["bf16"]["seconds"] / t, 3)}
+    log(f"mixed bf16 tournament: {t:.3f} s, iters {r['iters']}, resid {r['scaled_resid']:.3f}")
     for group in res["params"].values():
         for k in group:
             h.set_param(k, 0)

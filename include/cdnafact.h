@@ -379,6 +379,62 @@ CDF_API cdf_status_t cdf_vbatch_plan_destroy(cdf_vbatch_plan_t plan);
  */
 CDF_API double cdf_io_lower_bound_elems(int kind, double n, double m_elems);
 
+/*
+ * General I/O lower bound of a statement of a disjoint-access affine program
+ * (Sec. 3 and 4), host only.  A statement with loop nest depth l reads m
+ * input accesses; access j is given by the set of distinct iteration
+ * variables that index it (bit t of access_vars[j] for variable t; its
+ * dimension is the number of bits) and its dominator weight (1, or 1/rho_S
+ * when it reads the output of a producer statement S, Sec. 4.2).  u is the
+ * number of out-degree-one input predecessors every compute vertex has
+ * (Sec. 3.2; 0 = none known), nvertices the statement's compute vertices |V|,
+ * array_id[j] names the array of access j (for the program bound).
+ */
+#define CDF_DAAP_MAX_VARS 8
+#define CDF_DAAP_MAX_ACCESSES 8
+typedef struct {
+    int nvars;
+    int naccesses;
+    unsigned access_vars[CDF_DAAP_MAX_ACCESSES];
+    double access_weight[CDF_DAAP_MAX_ACCESSES];
+    int array_id[CDF_DAAP_MAX_ACCESSES];
+    int u;
+    double nvertices;
+} cdf_daap_statement_t;
+
+/*
+ * rho  = min over X > M of chi(X) / (X - M), capped at 1/u (the maximum
+ *        computational intensity), attained at x0 (Sec. 3.2);
+ * chi  = chi(x0), the largest subcomputation whose dominator set has x0
+ *        vertices; tile[t] = |D^t| there (the extents of an I/O-optimal tile);
+ *        access[j] = weighted size of access j there;
+ * q    = nvertices / rho, the lower bound on loads and stores.
+ */
+typedef struct {
+    double rho, x0, chi, q;
+    double tile[CDF_DAAP_MAX_VARS];
+    double access[CDF_DAAP_MAX_ACCESSES];
+} cdf_daap_result_t;
+
+/*
+ * chi(X) = max prod_t D_t s.t. sum_j w_j prod_{t in access j} D_t <= X,
+ * D_t >= 1 (continuous relaxation, Sec. 3.2), and the maximizing D_t in
+ * tile[0..nvars) (tile may be NULL).  CDF_ERR_INVALID_ARG for an invalid
+ * statement (depth or access count out of range, an empty access, a
+ * non-positive weight, a variable that indexes no access) or X not above the
+ * sum of the weights.
+ */
+CDF_API cdf_status_t cdf_daap_chi(const cdf_daap_statement_t *s, double X, double *chi, double *tile);
+/* The statement's bound for a fast memory of M elements (M > 0). */
+CDF_API cdf_status_t cdf_daap_statement_bound(const cdf_daap_statement_t *s, double M, cdf_daap_result_t *r);
+/*
+ * Bound of a program of n statements (Sec. 4): the sum of their bounds minus
+ * the input loads that statements sharing an array (equal array_id) can
+ * share: each statement alone loads access[j] * nvertices / chi elements of
+ * it in its optimal schedule, and at least the largest of these remain.
+ */
+CDF_API cdf_status_t cdf_daap_program_bound(int n, const cdf_daap_statement_t *s, double M, double *q);
+
 /* ------------------------------------------------------- kernel timing */
 
 /*

@@ -50,6 +50,20 @@ class CdfError(RuntimeError):
         super().__init__(msg)
 
 
+DAAP_MAX = 8  # CDF_DAAP_MAX_VARS, CDF_DAAP_MAX_ACCESSES
+
+
+class DaapStatement(ctypes.Structure):
+    _fields_ = [("nvars", ctypes.c_int), ("naccesses", ctypes.c_int),
+                ("access_vars", ctypes.c_uint * DAAP_MAX), ("access_weight", ctypes.c_double * DAAP_MAX),
+                ("array_id", ctypes.c_int * DAAP_MAX), ("u", ctypes.c_int), ("nvertices", ctypes.c_double)]
+
+
+class DaapResult(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("x0", ctypes.c_double), ("chi", ctypes.c_double), ("q", ctypes.c_double),
+                ("tile", ctypes.c_double * DAAP_MAX), ("access", ctypes.c_double * DAAP_MAX)]
+
+
 def lib() -> ctypes.CDLL:
     """Load libcdnafact.so; raises if it has not been built."""
     global _lib
@@ -87,6 +101,10 @@ def lib() -> ctypes.CDLL:
         "cdf_vbatch_run": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "cdf_vbatch_plan_destroy": (_i, [_vp]),
         "cdf_io_lower_bound_elems": (ctypes.c_double, [_i, ctypes.c_double, ctypes.c_double]),
+        "cdf_daap_chi": (_i, [ctypes.POINTER(DaapStatement), ctypes.c_double, _c_double_p, _c_double_p]),
+        "cdf_daap_statement_bound": (_i, [ctypes.POINTER(DaapStatement), ctypes.c_double,
+                                          ctypes.POINTER(DaapResult)]),
+        "cdf_daap_program_bound": (_i, [_i, ctypes.POINTER(DaapStatement), ctypes.c_double, _c_double_p]),
         "cdf_profile_begin": (_i, [_vp]),
         "cdf_profile_end": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_longlong), _c_double_p, _c_double_p, _c_double_p]),
     }
@@ -379,3 +397,53 @@ class VBatchPlan:
 
 def io_lower_bound_elems(kind: int, n: float, m_elems: float) -> float:
     return float(lib().cdf_io_lower_bound_elems(int(kind), float(n), float(m_elems)))
+
+
+def _daap_statement(nvars, accesses, weights=None, nvertices=1.0, u=0, arrays=None) -> DaapStatement:
+    """Marshal a statement: accesses = per input access, the indices of its
+    distinct iteration variables (see cdf_daap_statement_t)."""
+    st = DaapStatement()
+    st.nvars = int(nvars)
+    st.naccesses = len(accesses)
+    if st.naccesses > DAAP_MAX:
+        raise ValueError("too many accesses")
+    for j, vs in enumerate(accesses):
+        st.access_vars[j] = sum(1 << int(t) for t in set(vs))
+        st.access_weight[j] = float(1.0 if weights is None else weights[j])
+        st.array_id[j] = int(j if arrays is None else arrays[j])
+    st.u = int(u)
+    st.nvertices = float(nvertices)
+    return st
+
+
+def daap_chi(nvars, accesses, weights, x: float):
+    """(chi(X), [|D^t|]) of one statement (see cdf_daap_chi)."""
+    st = _daap_statement(nvars, accesses, weights)
+    chi = ctypes.c_double()
+    tile = (ctypes.c_double * DAAP_MAX)()
+    _check("cdf_daap_chi", lib().cdf_daap_chi(ctypes.byref(st), float(x), ctypes.byref(chi), tile), None)
+    return chi.value, list(tile[:nvars])
+
+
+def daap_statement_bound(nvars, accesses, weights, nvertices, m: float, u: int = 0) -> dict:
+    """The statement's I/O bound for fast memory m (see cdf_daap_statement_bound)."""
+    st = _daap_statement(nvars, accesses, weights, nvertices, u)
+    r = DaapResult()
+    _check("cdf_daap_statement_bound", lib().cdf_daap_statement_bound(ctypes.byref(st), float(m), ctypes.byref(r)),
+           None)
+    return {"rho": r.rho, "x0": r.x0, "chi": r.chi, "q": r.q, "tiles": list(r.tile[:nvars]),
+            "access_sizes": list(r.access[:len(accesses)])}
+
+
+def daap_program_bound(statements, m: float) -> float:
+    """Program bound (see cdf_daap_program_bound); statements as dicts with
+    nvars, accesses, weights, nvertices, u and arrays (hashable ids)."""
+    ids = {}
+    arr = (DaapStatement * len(statements))()
+    for i, s in enumerate(statements):
+        arrays = [ids.setdefault(a, len(ids)) for a in s["arrays"]]
+        arr[i] = _daap_statement(s["nvars"], s["accesses"], s["weights"], s["nvertices"], s.get("u", 0), arrays)
+    q = ctypes.c_double()
+    _check("cdf_daap_program_bound", lib().cdf_daap_program_bound(len(statements), arr, float(m), ctypes.byref(q)),
+           None)
+    return q.value
