@@ -449,10 +449,9 @@ def batched_section(args, torch, cdf, workloads, h, tuned):
         p_ptrs = torch.tensor([piv.data_ptr() + i * nmax * 4 for i in range(count)], dtype=torch.int64,
                               device="cuda")
         info = torch.zeros(count, dtype=torch.int32, device="cuda")
-        params = tuned(h, "vbatch", nmax, dtn)
-        plan = cdf.VBatchPlan(sizes, kinds, dt, h)
-        for k in params:
-            h.set_param(k, 0)
+        # the plan takes its launch shape from the tuner's cache itself
+        plan = cdf.VBatchPlan(sizes, kinds, dt, h, tuned=not args.no_tune_cache)
+        params = plan.params
         times = []
         for rep in range(6):
             buf.copy_(src)

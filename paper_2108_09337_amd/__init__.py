@@ -368,14 +368,28 @@ def lowp_update(prec: str, QA, ea, QB, eb, C, k: int, h: Handle | None = None) -
 class VBatchPlan:
     """A planned batch of small factorizations (see cdf_vbatch_plan_create)."""
 
-    def __init__(self, sizes, kinds, dtype=F64, h: Handle | None = None):
+    def __init__(self, sizes, kinds, dtype=F64, h: Handle | None = None, tuned: bool = True):
+        """tuned: take the launch shape from the autotuner's cache entry
+        nearest to the batch's largest order (if the cache has one; the
+        handle's own parameters otherwise)."""
         self.h = h or handle()
         self.sizes = np.ascontiguousarray(sizes, dtype=np.int32)
         self.kinds = np.ascontiguousarray(kinds, dtype=np.int32)
+        saved = {}
+        self.params = {}
+        if tuned and len(self.sizes):
+            from . import tune as _tune
+            names = _tune.SPACES["vbatch"]
+            saved = {k: self.h.get_param(k) for k in names}
+            self.params = _tune.apply(self.h, "vbatch", int(self.sizes.max()), "f64" if dtype == F64 else "f32")
         plan = _vp()
-        st = lib().cdf_vbatch_plan_create(self.h.bind_stream(), len(self.sizes),
-                                          self.sizes.ctypes.data_as(_c_int_p), self.kinds.ctypes.data_as(_c_int_p),
-                                          int(dtype), ctypes.byref(plan))
+        try:
+            st = lib().cdf_vbatch_plan_create(self.h.bind_stream(), len(self.sizes),
+                                              self.sizes.ctypes.data_as(_c_int_p),
+                                              self.kinds.ctypes.data_as(_c_int_p), int(dtype), ctypes.byref(plan))
+        finally:
+            for k, v in saved.items():
+                self.h.set_param(k, v)
         _check("cdf_vbatch_plan_create", st, self.h.ptr)
         self._plan = plan
 

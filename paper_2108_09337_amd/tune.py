@@ -11,11 +11,17 @@ parameters from the cache; the batched plan and the benchmark use it.
 
 Search spaces (the parameters the paper tunes are the block size v and the
 replication depth, Sec. 7.2 and Sec. 8; on one GPU they become the panel
-width, the leaf shape and the batched launch shape):
-  getrf        lu_nb in {256, 384, 512} x lu_leaf_rows in {1, 2} x gemm_wg_per_cu in {4, 5}
-  potrf        chol_nb in {128, 256, 384, 512} x gemm_wg_per_cu in {4, 5}
-  mixed_getrf  mixed_nb in {256, 384, 512} (BF16 update)
-  vbatch       vbatch_nb in {0 (32 where it fits), 16} x vbatch_wg_per_cu in {1, 2}
+width, the leaf shape, the update GEMM's tile and occupancy, how U12 is
+formed, the pivoting of the mixed LU and the batched launch shape):
+  getrf        lu_nb {256, 384, 512}, lu_leaf_rows {1, 2}, gemm_wg_per_cu {4, 5},
+               gemm_tile {64, 128}, lu_u12 {0 (L11^-1 product), 1 (substitution)}
+  potrf        chol_nb {128, 256, 384, 512}, gemm_wg_per_cu {4, 5}, gemm_tile {64, 128}
+  mixed_getrf  mixed_nb {256, 384, 512}, lu_u12 {0, 1},
+               lu_pivot {0 (partial), 1 (tournament)} (BF16 update)
+  vbatch       vbatch_nb {0 (32 where it fits), 16}, vbatch_wg_per_cu {1, 2}
+Spaces of at most 16 points are searched exhaustively; larger ones by
+coordinate descent (each parameter in turn over its values with the others
+at their current best, two sweeps, every point timed at most once).
 """
 from __future__ import annotations
 
@@ -35,11 +41,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(_HERE, "tune_cache.json")
 
 SPACES = {
-    "getrf": {"lu_nb": [256, 384, 512], "lu_leaf_rows": [1, 2], "gemm_wg_per_cu": [4, 5]},
-    "potrf": {"chol_nb": [128, 256, 384, 512], "gemm_wg_per_cu": [4, 5]},
-    "mixed_getrf": {"mixed_nb": [256, 384, 512]},
+    "getrf": {"lu_nb": [256, 384, 512], "lu_leaf_rows": [1, 2], "gemm_wg_per_cu": [4, 5], "gemm_tile": [64, 128],
+              "lu_u12": [0, 1]},
+    "potrf": {"chol_nb": [128, 256, 384, 512], "gemm_wg_per_cu": [4, 5], "gemm_tile": [64, 128]},
+    "mixed_getrf": {"mixed_nb": [256, 384, 512], "lu_u12": [0, 1], "lu_pivot": [0, 1]},
     "vbatch": {"vbatch_nb": [0, 16], "vbatch_wg_per_cu": [1, 2]},
 }
+EXHAUSTIVE_MAX = 16
 
 
 def cache_path() -> str:
@@ -84,11 +92,32 @@ def apply(h: "cdf.Handle", op: str, n: int, dtype: str = "f64", cache: dict | No
     return params
 
 
-def _candidates(op):
-    space = SPACES[op]
+def _search(op, evaluate, spaces=None):
+    """Minimize evaluate(params) over the op's space (exhaustive if small,
+    else coordinate descent); returns the list of (seconds, params) timed."""
+    space = (spaces or SPACES)[op]
     names = sorted(space)
-    for combo in itertools.product(*(space[k] for k in names)):
-        yield dict(zip(names, combo))
+    seen = {}
+
+    def ev(params):
+        k = tuple(params[n] for n in names)
+        if k not in seen:
+            seen[k] = evaluate(dict(params))
+        return seen[k]
+
+    if math.prod(len(space[n]) for n in names) <= EXHAUSTIVE_MAX:
+        for combo in itertools.product(*(space[n] for n in names)):
+            ev(dict(zip(names, combo)))
+    else:
+        best = {n: space[n][0] for n in names}
+        for _ in range(2):
+            for n in names:
+                ts = []
+                for v in space[n]:
+                    cand = dict(best, **{n: v})
+                    ts.append((ev(cand), v))
+                best[n] = min(ts)[1]
+    return [(t, dict(zip(names, k))) for k, t in seen.items()]
 
 
 def _time(fn, reps):
@@ -105,7 +134,7 @@ def _time(fn, reps):
     return best
 
 
-def tune_dense(op: str, n: int, reps: int = 2, log=print) -> dict:
+def tune_dense(op: str, n: int, reps: int = 2, log=print, spaces=None) -> dict:
     import workloads
     h = cdf.handle()
     # inputs drawn on the GPU (same distributions as the host generators)
@@ -113,8 +142,8 @@ def tune_dense(op: str, n: int, reps: int = 2, log=print) -> dict:
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
     ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
     W = cdf.cm_empty(n, n, torch.float32) if op == "mixed_getrf" else None
-    results = []
-    for params in _candidates(op):
+
+    def evaluate(params):
         for k, v in params.items():
             h.set_param(k, v)
 
@@ -128,16 +157,22 @@ def tune_dense(op: str, n: int, reps: int = 2, log=print) -> dict:
             else:
                 cdf.sgetrf_mixed("bf16", state, W, ipiv, info)
 
-        t = _time(run, reps)
-        results.append((t, params))
+        try:
+            t = _time(run, reps)
+        finally:
+            for k in params:
+                h.set_param(k, 0)
+        if int(info.item()) != 0:
+            t = float("inf")  # a failing candidate is never chosen
         log(f"  {op} n={n} {params}: {t * 1e3:.2f} ms")
-        for k in params:
-            h.set_param(k, 0)
+        return t
+
+    results = _search(op, evaluate, spaces)
     t, params = min(results, key=lambda r: r[0])
     return {"params": params, "seconds": t, "n": n, "tried": len(results)}
 
 
-def tune_vbatch(count: int = 4096, dtype: str = "f64", reps: int = 3, log=print) -> dict:
+def tune_vbatch(count: int = 4096, dtype: str = "f64", reps: int = 3, log=print, spaces=None) -> dict:
     import workloads
     sizes = workloads.batch_sizes(count)
     kinds = workloads.batch_kinds(count)
@@ -156,13 +191,15 @@ def tune_vbatch(count: int = 4096, dtype: str = "f64", reps: int = 3, log=print)
     p_ptrs = torch.tensor([piv.data_ptr() + i * nmax * 4 for i in range(count)], dtype=torch.int64, device="cuda")
     info = torch.zeros(count, dtype=torch.int32, device="cuda")
     h = cdf.handle()
-    results = []
-    for params in _candidates("vbatch"):
+
+    def evaluate(params):
         for k, v in params.items():
             h.set_param(k, v)
-        plan = cdf.VBatchPlan(sizes, kinds, dt, h)
-        for k in params:
-            h.set_param(k, 0)
+        try:
+            plan = cdf.VBatchPlan(sizes, kinds, dt, h, tuned=False)
+        finally:
+            for k in params:
+                h.set_param(k, 0)
 
         def run(prepare, state=None):
             if prepare:
@@ -172,8 +209,10 @@ def tune_vbatch(count: int = 4096, dtype: str = "f64", reps: int = 3, log=print)
 
         t = _time(run, reps)
         plan.close()
-        results.append((t, params))
         log(f"  vbatch {dtype} count={count} {params}: {t * 1e3:.3f} ms")
+        return t
+
+    results = _search("vbatch", evaluate, spaces)
     t, params = min(results, key=lambda r: r[0])
     return {"params": params, "seconds": t, "n": int(nmax), "count": count, "tried": len(results)}
 

@@ -1,4 +1,4 @@
-"""Batched small factorizations (one persistent hipGraph launch) against the
+"""Batched small factorizations (one persistent launch) against the
 per-problem CPU oracle (needs an MI355X)."""
 import numpy as np
 import pytest
