@@ -41,6 +41,7 @@
 
 #include "internal.h"
 #include "pairs.h"
+#include "wave.h"
 
 #include <climits>
 
@@ -60,10 +61,6 @@ constexpr size_t kRowWords = 2 * GMAX * LW * 2;  // candidate rows: two tagged w
 constexpr size_t kRowjWords = 2 * LW * 2;        // row j
 constexpr size_t kExchBytes = kTagBytes + (kRowWords + kRowjWords) * sizeof(u64);
 static_assert(kExchBytes <= cdf::kLeafWsBytes, "leaf workspace");
-
-__device__ inline void better(double &bv, int &bi, double ov, int oi) {
-    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-}
 
 __device__ inline void put_tag(u64 *p, u64 v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ inline u64 get_tag(const u64 *p) {
@@ -125,9 +122,11 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
                                                      long long budget_ticks, unsigned max_polls,
                                                      unsigned epoch_skew) {
     constexpr int RT = LT * R;  // rows per workgroup
-    __shared__ double prow[LW], oldj[LW], cand[LW], lrowj[LW];
-    __shared__ double wv[LT / 64], xv[LT / 64];
-    __shared__ int wi[LT / 64], xi[LT / 64], xw[LT / 64];
+    constexpr int NW = LT / 64;
+    __shared__ double prow[LW], oldj[LW], candw[2][NW][LW], lrowj[2][LW];
+    __shared__ u64 wk_s[2][NW];
+    __shared__ unsigned wr_s[2][NW];
+    __shared__ int xi[1];
     __shared__ int spiv[LW];  // region row (1-based) swapped with row rc0 + j
     __shared__ int pdst[MAXPAIRS], psrc[MAXPAIRS];
     __shared__ int s_np;
@@ -139,6 +138,9 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
     const int lane = t & 63, wave = t >> 6;
     const int rbase = g * RT;
     u64 *rowj = rows + kRowWords;
+    // the leaf is the critical path and shares its CUs with the update
+    // GEMM's workgroups: its waves win the instruction arbitration
+    __builtin_amdgcn_s_setprio(3);
 
     // an earlier leaf of this factorization gave up: return at once
     if (t == 0) s_stop = G > 1 ? get_err(err) : 0;
@@ -164,36 +166,46 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
         constexpr int j = decltype(jc)::value;
         if (j >= n || stopped_at >= 0) return;
         const int par = j & 1;
-        // 1. local candidate of column j among rows >= j
-        double bv = -1.0;
-        int bi = INT_MAX;
+        // 1. local candidate of column j among rows >= j: the largest key,
+        //    then the smallest row (a thread's rows ascend with s), by wave
+        //    DPP reductions; each wave's winner writes its row to the wave's
+        //    slot and the owner of row j writes row j (slots by column
+        //    parity), then one barrier and a branch-free choice among the
+        //    waves' (key, row) pairs
+        u64 tk = 0ull;
+        unsigned tr = ~0u;
         cdf::static_for<0, R>([&](auto sc) {
             constexpr int s = decltype(sc)::value;
             const int r = rbase + s * LT + t;
-            if (r < m && r >= j) better(bv, bi, fabs(x[s][j]), r);
+            const u64 k = (r < m && r >= j) ? pivot_key(x[s][j]) : 0ull;
+            if (k > tk) { tk = k; tr = (unsigned)r; }
         });
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double ov = __shfl_xor(bv, off);
-            const int oi = __shfl_xor(bi, off);
-            better(bv, bi, ov, oi);
-        }
-        if (lane == 0) { wv[wave] = bv; wi[wave] = bi; }
-        __syncthreads();
-        double v = wv[0];
-        int p = wi[0];
-#pragma unroll
-        for (int w = 1; w < LT / 64; ++w) better(v, p, wv[w], wi[w]);
-        // the candidate's row and row j go to LDS, each written by its owner
+        unsigned wrow;
+        const u64 wkey = wave_best(tk, tr, &wrow);
         cdf::static_for<0, R>([&](auto sc) {
             constexpr int s = decltype(sc)::value;
             const int r = rbase + s * LT + t;
-            if (r == p)
-                cdf::static_for<0, LW>([&](auto cc) { cand[decltype(cc)::value] = x[s][decltype(cc)::value]; });
+            if (wkey != 0ull && (unsigned)r == wrow)
+                cdf::static_for<0, LW>([&](auto cc) { candw[par][wave][decltype(cc)::value] = x[s][decltype(cc)::value]; });
             if (r == j)
-                cdf::static_for<0, LW>([&](auto cc) { lrowj[decltype(cc)::value] = x[s][decltype(cc)::value]; });
+                cdf::static_for<0, LW>([&](auto cc) { lrowj[par][decltype(cc)::value] = x[s][decltype(cc)::value]; });
         });
+        if (lane == 0) { wk_s[par][wave] = wkey; wr_s[par][wave] = wrow; }
         __syncthreads();
+        u64 v = wk_s[par][0];
+        unsigned pr_u = wr_s[par][0];
+        int wsel = 0;
+#pragma unroll
+        for (int q = 1; q < NW; ++q) {
+            const u64 kq = wk_s[par][q];
+            const unsigned rq = wr_s[par][q];
+            const bool b = kq > v || (kq == v && rq < pr_u);
+            v = b ? kq : v;
+            pr_u = b ? rq : pr_u;
+            wsel = b ? q : wsel;
+        }
+        int p = v != 0ull ? (int)pr_u : INT_MAX;
+        const double *cand = candw[par][wsel];
         if (G > 1) {
             const u64 e = (u64)(epoch0 + (unsigned)j) << 32;
             // the epoch waited for: e, except under the test setting that
@@ -202,18 +214,20 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
             if (wave == 0) {
                 // publish rows and tags, all words tagged with the epoch
                 if (p != INT_MAX && t < n) put_pair(rows + (((size_t)par * GMAX + g) * LW + t) * 2, cand[t], e);
-                if (j >= rbase && j < rbase + RT && t < n) put_pair(rowj + ((size_t)par * LW + t) * 2, lrowj[t], e);
+                if (j >= rbase && j < rbase + RT && t < n)
+                    put_pair(rowj + ((size_t)par * LW + t) * 2, lrowj[par][t], e);
                 if (t < 3) {
-                    const u64 bits = (u64)__double_as_longlong(v);
-                    const u64 half = t == 0 ? bits >> 32 : (t == 1 ? bits & 0xffffffffull : (u64)(unsigned)p);
+                    // the candidate's key in two halves, then its row
+                    const u64 half = t == 0 ? v >> 32 : (t == 1 ? v & 0xffffffffull : (u64)(unsigned)p);
                     put_tag(tags + ((size_t)par * GMAX + g) * kTagWords + t, e | half);
                 }
             }
             // 2. wave 0 polls every workgroup's tags (up to GMAX / 64 per lane,
             //    pausing between rounds so that the polling leaves the memory
             //    path to kernels running beside the leaf); waves 1.. wait at
-            //    the barrier.  The winner is the largest |a|, then the
-            //    smallest row: a total order, so the reduction order is free.
+            //    the barrier.  The winner is the largest key, then the
+            //    smallest row (DPP reductions): a total order, so the
+            //    reduction order is free.
             if (wave == 0) {
                 constexpr int QPL = GMAX / 64;
                 u64 w[QPL][3];
@@ -248,30 +262,24 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
                         atomicExch(info, CDF_INFO_TIMEOUT);
                     }
                 }
-                double cv = -1.0;
-                int ci = INT_MAX, cw = 0;
+                u64 ck = 0ull;
+                unsigned cr = ~0u;
 #pragma unroll
                 for (int i = 0; i < QPL; ++i) {
                     const int q = lane + 64 * i;
                     if (q < G) {
-                        const double ov = __longlong_as_double((long long)((w[i][0] << 32) | (w[i][1] & 0xffffffffull)));
-                        const int oi = (int)(unsigned)(w[i][2] & 0xffffffffull);
-                        if (ov > cv || (ov == cv && oi < ci)) { cv = ov; ci = oi; cw = q; }
+                        const u64 ok_ = ((w[i][0] & 0xffffffffull) << 32) | (w[i][1] & 0xffffffffull);
+                        const unsigned orow = (unsigned)(w[i][2] & 0xffffffffull);
+                        if (ok_ > ck || (ok_ == ck && orow < cr)) { ck = ok_; cr = orow; }
                     }
                 }
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) {
-                    const double ov = __shfl_xor(cv, off);
-                    const int oi = __shfl_xor(ci, off);
-                    const int ow = __shfl_xor(cw, off);
-                    if (ov > cv || (ov == cv && oi < ci)) { cv = ov; ci = oi; cw = ow; }
-                }
-                if (lane == 0) { xv[0] = cv; xi[0] = ci; xw[0] = cw; }
+                unsigned crow;
+                const u64 ckey = wave_best(ck, cr, &crow);
+                if (lane == 0) xi[0] = ckey != 0ull ? (int)crow : INT_MAX;
             }
             __syncthreads();
-            v = xv[0];
             p = xi[0];
-            const int win = xw[0];
+            const int win = p == INT_MAX ? 0 : p / RT;  // the workgroup that owns row p
             // 3. winning row and current row j
             if (t < n && !s_stop) {
                 // row j is always published (by its owner); a candidate row
@@ -296,8 +304,8 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
                 }
             }
         } else if (t < n) {
-            oldj[t] = lrowj[t];
-            prow[t] = p == INT_MAX ? lrowj[t] : cand[t];
+            oldj[t] = lrowj[par][t];
+            prow[t] = p == INT_MAX ? lrowj[par][t] : cand[t];
         }
         if (p == INT_MAX) p = j;  // no ordered candidate (NaN column): no interchange
         __syncthreads();

@@ -20,6 +20,7 @@
 // leaf has no grid-wide wait.  Zero pivots: recorded in info, the column's
 // multipliers left unscaled, as the partial-pivoting leaf does.
 #include "internal.h"
+#include "wave.h"
 
 #include <climits>
 
@@ -29,33 +30,6 @@ constexpr int TW = 32;   // leaf width
 constexpr int TN = 256;  // threads per node workgroup (rows per node, at most)
 constexpr int TNW = TN / 64;
 constexpr int SET = 1 + TW;  // a candidate set: count, then row ids
-typedef unsigned long long u64;
-
-// Pivot key: 1 + the bit pattern of |a| (non-negative doubles order like
-// their patterns), 0 for a row that takes no part and for NaN.
-__device__ inline u64 tkey(double a) { return a == a ? (u64)__double_as_longlong(fabs(a)) + 1ull : 0ull; }
-
-template <int CTRL, int ROW_MASK>
-__device__ inline u64 tdpp_max(u64 v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROW_MASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROW_MASK, 0xf, false);
-    const u64 o = ((u64)(unsigned)hi << 32) | (unsigned)lo;
-    return o > v ? o : v;
-}
-
-// Largest key of the wave, in every lane (row shifts 1, 2, 4, 8, then the
-// row broadcasts 15 and 31 bring the four row maxima to lane 63).
-__device__ inline u64 twave_max(u64 v) {
-    v = tdpp_max<0x111, 0xf>(v);
-    v = tdpp_max<0x112, 0xf>(v);
-    v = tdpp_max<0x114, 0xf>(v);
-    v = tdpp_max<0x118, 0xf>(v);
-    v = tdpp_max<0x142, 0xa>(v);
-    v = tdpp_max<0x143, 0xc>(v);
-    const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, 63);
-    const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
-    return ((u64)hi << 32) | lo;
-}
 
 struct __align__(16) TSlot {
     u64 key;
@@ -123,8 +97,8 @@ __global__ __launch_bounds__(TN) void tourn_node_kernel(int M, int w, const doub
         if (j >= k) return;
         const int par = j & 1;
         if (wact) {
-            const u64 key = (t >= j && t < rows) ? tkey(x[j]) : 0ull;
-            const u64 wk = twave_max(key);
+            const u64 key = (t >= j && t < rows) ? pivot_key(x[j]) : 0ull;
+            const u64 wk = wave_max_key(key);
             const u64 hit = __ballot(key == wk && wk != 0ull);
             const int bi = hit ? (t & ~63) + __builtin_ctzll(hit) : INT_MAX;
             if (t == bi) {

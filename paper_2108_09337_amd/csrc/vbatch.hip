@@ -16,6 +16,7 @@
 // Every workgroup exits once the counter passes the batch size.
 #include "internal.h"
 #include "pairs.h"
+#include "wave.h"
 
 #include <algorithm>
 #include <climits>
@@ -214,39 +215,6 @@ struct __align__(16) Slot {
     u64 key;
     int idx, pad;
 };
-
-// Pivot key of a candidate: 1 + the bit pattern of |a| (the patterns of
-// non-negative floating-point values order like the values), 0 for a row
-// that takes no part and for NaN (which never wins).
-__device__ inline u64 pivot_key(double a) {
-    return a == a ? (u64)__double_as_longlong(fabs(a)) + 1ull : 0ull;
-}
-__device__ inline u64 pivot_key(float a) { return a == a ? (u64)__float_as_uint(fabsf(a)) + 1ull : 0ull; }
-
-// One step of the wave maximum: v = max(v, v of the lane the DPP control
-// selects); lanes without a source see 0.
-template <int CTRL, int ROW_MASK>
-__device__ inline u64 dpp_max_step(u64 v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROW_MASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROW_MASK, 0xf, false);
-    const u64 o = ((u64)(unsigned)hi << 32) | (unsigned)lo;
-    return o > v ? o : v;
-}
-
-// Largest key over the wave, in every lane: row shifts by 1, 2, 4, 8 leave
-// each row's maximum in its lane 15, two row broadcasts bring all four to
-// lane 63 (DPP data movement: no LDS round trips).
-__device__ inline u64 wave_max_key(u64 v) {
-    v = dpp_max_step<0x111, 0xf>(v);  // row_shr:1
-    v = dpp_max_step<0x112, 0xf>(v);  // row_shr:2
-    v = dpp_max_step<0x114, 0xf>(v);  // row_shr:4
-    v = dpp_max_step<0x118, 0xf>(v);  // row_shr:8
-    v = dpp_max_step<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-    v = dpp_max_step<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-    const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, 63);
-    const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
-    return ((u64)hi << 32) | lo;
-}
 
 // LU of the panel [k0, k0 + kb) over rows [k0, n), m = n - k0 <= NT rows:
 // thread t owns panel row t, its kb columns in registers (the column loop is
