@@ -96,15 +96,24 @@ __device__ inline void put_pair(u64 *p, double v, u64 e) {
     put_tag(p, e | (bits >> 32));
     put_tag(p + 1, e | (bits & 0xffffffffull));
 }
-// Reads the double at p once both words carry epoch e; false if the wait
-// ran out of budget first (*v is then unspecified).
-__device__ inline bool get_pair(const u64 *p, u64 e, double *v, WaitBudget &wb, const int *err, bool *timed_out) {
+// Reads the doubles at pa and (unless null) pb once all their words carry
+// epoch e, polling both in the same rounds; false if the wait ran out of
+// budget first.
+__device__ inline bool get_two(const u64 *pa, const u64 *pb, u64 e, double *va, double *vb, WaitBudget &wb,
+                               const int *err, bool *timed_out) {
     for (;;) {
         const int ev = get_err(err);
         const long long now = wall_clock64();
-        const u64 w0 = get_tag(p), w1 = get_tag(p + 1);
-        if ((w0 & ~0xffffffffull) == e && (w1 & ~0xffffffffull) == e) {
-            *v = __longlong_as_double((long long)((w0 << 32) | (w1 & 0xffffffffull)));
+        const u64 a0 = get_tag(pa), a1 = get_tag(pa + 1);
+        u64 b0 = e, b1 = e;
+        if (pb) {
+            b0 = get_tag(pb);
+            b1 = get_tag(pb + 1);
+        }
+        if ((a0 & ~0xffffffffull) == e && (a1 & ~0xffffffffull) == e && (b0 & ~0xffffffffull) == e &&
+            (b1 & ~0xffffffffull) == e) {
+            *va = __longlong_as_double((long long)((a0 << 32) | (a1 & 0xffffffffull)));
+            if (pb) *vb = __longlong_as_double((long long)((b0 << 32) | (b1 & 0xffffffffull)));
             return true;
         }
         if (wb.spent(ev, now, timed_out)) return false;
@@ -287,12 +296,11 @@ __global__ __launch_bounds__(LT) void lu_leaf_kernel(int m, int n, double *__res
                 WaitBudget wb(budget_ticks, max_polls);
                 bool timed_out = false;
                 double oj = 0.0, pr = 0.0;
-                bool ok = get_pair(rowj + ((size_t)par * LW + t) * 2, ew, &oj, wb, err, &timed_out);
-                if (ok) {
-                    pr = oj;
-                    if (p != INT_MAX)
-                        ok = get_pair(rows + (((size_t)par * GMAX + win) * LW + t) * 2, ew, &pr, wb, err, &timed_out);
-                }
+                // both rows in the same rounds (one round trip, not two)
+                const bool ok = get_two(rowj + ((size_t)par * LW + t) * 2,
+                                        p != INT_MAX ? rows + (((size_t)par * GMAX + win) * LW + t) * 2 : nullptr,
+                                        ew, &oj, &pr, wb, err, &timed_out);
+                if (p == INT_MAX) pr = oj;
                 oldj[t] = oj;
                 prow[t] = pr;
                 if (!ok) {
