@@ -17,39 +17,33 @@ __device__ inline u64 pivot_key(double a) {
 }
 __device__ inline u64 pivot_key(float a) { return a == a ? (u64)__float_as_uint(fabsf(a)) + 1ull : 0ull; }
 
-// One step of a wave maximum of 64-bit keys: v = max(v, v of the lane the
-// DPP control selects); lanes without a source see 0.
+// One step of a wave maximum / minimum of 32-bit values: v = max(v, v of
+// the lane the DPP control selects) (min likewise); lanes without a source
+// see the operation's identity.  The compiler folds each step into one
+// v_max_u32 / v_min_u32 with a DPP source.
 template <int CTRL, int ROW_MASK>
-__device__ inline u64 dpp_max_step(u64 v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROW_MASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROW_MASK, 0xf, false);
-    const u64 o = ((u64)(unsigned)hi << 32) | (unsigned)lo;
+__device__ inline unsigned dpp_max_step(unsigned v) {
+    const unsigned o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
     return o > v ? o : v;
 }
-
-// The same for a minimum of 32-bit values; lanes without a source see ~0.
 template <int CTRL, int ROW_MASK>
 __device__ inline unsigned dpp_min_step(unsigned v) {
     const unsigned o = (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, CTRL, ROW_MASK, 0xf, false);
     return o < v ? o : v;
 }
 
-// Largest key over the wave, in every lane: row shifts by 1, 2, 4, 8 leave
-// each row's maximum in its lane 15, two row broadcasts bring all four to
-// lane 63, which is read back.
-__device__ inline u64 wave_max_key(u64 v) {
+// Largest / smallest value over the wave, in every lane: row shifts by 1, 2,
+// 4, 8 leave each row's result in its lane 15, two row broadcasts bring all
+// four to lane 63, which is read back.
+__device__ inline unsigned wave_max_u32(unsigned v) {
     v = dpp_max_step<0x111, 0xf>(v);  // row_shr:1
     v = dpp_max_step<0x112, 0xf>(v);  // row_shr:2
     v = dpp_max_step<0x114, 0xf>(v);  // row_shr:4
     v = dpp_max_step<0x118, 0xf>(v);  // row_shr:8
     v = dpp_max_step<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
     v = dpp_max_step<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-    const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, 63);
-    const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
-    return ((u64)hi << 32) | lo;
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
-
-// Smallest value over the wave, in every lane.
 __device__ inline unsigned wave_min_u32(unsigned v) {
     v = dpp_min_step<0x111, 0xf>(v);
     v = dpp_min_step<0x112, 0xf>(v);
@@ -58,6 +52,16 @@ __device__ inline unsigned wave_min_u32(unsigned v) {
     v = dpp_min_step<0x142, 0xa>(v);
     v = dpp_min_step<0x143, 0xc>(v);
     return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Largest 64-bit key over the wave, in every lane: the largest high half,
+// then the largest low half among the lanes that hold it (two passes of
+// single-instruction 32-bit steps).
+__device__ inline u64 wave_max_key(u64 key) {
+    const unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
+    const unsigned mh = wave_max_u32(hi);
+    const unsigned ml = wave_max_u32(hi == mh ? lo : 0u);
+    return ((u64)mh << 32) | ml;
 }
 
 // The wave's best (key, row): the largest key, then the smallest row among
