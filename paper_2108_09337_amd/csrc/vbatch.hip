@@ -152,7 +152,7 @@ __device__ __attribute__((always_inline)) void lds_update(G<T> *C, int ldc, int 
         // clamped to element 0 and zeroes what lies outside.
         auto steps = [&](auto edge_tag) {
             constexpr bool EDGE = decltype(edge_tag)::value;
-#pragma unroll
+#pragma unroll 2
             for (int k0 = 0; k0 < NB; k0 += 4) {
                 const int kk = k0 + lk;
                 T a[2], bb[2];
@@ -385,31 +385,77 @@ __device__ __attribute__((always_inline)) void lu_one(int n, G<T> *A, int lda, G
             __syncthreads();
         }
         const int rest = n - k0 - kb;
-        // U12 = L11^-1 A12 (unit lower), one column per thread, in registers
-        for (int c = t; c < rest; c += NT) {
-            T x[NB];
-            G<T> *col = A + k0 + (size_t)(k0 + kb + c) * lda;
-#pragma unroll
-            for (int i = 0; i < NB; ++i) x[i] = i < kb ? col[i] : T(0);
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-#pragma unroll
-                for (int i = j + 1; i < NB; ++i)
-                    if (i < kb) x[i] = fma(-P[(size_t)j * m + i], x[j], x[i]);
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-                if (i < kb) col[i] = x[i];
+        if (rest <= 0) continue;  // the last panel (then kb may be < NB; otherwise kb == NB)
+        // L11^-1 (unit lower) in LDS by rank-1 steps (no register arrays:
+        // the kernel's registers are spoken for), in the U12 chunk's area:
+        // Y = I, then for k = 0.., Y(i, j) -= L(i, k) Y(k, j) for i > k >= j
+        // (row k of Y is final by step k).  Then written over L11 in the
+        // panel's LDS copy (L21 below it is what the update reads):
+        // Linv(i, j) = P[j * m + i].  Accepted if no entry exceeds 16 in
+        // magnitude; otherwise U12 is solved by substitution with L11 from A.
+        __shared__ int s_bad;
+        T *Y = Uc;  // NB x NB, row-major
+        for (int e = t; e < NB * NB; e += NT) Y[e] = (e / NB == e % NB) ? T(1) : T(0);
+        if (t == 0) s_bad = 0;
+        __syncthreads();
+        for (int k = 0; k < NB - 1; ++k) {
+            const int rows = NB - 1 - k, cols_k = k + 1;  // i in (k, NB), j in [0, k]
+            for (int e = t; e < rows * cols_k; e += NT) {
+                const int i = k + 1 + e / cols_k, j = e % cols_k;
+                Y[i * NB + j] = fma(-P[(size_t)k * m + i], Y[k * NB + j], Y[i * NB + j]);
+            }
+            __syncthreads();
+        }
+        for (int e = t; e < NB * NB; e += NT) {
+            const int i = e / NB, j = e % NB;
+            const T v = Y[e];
+            P[(size_t)j * m + i] = v;
+            if (!(tabs(v) <= T(16))) s_bad = 1;
         }
         __syncthreads();
+        const bool good = s_bad == 0;
         for (int cb = 0; cb < rest; cb += UC) {
             const int cols = min(UC, rest - cb);
-            for (int e = t; e < kb * cols; e += NT) {
-                const int i = e % kb, c = e / kb;
+            for (int e = t; e < NB * cols; e += NT) {
+                const int i = e % NB, c = e / NB;
                 Uc[(size_t)i * UC + c] = A[(size_t)(k0 + i) + (size_t)(k0 + kb + cb + c) * lda];
             }
             __syncthreads();
+            // U12 chunk = L11^-1 A12 chunk in LDS: the product (every element
+            // read before any is written), or substitution, one column per
+            // thread
+            if (good) {
+                constexpr int PE = NB * UC / NT;
+                T u[PE];
+#pragma unroll
+                for (int r = 0; r < PE; ++r) {
+                    const int e = t + NT * r, c = e % UC, i = e / UC;
+                    T acc = T(0);
+                    if (c < cols)
+                        for (int k = 0; k <= i; ++k) acc = fma(P[(size_t)k * m + i], Uc[(size_t)k * UC + c], acc);
+                    u[r] = acc;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < PE; ++r) {
+                    const int e = t + NT * r, c = e % UC, i = e / UC;
+                    if (c < cols) Uc[(size_t)i * UC + c] = u[r];
+                }
+            } else if (t < cols) {
+                for (int i = 1; i < NB; ++i) {
+                    T acc = Uc[(size_t)i * UC + t];
+                    for (int k = 0; k < i; ++k)
+                        acc = fma(-A[(size_t)(k0 + i) + (size_t)(k0 + k) * lda], Uc[(size_t)k * UC + t], acc);
+                    Uc[(size_t)i * UC + t] = acc;
+                }
+            }
+            __syncthreads();
+            for (int e = t; e < NB * cols; e += NT) {
+                const int i = e % NB, c = e / NB;
+                A[(size_t)(k0 + i) + (size_t)(k0 + kb + cb + c) * lda] = Uc[(size_t)i * UC + c];
+            }
             lds_update<T, NB>(A + (k0 + kb) + (size_t)(k0 + kb + cb) * lda, lda, rest, cols, kb, P + kb, m, Uc, UC, false,
-                          0);
+                              0);
             __syncthreads();
         }
     }
