@@ -239,7 +239,11 @@ __device__ __attribute__((always_inline)) int lu_panel_regs(int m, int kb, G<T> 
     T x[NB];
     cdf::static_for<0, NB>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        x[c] = (t < m && c < kb) ? A[(size_t)(k0 + t) + (size_t)(k0 + c) * lda] : T(0);
+        // every load issued (out-of-range ones read the panel's first entry
+        // and are discarded): no load sits in a branch
+        const bool ok = t < m && c < kb;
+        const T v = A[ok ? (size_t)(k0 + t) + (size_t)(k0 + c) * lda : (size_t)k0 + (size_t)k0 * lda];
+        x[c] = ok ? v : T(0);
     });
     cdf::static_for<0, NB>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
@@ -477,7 +481,9 @@ __device__ __attribute__((always_inline)) bool chol_panel_regs(int m, int kb, G<
     T x[NB];
     cdf::static_for<0, NB>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        x[c] = (t < m && c < kb && c <= t) ? A[(size_t)(k0 + t) + (size_t)(k0 + c) * lda] : T(0);
+        const bool ok = t < m && c < kb && c <= t;
+        const T v = A[ok ? (size_t)(k0 + t) + (size_t)(k0 + c) * lda : (size_t)k0 + (size_t)k0 * lda];
+        x[c] = ok ? v : T(0);
     });
     bool ok = true;
     // waves past the panel's last row only keep the barriers (rows j and
