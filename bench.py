@@ -155,11 +155,21 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
             S.copy_(S0)
         torch.cuda.synchronize()
 
+    def use(params, other):
+        # the two operations share handle parameters (the update GEMM's tile
+        # and occupancy): each runs with its own tuned values
+        for k in other:
+            h.set_param(k, 0)
+        for k, v in params.items():
+            h.set_param(k, v)
+
     def step(ev):
+        use(lu_params, ch_params)
         ev[0].record()
         cdf.dgetrf(A, ipiv, info_lu)
         ev[1].record()
         if S is not None:
+            use(ch_params, lu_params)
             cdf.dpotrf(S, info_ch)
         ev[2].record()
 
@@ -196,16 +206,17 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
     value = (flops_lu + flops_ch) / (ms * 1e-3) / 1e12
     log(f"ms/step {ms:.1f}  LU {flops_lu / t_lu / 1e12:.2f} TF  Chol {flops_ch / max(t_ch, 1e-12) / 1e12:.2f} TF")
 
+    use(lu_params, ch_params)  # the LU's values for what follows (the block size below)
     # dominant kernel: the FP64 update GEMM (Schur-complement updates only;
     # the products forming U12 = L11^-1 A12 are filed apart), every launch of
     # it inside the first timed LU step
-    lu_nb = h.get_param("lu_nb") or 512
+    lu_nb = h.get_param("lu_nb") or (512 if n >= 16384 else 256)  # the library's default otherwise
     launches = max(prof_nn["launches"], 1)
     avg = prof_nn["total_ms"] * 1e-3 / launches
     fpl = prof_nn["flops"] / launches
     bpl = prof_nn.get("bytes", 0.0) / launches
     achieved = fpl / avg / 1e12 if avg > 0 else None
-    traffic = traffic_per_launch(n, h.get_param("lu_nb") or 512)
+    traffic = traffic_per_launch(n, lu_nb)
     roofline = {"bound": "mfma", "achieved": None if achieved is None else round(achieved, 3), "peak": FP64_PEAK,
                 "unit": "TFLOP/s", "frac": None if achieved is None else round(achieved / FP64_PEAK, 4),
                 "traffic": traffic,
@@ -236,7 +247,8 @@ def fp64_section(args, torch, cdf, workloads, h, tuned):
         assert parity["lu_backward_error"] <= 10.0 and parity.get("chol_backward_error", 0.0) <= 10.0
         torch.cuda.empty_cache()
     out = {"value": value, "ms": ms, "t_lu": t_lu, "t_ch": t_ch, "flops_lu": flops_lu, "flops_ch": flops_ch,
-           "roofline": roofline, "lu_nb": lu_nb, "chol_nb": h.get_param("chol_nb") or 128,
+           "roofline": roofline, "lu_nb": lu_nb,
+           "chol_nb": ch_params.get("chol_nb") or (512 if n >= 16384 else 128),  # the library's default otherwise
            "params": {"getrf": lu_params, "potrf": ch_params}, "parity": parity,
            "lu_result": A, "ipiv": ipiv.cpu().numpy(), "chol_result": S}
     for k in list(lu_params) + list(ch_params):
@@ -293,8 +305,18 @@ def mixed_section(args, torch, cdf, workloads, h, tuned):
     b = workloads.rhs_uniform_torch(n)
     X = torch.empty(n, dtype=torch.float64, device="cuda")
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
-    res = {"n": n, "nrhs": 1, "params": {"fp64": tuned(h, "getrf", n), "mixed": tuned(h, "mixed_getrf", n)}}
+    p64 = tuned(h, "getrf", n)
+    pmx = tuned(h, "mixed_getrf", n)
+    res = {"n": n, "nrhs": 1, "params": {"fp64": p64, "mixed": pmx}}
+
+    def use(params, other):  # the two LUs share some handle parameters
+        for k in other:
+            h.set_param(k, 0)
+        for k, v in params.items():
+            h.set_param(k, v)
+
     for prec in ("fp64", "bf16", "fp16"):
+        use(p64, pmx) if prec == "fp64" else use(pmx, p64)
         cdf.dgesv_mixed(prec, A, b, X, info, max_iter=30, h=h)  # warm-up (also allocates the workspace)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
