@@ -15,7 +15,8 @@ width, the leaf shape, the update GEMM's tile and occupancy, how U12 is
 formed, the pivoting of the mixed LU and the batched launch shape):
   getrf        lu_nb {256, 384, 512}, lu_leaf_rows {1, 2}, gemm_wg_per_cu {4, 5},
                gemm_tile {64, 128}, lu_u12 {0 (L11^-1 product), 1 (substitution)}
-  potrf        chol_nb {128, 256, 384, 512}, gemm_wg_per_cu {4, 5}, gemm_tile {64, 128}
+  potrf        chol_nb {128, 256, 384, 512}, gemm_wg_per_cu {4, 5} (its products are A B^T
+               forms, which have no 128 x 128 variant)
   mixed_getrf  mixed_nb {256, 384, 512}, lu_u12 {0, 1},
                lu_pivot {0 (partial), 1 (tournament)} (BF16 update)
   vbatch       vbatch_nb {0 (32 where it fits), 16}, vbatch_wg_per_cu {1, 2}
@@ -43,7 +44,7 @@ DEFAULT_CACHE = os.path.join(_HERE, "tune_cache.json")
 SPACES = {
     "getrf": {"lu_nb": [256, 384, 512], "lu_leaf_rows": [1, 2], "gemm_wg_per_cu": [4, 5], "gemm_tile": [64, 128],
               "lu_u12": [0, 1]},
-    "potrf": {"chol_nb": [128, 256, 384, 512], "gemm_wg_per_cu": [4, 5], "gemm_tile": [64, 128]},
+    "potrf": {"chol_nb": [128, 256, 384, 512], "gemm_wg_per_cu": [4, 5]},
     "mixed_getrf": {"mixed_nb": [256, 384, 512], "lu_u12": [0, 1], "lu_pivot": [0, 1]},
     "vbatch": {"vbatch_nb": [0, 16], "vbatch_wg_per_cu": [1, 2]},
 }

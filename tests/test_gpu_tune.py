@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 SMALL = {  # reduced spaces: every dimension still searched
     "getrf": {"lu_nb": [128, 256], "lu_leaf_rows": [1, 2], "gemm_wg_per_cu": [4, 5], "gemm_tile": [64, 128],
               "lu_u12": [0, 1]},
-    "potrf": {"chol_nb": [128, 256], "gemm_wg_per_cu": [4], "gemm_tile": [64, 128]},
+    "potrf": {"chol_nb": [128, 256], "gemm_wg_per_cu": [4, 5]},
     "mixed_getrf": {"mixed_nb": [256], "lu_u12": [0, 1], "lu_pivot": [0, 1]},
     "vbatch": {"vbatch_nb": [0, 16], "vbatch_wg_per_cu": [1, 2]},
 }
