@@ -128,7 +128,9 @@ typedef enum {
                                        pivoting (Sec. 7.3): every 32-column leaf of a panel picks its
                                        pivots in rounds of local LUs over row blocks, a different but
                                        equally valid row order (|L| may exceed 1) */
-    CDF_PARAM_TOURN_BLOCK = 14,     /* tournament: rows per first-round block, 32..256 (0 = 256) */
+    CDF_PARAM_TOURN_BLOCK = 14,     /* tournament: rows per first-round block, 32..256 (0 = 256); raised
+                                       where a leaf has more than 512 such blocks; tournament pivoting
+                                       needs n <= 131072 (512 blocks of 256 rows) */
     CDF_PARAM_TOURN_FANIN = 15,     /* tournament: candidate sets merged per node, 2..8 (0 = 8) */
     CDF_PARAM_COUNT = 16
 } cdf_param_t;

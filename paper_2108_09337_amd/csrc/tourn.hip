@@ -246,8 +246,11 @@ hipError_t tourn_leaf(cdf_handle_t h, const LeafArea &la, hipStream_t s, int m, 
     int block = h->params[CDF_PARAM_TOURN_BLOCK] > 0 ? h->params[CDF_PARAM_TOURN_BLOCK] : TN;
     int fanin = h->params[CDF_PARAM_TOURN_FANIN] > 0 ? h->params[CDF_PARAM_TOURN_FANIN] : TN / TW;
     if (block < TW || block > TN || fanin < 2 || fanin * TW > TN) return hipErrorInvalidValue;
+    // at most kTournMaxSets first-round blocks: larger blocks where the leaf
+    // has more rows than that many blocks of the requested size hold
+    if ((m + block - 1) / block > kTournMaxSets) block = (((m + kTournMaxSets - 1) / kTournMaxSets + TW - 1) / TW) * TW;
     const int G0 = (m + block - 1) / block;
-    if (G0 > kTournMaxSets) return hipErrorInvalidValue;
+    if (block > TN || G0 > kTournMaxSets) return hipErrorInvalidValue;  // more than 131072 rows
     char *base = static_cast<char *>(la.base) + kTournOffset;
     int *sets[2] = {reinterpret_cast<int *>(base), reinterpret_cast<int *>(base) + kTournMaxSets * SET};
     double *F = reinterpret_cast<double *>(base + 2 * (size_t)kTournMaxSets * SET * sizeof(int));
