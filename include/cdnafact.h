@@ -97,7 +97,7 @@ typedef enum {
     CDF_PARAM_CHOL_NB = 1,       /* Cholesky outer block width (multiple of 32, <= 512) */
     CDF_PARAM_LU_LEAF_ROWS = 2,  /* rows per thread in the LU panel leaf (1 or 2) */
     CDF_PARAM_MIXED_NB = 3,      /* block width of the mixed-precision factorizations (multiple of 32,
-                                    <= 512; the Cholesky uses at most 256) */
+                                    <= 512; look-ahead where it is a multiple of 128) */
     CDF_PARAM_VBATCH_NB = 4,     /* batched panel width: 0 = 32 where it fits in LDS, 16 = always 16 */
     CDF_PARAM_VBATCH_WG_PER_CU = 5, /* batched persistent workgroups per CU (1 or 2; 0 = 1) */
     CDF_PARAM_GEMM_WG_PER_CU = 6,   /* update-GEMM workgroups resident per CU in this handle's

@@ -110,23 +110,34 @@ hipError_t ensure_aux(cdf_handle_t h) {
     return hipSuccess;
 }
 
-hipError_t potrf_blocked(cdf_handle_t h, int n, double *A, int lda, int *info, int info_off, int nb) {
-    hipStream_t s = h->stream;
+// Block column of a lower Cholesky: the m x kb column [A11; A21] with its kb
+// x kb diagonal block on top, factored right-looking over sub-blocks of at
+// most 64 columns (the register-resident right-side solve's limit, so that
+// the panel fits beside the update GEMM on another stream); each sub-block
+// updates only the rest of this block column.  Launches go to stream s;
+// info values are offset by info_off.
+hipError_t potrf_panel(cdf_handle_t h, hipStream_t s, int m, int kb, double *A, int lda, int *info, int info_off) {
     const GemmCtx gc = gemm_ctx(h);
-    for (int k = 0; k < n; k += nb) {
-        const int kb = nb < n - k ? nb : n - k;
-        double *a11 = A + k + (size_t)k * lda;
-        CDF_HIP_RET(potrf_diag(s, kb, a11, lda, info, info_off + k));
-        const int rest = n - k - kb;
-        if (rest > 0) {
-            double *a21 = A + (k + kb) + (size_t)k * lda;
-            double *a22 = A + (k + kb) + (size_t)(k + kb) * lda;
-            CDF_HIP_RET(trsm_small(s, TRSM_RLTN, kb, rest, a11, lda, a21, lda, info));
-            CDF_HIP_RET(dgemm(s, 0, 1, rest, rest, kb, -1.0, a21, lda, a21, lda, 1.0, a22, lda, true, info, &gc));
+    constexpr int kSub = 64;
+    for (int j = 0; j < kb; j += kSub) {
+        const int jb = kSub < kb - j ? kSub : kb - j;
+        double *a11 = A + j + (size_t)j * lda;
+        CDF_HIP_RET(potrf_diag(s, jb, a11, lda, info, info_off + j));
+        const int below = m - j - jb;
+        if (below > 0) CDF_HIP_RET(trsm_small(s, TRSM_RLTN, jb, below, a11, lda, a11 + jb, lda, info));
+        const int c = j + jb, w = kb - c;  // remaining columns of the block column
+        if (w > 0) {
+            double *l = A + c + (size_t)j * lda;  // rows [c, m) of the sub-block's L
+            CDF_HIP_RET(dgemm(s, 0, 1, w, w, jb, -1.0, l, lda, l, lda, 1.0, A + c + (size_t)c * lda, lda, true, info,
+                              &gc));
+            if (m - c - w > 0)
+                CDF_HIP_RET(dgemm(s, 0, 1, m - c - w, w, jb, -1.0, l + w, lda, l, lda, 1.0,
+                                  A + (c + w) + (size_t)c * lda, lda, false, info, &gc));
         }
     }
     return hipSuccess;
 }
+
 
 }  // namespace cdf
 
@@ -291,29 +302,9 @@ hipError_t potrf_impl(cdf_handle_t h, int n, double *A, int lda, int *info) {
     hipStream_t s1 = h->aux;
     CDF_HIP_RET(cdf::fill_int(s0, info, 1, 0));
     const int nb = chol_nb(h, n);
-    // block column [k, k+kb): right-looking over sub-blocks of at most 64
-    // columns (the register-resident right-side solve's limit, so that the
-    // panel fits beside the update GEMM); each sub-block updates only the
-    // rest of this block column.
-    constexpr int kSub = 64;
+    // block column [k, k+kb) over rows [k, n)
     auto panel = [&](hipStream_t s, int k, int kb) -> hipError_t {
-        for (int kk = k; kk < k + kb; kk += kSub) {
-            const int kbb = kSub < k + kb - kk ? kSub : k + kb - kk;
-            double *a11 = A + kk + (size_t)kk * lda;
-            CDF_HIP_RET(cdf::potrf_diag(s, kbb, a11, lda, info, kk));
-            const int below = n - kk - kbb;
-            if (below > 0) CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_RLTN, kbb, below, a11, lda, a11 + kbb, lda, info));
-            const int c = kk + kbb, w = k + kb - c;  // remaining columns of the block column
-            if (w > 0) {
-                double *l = A + c + (size_t)kk * lda;  // rows [c, n) of the sub-block's L
-                CDF_HIP_RET(cdf::dgemm(s, 0, 1, w, w, kbb, -1.0, l, lda, l, lda, 1.0, A + c + (size_t)c * lda, lda,
-                                       true, info, &gc));
-                if (n - c - w > 0)
-                    CDF_HIP_RET(cdf::dgemm(s, 0, 1, n - c - w, w, kbb, -1.0, l + w, lda, l, lda, 1.0,
-                                           A + (c + w) + (size_t)c * lda, lda, false, info, &gc));
-            }
-        }
-        return hipSuccess;
+        return cdf::potrf_panel(h, s, n - k, kb, A + k + (size_t)k * lda, lda, info, k);
     };
     CDF_HIP_RET(panel(s0, 0, nb < n ? nb : n));
     for (int k = 0; k < n; k += nb) {

@@ -185,8 +185,9 @@ hipError_t apply_pairs(hipStream_t s, int c0, int c1, double *A, int lda, const 
 hipError_t apply_pairs(hipStream_t s, int c0, int c1, float *A, int lda, const int *pairs);
 // ipiv_out[i] = ipiv_in[i] + off for i < count.
 hipError_t offset_pivots(hipStream_t s, const int *ipiv_in, int *ipiv_out, int count, int off);
-// Blocked lower Cholesky of an n x n matrix (block width nb <= 128).
-hipError_t potrf_blocked(cdf_handle_t h, int n, double *A, int lda, int *info, int info_off, int nb);
+// Block column of a lower Cholesky (m x kb, its diagonal block on top),
+// factored in sub-blocks of 64 columns on stream s; info offset by info_off.
+hipError_t potrf_panel(cdf_handle_t h, hipStream_t s, int m, int kb, double *A, int lda, int *info, int info_off);
 
 // Apply interchanges ipiv[k1..k2) (absolute, 1-based) to rows of columns
 // [c0, c1) of A (nrows rows); an entry outside [k+1, nrows] is ignored.

@@ -318,14 +318,6 @@ __global__ void convert_kernel(int m, int n, const S *__restrict__ a, int lda, D
     b[(size_t)i + (size_t)j * ldb] = (D)a[(size_t)i + (size_t)j * lda];
 }
 
-// Symmetric extension: a(j, i) = a(i, j) for i > j (upper from lower).
-__global__ void symmetrize_kernel(int n, double *__restrict__ a, int lda) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= n || i <= j) return;
-    a[(size_t)j + (size_t)i * lda] = a[(size_t)i + (size_t)j * lda];
-}
-
 __global__ void add_offset_kernel(const int *__restrict__ src, int *__restrict__ dst, int count, int off) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) dst[i] = src[i] + off;
@@ -756,25 +748,61 @@ hipError_t mixed_getrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, int *i
     return hipSuccess;
 }
 
-// Blocked right-looking lower Cholesky of the binary32 copy W.
-hipError_t mixed_potrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, MixedWs &w, int nb_in, int *info) {
-    hipStream_t s = h->stream;
-    const int nb = nb_in < 256 ? nb_in : 256;  // the right-side solve takes triangles up to 256
+// Blocked right-looking lower Cholesky of the binary32 copy W.  Each block
+// column is copied to binary64 (P), factored there (diagonal block and the
+// rows below it, in sub-blocks of 64 columns: binary64 L11 and L21 = A21
+// L11^-T), rounded back to W, and its L21 tile-quantized for the
+// low-precision SYRK of the trailing lower triangle.  Look-ahead of depth
+// one, as in the binary64 path: the next block column is updated first and
+// factored on the second stream while the rest of the trailing triangle is
+// updated (when the block width is a multiple of the quantization tile, so
+// both parts keep the tile exponents of L21); the quantized L21 of
+// consecutive block columns alternates between two buffers.
+hipError_t mixed_potrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, MixedWs &w, int nb, int *info) {
+    hipStream_t s0 = h->stream;
+    CDF_HIP_RET(cdf::ensure_aux(h));
+    hipStream_t s1 = h->aux;
     const int kp = kpad_of(nb);
-    for (int k = 0; k < n; k += nb) {
+    const bool split = nb % QT == 0;
+    void *Q[2] = {w.QA, w.QB};
+    int *E[2] = {w.ea, w.eb};
+    auto panel = [&](hipStream_t s, int k, int kb, int buf) -> hipError_t {
+        const int m = n - k;
+        float *wk = W + k + (size_t)k * ldw;
+        CDF_HIP_RET(cdf::convert_s2d(s, m, kb, wk, ldw, w.P[buf], m, true));
+        CDF_HIP_RET(cdf::potrf_panel(h, s, m, kb, w.P[buf], m, info, k));
+        CDF_HIP_RET(cdf::convert_d2s(s, m, kb, w.P[buf], m, wk, ldw, true));
+        if (m > kb) CDF_HIP_RET(cdf::quantize(s, fmt, m - kb, kb, wk + kb, ldw, QT, kb, Q[buf], kp, E[buf], true));
+        return hipSuccess;
+    };
+    CDF_HIP_RET(panel(s0, 0, nb < n ? nb : n, 0));
+    for (int k = 0, it = 0; k < n; k += nb, ++it) {
         const int kb = nb < n - k ? nb : n - k;
-        const int rest = n - k - kb;
-        float *w11 = W + k + (size_t)k * ldw;
-        CDF_HIP_RET(cdf::convert_s2d(s, kb, kb, w11, ldw, w.P[0], kb, true));
-        CDF_HIP_RET(cdf::potrf_blocked(h, kb, w.P[0], kb, info, k, 128));
-        CDF_HIP_RET(cdf::convert_d2s(s, kb, kb, w.P[0], kb, w11, ldw, true));
-        if (rest > 0) {
-            float *w21 = W + (k + kb) + (size_t)k * ldw;
-            float *w22 = W + (k + kb) + (size_t)(k + kb) * ldw;
-            CDF_HIP_RET(cdf::trsm_small(s, cdf::TRSM_RLTN, kb, rest, w.P[0], kb, w21, ldw, info));
-            CDF_HIP_RET(cdf::quantize(s, fmt, rest, kb, w21, ldw, QT, kb, w.QA, kp, w.ea, true));
-            CDF_HIP_RET(cdf::lowp_update(s, fmt, rest, rest, kb, w.QA, kp, w.ea, w.QA, kp, w.ea, w22, ldw, true,
+        const int k1 = k + kb;
+        if (k1 >= n) break;
+        const int kb1 = nb < n - k1 ? nb : n - k1;
+        const int rest = n - k1;
+        const int b = it & 1;
+        const char *q = static_cast<const char *>(Q[b]);  // L21 of block column k, rows [k1, n)
+        const int *e = E[b];
+        float *d1 = W + k1 + (size_t)k1 * ldw;             // next diagonal block
+        if (split && rest > kb1) {
+            const char *q2 = q + (size_t)kb1 * kp * esize(fmt);  // its rows [k1 + kb1, n)
+            const int *e2 = e + kb1 / QT;
+            // next block column: its diagonal block (lower) and the rows below it
+            CDF_HIP_RET(cdf::lowp_update(s0, fmt, kb1, kb1, kb, q, kp, e, q, kp, e, d1, ldw, true, info));
+            CDF_HIP_RET(cdf::lowp_update(s0, fmt, rest - kb1, kb1, kb, q2, kp, e2, q, kp, e, d1 + kb1, ldw, false,
                                          info));
+            CDF_HIP_RET(hipEventRecord(h->ev[0], s0));
+            CDF_HIP_RET(hipStreamWaitEvent(s1, h->ev[0], 0));
+            CDF_HIP_RET(panel(s1, k1, kb1, b ^ 1));
+            CDF_HIP_RET(hipEventRecord(h->ev[1], s1));
+            CDF_HIP_RET(cdf::lowp_update(s0, fmt, rest - kb1, rest - kb1, kb, q2, kp, e2, q2, kp, e2,
+                                         d1 + kb1 + (size_t)kb1 * ldw, ldw, true, info));
+            CDF_HIP_RET(hipStreamWaitEvent(s0, h->ev[1], 0));
+        } else {
+            CDF_HIP_RET(cdf::lowp_update(s0, fmt, rest, rest, kb, q, kp, e, q, kp, e, d1, ldw, true, info));
+            CDF_HIP_RET(panel(s0, k1, kb1, b ^ 1));
         }
     }
     return hipSuccess;
@@ -816,8 +844,7 @@ cdf_status_t mixed_solve(cdf_handle_t h, int fmt, bool chol, int n, int nrhs, co
     int ldres = lda;
     if (chol) {
         CDF_HIP_TRY(cdf::copy_cols(s, n, n, A, lda, w.Afull, n));
-        hipLaunchKernelGGL(symmetrize_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, n, w.Afull, n);
-        CDF_HIP_TRY(hipGetLastError());
+        CDF_HIP_TRY(cdf::symmetrize_lower(s, n, w.Afull, n));
         Ares = w.Afull;
         ldres = n;
     }
