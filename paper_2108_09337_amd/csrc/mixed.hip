@@ -176,14 +176,21 @@ __device__ inline int xcd_remap(int bid, int nwg) {
     return (bid & 7) * (full >> 3) + (bid >> 3);
 }
 
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glob_void;
+
 // C (binary32) -= dq(QA) dq(QB): a 128 x 128 tile per workgroup, 64 x 64 per
-// wave as 4 x 4 blocks of the 16x16x32 MFMA.  The update streams C once
-// (read + write, 8 bytes per element against 2k flops), so it is bound by
-// HBM: C is read with 16-byte loads at the start into registers of its own,
-// so that its latency overlaps the whole K loop, and written once at the
-// end as C - 2^-(ea+eb) * acc.  Operands go through LDS in chunks of 128
-// bytes of K per row (double-buffered, rows padded by 16 bytes so the
-// fragment reads of 16 consecutive rows hit distinct banks).
+// wave as 4 x 4 blocks of the 16x16x32 MFMA, two workgroups per CU.  The
+// update streams C once (read + write, 8 bytes per element against 2k
+// flops), so it is bound by HBM: C is read with 16-byte loads at the start
+// into registers of its own and written once at the end as C - 2^-(ea+eb)
+// acc.  The operands come in chunks of 64 bytes of K per row, loaded
+// straight into LDS (no register staging) through a ring of four stages, so
+// that three chunks are in flight while one is multiplied: the operand rows
+// are shared by many tiles and mostly hit L2 or the last-level cache, whose
+// latency one chunk of work does not cover.  In LDS a row's four 16-byte
+// pieces are stored XOR-swizzled by bits 2..3 of the row, so the fragment
+// reads of 16 consecutive rows fall in distinct banks without padding.
 template <int FMT, bool LOWER>
 __global__ __launch_bounds__(NT, 2) void lowp_gemm_kernel(int m, int n, int kpad, const void *__restrict__ QA, int lda,
                                                           const int *__restrict__ ea, const void *__restrict__ QB,
@@ -192,11 +199,11 @@ __global__ __launch_bounds__(NT, 2) void lowp_gemm_kernel(int m, int n, int kpad
     if (stop != nullptr && *stop != 0) return;
     using F = Frag<FMT>;
     constexpr int ES = F::ES;    // bytes per code
-    constexpr int CB = 128;      // bytes of K per row and chunk
-    constexpr int KC = CB / ES;  // K per chunk
-    constexpr int RS = CB + 16;  // LDS row stride (bytes)
-    __shared__ __attribute__((aligned(16))) unsigned char As[2][QT * RS];
-    __shared__ __attribute__((aligned(16))) unsigned char Bs[2][QT * RS];
+    constexpr int CB = 64;       // bytes of K per row and chunk
+    constexpr int KC = CB / ES;  // K per chunk (one or two MFMA steps)
+    constexpr int NS = 4;        // LDS stages
+    constexpr int SB = 2 * QT * CB;  // bytes per stage: A rows, then B rows
+    __shared__ __attribute__((aligned(16))) unsigned char S[NS * SB];
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     int tm, tn;
     if (LOWER) {
@@ -217,94 +224,144 @@ __global__ __launch_bounds__(NT, 2) void lowp_gemm_kernel(int m, int n, int kpad
     const int wm = wave & 1, wn = wave >> 1;
     const int lrow = lane & 15, lk = lane >> 4;
     const int sc = ea[tm] + eb[tn];
-    const bool vec = ((reinterpret_cast<uintptr_t>(C) & 15) == 0) && (ldc & 3) == 0;
+    // interior tile (the whole tile inside C, and for the lower form strictly
+    // below the diagonal) with 16-byte aligned columns: every lane takes the
+    // vector path.  The test is uniform over the workgroup, so the vector
+    // loads are issued back to back (a per-lane choice between vector and
+    // element loads into the same registers makes each vector load wait for
+    // all earlier ones).
+    const bool full = ((reinterpret_cast<uintptr_t>(C) & 15) == 0) && (ldc & 3) == 0 && m0 + QT <= m &&
+                      n0 + QT <= n && (!LOWER || tm > tn);
 
     // 16x16 f32 output block: register v of a lane holds row 4*(lane/16)+v, column lane%16.
-    v4f acc[4][4], cr[4][4];
+    v4f acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-            const int col = n0 + wn * 64 + j * 16 + lrow;
-            const int row0 = m0 + wm * 64 + i * 16 + lk * 4;
-            if (vec && row0 + 3 < m && col < n && (!LOWER || row0 >= col)) {
-                cr[i][j] = *reinterpret_cast<const v4f *>(C + (size_t)row0 + (size_t)col * ldc);
-            } else {
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    // C in whole column segments: wave w holds tile columns 32 w .. 32 w + 31,
+    // register q of lane l the rows 4 (l % 32) .. 4 (l % 32) + 3 of column
+    // 32 w + 2 q + l / 32, so each load and store instruction covers two
+    // 512-byte column pieces.
+    const int crow = 4 * (lane & 31);
+    v4f cc[16];
+    if (full) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = row0 + v;
-                    cr[i][j][v] = (row < m && col < n && (!LOWER || row >= col)) ? C[(size_t)row + (size_t)col * ldc] : 0.f;
-                }
+        for (int q = 0; q < 16; ++q) {
+            const int col = n0 + 32 * wave + 2 * q + (lane >> 5);
+            cc[q] = *reinterpret_cast<const v4f *>(C + (size_t)(m0 + crow) + (size_t)col * ldc);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int col = n0 + 32 * wave + 2 * q + (lane >> 5);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + crow + v;
+                cc[q][v] = (row < m && col < n && (!LOWER || row >= col)) ? C[(size_t)row + (size_t)col * ldc] : 0.f;
             }
         }
+    }
 
-    // operand pieces of 16 bytes: piece e = t + NT q covers row e / 8, bytes (e % 8) * 16 of the chunk
+    // Loads of a chunk: wave w brings row groups 2w, 2w + 1 (16 rows each) of
+    // A and of B, one 1 KB instruction per group: lane l writes the group's
+    // LDS bytes 16 l .. 16 l + 15, i.e. slot l % 4 of row l / 4, which holds
+    // the row's piece (l % 4) ^ ((row / 4) % 4).  Rows past the matrix read
+    // its last row and pieces past the padded K its last piece (the products
+    // of such rows are not stored; such K steps are skipped).
     const unsigned char *qa = static_cast<const unsigned char *>(QA);
     const unsigned char *qb = static_cast<const unsigned char *>(QB);
-    v4u ra[4], rb[4];
-    auto gload = [&](int k0) {
+    const int kbytes = kpad * ES;
+    const int lr = lane >> 2, piece = (lane & 3) ^ ((lr >> 2) & 3);
+    const unsigned char *asrc[2], *bsrc[2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = t + NT * q, r = e >> 3, off = (e & 7) * 16;
-            const int kk = k0 + off / ES;
-            const v4u z = v4u{0u, 0u, 0u, 0u};
-            ra[q] = (m0 + r < m && kk < kpad) ? *reinterpret_cast<const v4u *>(qa + ((size_t)(m0 + r) * lda + kk) * ES) : z;
-            rb[q] = (n0 + r < n && kk < kpad) ? *reinterpret_cast<const v4u *>(qb + ((size_t)(n0 + r) * ldb + kk) * ES) : z;
+    for (int u = 0; u < 2; ++u) {
+        const int g = 2 * wave + u;
+        asrc[u] = qa + (size_t)min(m0 + 16 * g + lr, m - 1) * lda * ES;
+        bsrc[u] = qb + (size_t)min(n0 + 16 * g + lr, n - 1) * ldb * ES;
+    }
+    auto issue = [&](int c) {
+        unsigned char *st = S + (c % NS) * SB;
+        const int off = min(c * CB + piece * 16, kbytes - 16);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int g = 2 * wave + u;
+            __builtin_amdgcn_global_load_lds((glob_void *)(asrc[u] + off), (lds_void *)(st + g * 1024), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((glob_void *)(bsrc[u] + off), (lds_void *)(st + QT * CB + g * 1024), 16,
+                                             0, 0);
         }
     };
-    auto sstore = [&](int b) {
+    // LDS byte of (row, byte b of the chunk) in a stage
+    auto lds_at = [](int row, int b) { return row * CB + ((((b >> 4) ^ (row >> 2)) & 3) << 4) + (b & 15); };
+    const int nc = (kbytes + CB - 1) / CB;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = t + NT * q, r = e >> 3, off = (e & 7) * 16;
-            *reinterpret_cast<v4u *>(&As[b][r * RS + off]) = ra[q];
-            *reinterpret_cast<v4u *>(&Bs[b][r * RS + off]) = rb[q];
-        }
-    };
-    const int nc = (kpad + KC - 1) / KC;
-    gload(0);
-    sstore(0);
-    __syncthreads();
+    for (int q = 0; q < NS - 1; ++q)
+        if (q < nc) issue(q);
     for (int c = 0; c < nc; ++c) {
-        const int b = c & 1;
-        if (c + 1 < nc) gload((c + 1) * KC);
+        // this wave's loads of chunk c have landed: the later chunks issued
+        // so far (4 loads each) may still be in flight
+        const int ahead = min(nc - 1 - c, NS - 2);
+        if (ahead >= 2) __builtin_amdgcn_s_waitcnt(0xF78);       // vmcnt(8)
+        else if (ahead == 1) __builtin_amdgcn_s_waitcnt(0xF74);  // vmcnt(4)
+        else __builtin_amdgcn_s_waitcnt(0xF70);                  // vmcnt(0)
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();  // ... for every wave; the stage of chunk c - 1 is free
+        asm volatile("" ::: "memory");
+        if (c + NS - 1 < nc) issue(c + NS - 1);
+        const unsigned char *As = S + (c % NS) * SB;
+        const unsigned char *Bs = As + QT * CB;
 #pragma unroll
         for (int ks = 0; ks < KC / KSTEP; ++ks) {
             if (c * KC + ks * KSTEP >= kpad) break;
+            const int b = (ks * KSTEP + lk * 8) * ES;
             typename F::T af[4], bf[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                af[i] = F::lds(&As[b][(wm * 64 + i * 16 + lrow) * RS + (ks * KSTEP + lk * 8) * ES]);
-                bf[i] = F::lds(&Bs[b][(wn * 64 + i * 16 + lrow) * RS + (ks * KSTEP + lk * 8) * ES]);
+                af[i] = F::lds(As + lds_at(wm * 64 + i * 16 + lrow, b));
+                bf[i] = F::lds(Bs + lds_at(wn * 64 + i * 16 + lrow, b));
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j] = F::mma(af[i], bf[j], acc[i][j]);
         }
-        if (c + 1 < nc) sstore(b ^ 1);
-        __syncthreads();
     }
 
+    // 2^-(ea+eb) acc through LDS (the operand stages are free once every
+    // wave is past its last chunk) into the column layout of C: tile column
+    // c holds its 32 four-row pieces at slots XOR-ed with c % 32, so the
+    // writes of 16 columns and the reads of one column are conflict-free.
+    __syncthreads();
+    float *X = reinterpret_cast<float *>(S);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int col = n0 + wn * 64 + j * 16 + lrow;
-            const int row0 = m0 + wm * 64 + i * 16 + lk * 4;
-            v4f out;
+            const int col = wn * 64 + j * 16 + lrow;
+            const int piece = (wm * 64 + i * 16 + lk * 4) >> 2;
+            v4f a;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) out[v] = cr[i][j][v] - ldexpf(acc[i][j][v], -sc);
-            if (vec && row0 + 3 < m && col < n && (!LOWER || row0 >= col)) {
-                *reinterpret_cast<v4f *>(C + (size_t)row0 + (size_t)col * ldc) = out;
-            } else {
+            for (int v = 0; v < 4; ++v) a[v] = ldexpf(acc[i][j][v], -sc);
+            *reinterpret_cast<v4f *>(X + col * QT + ((piece ^ (col & 31)) << 2)) = a;
+        }
+    __syncthreads();
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = row0 + v;
-                    if (row < m && col < n && (!LOWER || row >= col)) C[(size_t)row + (size_t)col * ldc] = out[v];
-                }
+    for (int q = 0; q < 16; ++q) {
+        const int tc = 32 * wave + 2 * q + (lane >> 5), col = n0 + tc;
+        const v4f a = *reinterpret_cast<const v4f *>(X + tc * QT + ((((lane & 31) ^ (tc & 31))) << 2));
+        v4f out;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[v] = cc[q][v] - a[v];
+        if (full) {
+            *reinterpret_cast<v4f *>(C + (size_t)(m0 + crow) + (size_t)col * ldc) = out;
+        } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + crow + v;
+                if (row < m && col < n && (!LOWER || row >= col)) C[(size_t)row + (size_t)col * ldc] = out[v];
             }
         }
+    }
 }
 
 // ------------------------------------------------------------- elementwise
