@@ -88,6 +88,57 @@ __global__ __launch_bounds__(NT) void potrf_diag_kernel(int n, double *__restric
     if (t == 0 && fail) *info = info_base + fail;
 }
 
+// Blocks of at most 64 columns (the panels' sub-blocks): one wave, lane i
+// holding row i of the block in registers.  Column k: the diagonal and the
+// later rows of column k are read from their lanes (readlane), so no LDS
+// and no barrier; the same operations in the same order as above (S1, S2
+// by division, S3 as fma(-L(i,k), L(j,k), a(i,j)) over j > k).  Elements
+// above the diagonal are updated too (their lanes simply compute with
+// them) but never read or stored.
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const long long x = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)x, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(x >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__global__ __launch_bounds__(64) void potrf64_kernel(int n, double *__restrict__ A, int lda, int *__restrict__ info,
+                                                     int info_base) {
+    if (*info != 0) return;
+    const int i = threadIdx.x;
+    double a[64];
+    cdf::static_for<0, 64>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        a[j] = (i < n && j < n && i >= j) ? A[(size_t)i + (size_t)j * lda] : 0.0;
+    });
+    int fail = 0;  // uniform
+    cdf::static_for<0, 64>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        if (k < n && !fail) {
+            const double d = lane_value(a[k], k);
+            if (!(d > 0.0)) {
+                fail = k + 1;
+            } else {
+                const double lkk = sqrt(d);
+                if (i == k) a[k] = lkk;
+                else if (i > k) a[k] = a[k] / lkk;
+                cdf::static_for<k + 1, 64>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    if (j < n) a[j] = fma(-a[k], lane_value(a[k], j), a[j]);
+                    // keep the broadcasts next to their uses (hoisted, they
+                    // would exhaust the scalar registers)
+                    if constexpr ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                });
+            }
+        }
+    });
+    cdf::static_for<0, 64>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (i < n && j < n && i >= j) A[(size_t)i + (size_t)j * lda] = a[j];
+    });
+    if (i == 0 && fail) *info = info_base + fail;
+}
+
 }  // namespace
 
 namespace cdf {
@@ -95,7 +146,10 @@ namespace cdf {
 hipError_t potrf_diag(hipStream_t s, int n, double *A, int lda, int *info, int info_base) {
     if (n <= 0) return hipSuccess;
     if (n > MAXN) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(NT), 0, s, n, A, lda, info, info_base);
+    if (n <= 64)
+        hipLaunchKernelGGL(potrf64_kernel, dim3(1), dim3(64), 0, s, n, A, lda, info, info_base);
+    else
+        hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(NT), 0, s, n, A, lda, info, info_base);
     return hipGetLastError();
 }
 

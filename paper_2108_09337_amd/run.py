@@ -77,8 +77,7 @@ def main():
         if args.op == "gesv-mixed":
             A = workloads.diag_dominant_torch(n)
         else:
-            pts = workloads.kernel_points(n)
-            A = cdf.to_device(workloads.exp_kernel_matrix(pts))
+            A = workloads.exp_kernel_matrix_torch(workloads.kernel_points(n))
         B = workloads.rhs_uniform_torch(n, args.nrhs)
         X = torch.empty_like(B)
         info = torch.zeros(1, dtype=torch.int32, device="cuda")
