@@ -115,16 +115,19 @@ hipError_t ensure_aux(cdf_handle_t h) {
 // most 64 columns (the register-resident right-side solve's limit, so that
 // the panel fits beside the update GEMM on another stream); each sub-block
 // updates only the rest of this block column.  Launches go to stream s;
-// info values are offset by info_off.
-hipError_t potrf_panel(cdf_handle_t h, hipStream_t s, int m, int kb, double *A, int lda, int *info, int info_off) {
+// info values are offset by info_off.  prio raises the issue priority of
+// the diagonal blocks and solves (measured: a gain beside the low-precision
+// SYRK, a loss beside the binary64 update, whose panel is not critical).
+hipError_t potrf_panel(cdf_handle_t h, hipStream_t s, int m, int kb, double *A, int lda, int *info, int info_off,
+                       bool prio) {
     const GemmCtx gc = gemm_ctx(h);
     constexpr int kSub = 64;
     for (int j = 0; j < kb; j += kSub) {
         const int jb = kSub < kb - j ? kSub : kb - j;
         double *a11 = A + j + (size_t)j * lda;
-        CDF_HIP_RET(potrf_diag(s, jb, a11, lda, info, info_off + j));
+        CDF_HIP_RET(potrf_diag(s, jb, a11, lda, info, info_off + j, prio));
         const int below = m - j - jb;
-        if (below > 0) CDF_HIP_RET(trsm_small(s, TRSM_RLTN, jb, below, a11, lda, a11 + jb, lda, info));
+        if (below > 0) CDF_HIP_RET(trsm_rltn_small(s, jb, below, a11, lda, a11 + jb, lda, info, prio));
         const int c = j + jb, w = kb - c;  // remaining columns of the block column
         if (w > 0) {
             double *l = A + c + (size_t)j * lda;  // rows [c, m) of the sub-block's L

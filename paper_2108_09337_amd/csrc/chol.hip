@@ -102,9 +102,12 @@ __device__ __forceinline__ double lane_value(double v, int l) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// PRIO: raised issue priority (a separate instantiation).
+template <bool PRIO>
 __global__ __launch_bounds__(64) void potrf64_kernel(int n, double *__restrict__ A, int lda, int *__restrict__ info,
                                                      int info_base) {
     if (*info != 0) return;
+    if (PRIO) __builtin_amdgcn_s_setprio(2);
     const int i = threadIdx.x;
     double a[64];
     cdf::static_for<0, 64>([&](auto jc) {
@@ -143,11 +146,13 @@ __global__ __launch_bounds__(64) void potrf64_kernel(int n, double *__restrict__
 
 namespace cdf {
 
-hipError_t potrf_diag(hipStream_t s, int n, double *A, int lda, int *info, int info_base) {
+hipError_t potrf_diag(hipStream_t s, int n, double *A, int lda, int *info, int info_base, bool prio) {
     if (n <= 0) return hipSuccess;
     if (n > MAXN) return hipErrorInvalidValue;
-    if (n <= 64)
-        hipLaunchKernelGGL(potrf64_kernel, dim3(1), dim3(64), 0, s, n, A, lda, info, info_base);
+    if (n <= 64 && prio)
+        hipLaunchKernelGGL(potrf64_kernel<true>, dim3(1), dim3(64), 0, s, n, A, lda, info, info_base);
+    else if (n <= 64)
+        hipLaunchKernelGGL(potrf64_kernel<false>, dim3(1), dim3(64), 0, s, n, A, lda, info, info_base);
     else
         hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(NT), 0, s, n, A, lda, info, info_base);
     return hipGetLastError();

@@ -187,7 +187,8 @@ hipError_t apply_pairs(hipStream_t s, int c0, int c1, float *A, int lda, const i
 hipError_t offset_pivots(hipStream_t s, const int *ipiv_in, int *ipiv_out, int count, int off);
 // Block column of a lower Cholesky (m x kb, its diagonal block on top),
 // factored in sub-blocks of 64 columns on stream s; info offset by info_off.
-hipError_t potrf_panel(cdf_handle_t h, hipStream_t s, int m, int kb, double *A, int lda, int *info, int info_off);
+hipError_t potrf_panel(cdf_handle_t h, hipStream_t s, int m, int kb, double *A, int lda, int *info, int info_off,
+                       bool prio = false);
 
 // Apply interchanges ipiv[k1..k2) (absolute, 1-based) to rows of columns
 // [c0, c1) of A (nrows rows); an entry outside [k+1, nrows] is ignored.
@@ -215,6 +216,10 @@ hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const dou
 // Same with a binary32 right-hand block (arithmetic in binary64).
 hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
                       float *B, int ldb, const int *stop = nullptr, int max_wg = 0);
+// B (nrows x nb, nb <= 64) <- B L^-T, L lower non-unit (the right-side solve
+// of trsm_small), with the solve's waves at raised priority if prio.
+hipError_t trsm_rltn_small(hipStream_t s, int nb, int nrows, const double *T, int ldt, double *B, int ldb,
+                           const int *stop, bool prio);
 
 // Full triangular solve with a large n x n factor (blocked: bs-wide diagonal
 // solves + GEMM updates; bs <= 256).
@@ -246,7 +251,9 @@ hipError_t trsm_inv_lower(hipStream_t s, bool transposed, int n, int nrhs, const
 // Cholesky of one diagonal block (n <= 128) held in LDS; stops at the first
 // non-positive pivot, writing info_base + j + 1 into *info if *info == 0.
 // *info != 0 on entry makes the kernel return without touching A.
-hipError_t potrf_diag(hipStream_t s, int n, double *A, int lda, int *info, int info_base);
+// prio: the block is on the critical chain beside a co-running update (its
+// wave issues at raised priority; blocks of at most 64 columns).
+hipError_t potrf_diag(hipStream_t s, int n, double *A, int lda, int *info, int info_base, bool prio = false);
 
 // Mixed-precision helpers.
 hipError_t convert_d2s(hipStream_t s, int m, int n, const double *A, int lda, float *W, int ldw,

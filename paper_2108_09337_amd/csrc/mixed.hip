@@ -827,7 +827,7 @@ hipError_t mixed_potrf(cdf_handle_t h, int fmt, int n, float *W, int ldw, MixedW
         const int m = n - k;
         float *wk = W + k + (size_t)k * ldw;
         CDF_HIP_RET(cdf::convert_s2d(s, m, kb, wk, ldw, w.P[buf], m, true));
-        CDF_HIP_RET(cdf::potrf_panel(h, s, m, kb, w.P[buf], m, info, k));
+        CDF_HIP_RET(cdf::potrf_panel(h, s, m, kb, w.P[buf], m, info, k, true));
         CDF_HIP_RET(cdf::convert_d2s(s, m, kb, w.P[buf], m, wk, ldw, true));
         if (m > kb) CDF_HIP_RET(cdf::quantize(s, fmt, m - kb, kb, wk + kb, ldw, QT, kb, Q[buf], kp, E[buf], true));
         return hipSuccess;

@@ -183,10 +183,13 @@ __global__ __launch_bounds__(NT) void trsm_rltn_kernel(int nb, int nrows, const 
 constexpr int RNC = 64;
 // FULL: nb == 64, so no entry is guarded and the compiler batches (and
 // merges) the triangle's scalar loads instead of waiting on each one.
-template <typename TB, bool FULL>
+// PRIO: raised issue priority (a separate instantiation, so the other one
+// keeps its register allocation).
+template <typename TB, bool FULL, bool PRIO = false>
 __global__ __launch_bounds__(64) void trsm_rltn_reg_kernel(int nb_in, int nrows, const double *__restrict__ T, int ldt,
                                                            TB *__restrict__ B, int ldb, const int *stop) {
     if (stop != nullptr && *stop != 0) return;
+    if (PRIO) __builtin_amdgcn_s_setprio(2);
     const int nb = FULL ? RNC : nb_in;
     const int r = blockIdx.x * 64 + threadIdx.x;
     const bool live = r < nrows;
@@ -231,15 +234,23 @@ hipError_t launch_left(hipStream_t s, int nb, int ncols, const double *T, int ld
 
 template <typename TB>
 hipError_t launch_right(hipStream_t s, int nb, int nrows, const double *T, int ldt, TB *B, int ldb,
-                        const int *stop) {
+                        const int *stop, bool prio = false) {
+    const dim3 grid((nrows + 63) / 64);
     if (nb == RNC) {
-        hipLaunchKernelGGL((trsm_rltn_reg_kernel<TB, true>), dim3((nrows + 63) / 64), dim3(64), 0, s, nb, nrows, T,
-                           ldt, B, ldb, stop);
+        if (prio)
+            hipLaunchKernelGGL((trsm_rltn_reg_kernel<TB, true, true>), grid, dim3(64), 0, s, nb, nrows, T, ldt, B, ldb,
+                               stop);
+        else
+            hipLaunchKernelGGL((trsm_rltn_reg_kernel<TB, true>), grid, dim3(64), 0, s, nb, nrows, T, ldt, B, ldb, stop);
         return hipGetLastError();
     }
     if (nb < RNC) {
-        hipLaunchKernelGGL((trsm_rltn_reg_kernel<TB, false>), dim3((nrows + 63) / 64), dim3(64), 0, s, nb, nrows, T,
-                           ldt, B, ldb, stop);
+        if (prio)
+            hipLaunchKernelGGL((trsm_rltn_reg_kernel<TB, false, true>), grid, dim3(64), 0, s, nb, nrows, T, ldt, B,
+                               ldb, stop);
+        else
+            hipLaunchKernelGGL((trsm_rltn_reg_kernel<TB, false>), grid, dim3(64), 0, s, nb, nrows, T, ldt, B, ldb,
+                               stop);
         return hipGetLastError();
     }
     static bool attr = false;
@@ -576,6 +587,13 @@ hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const dou
 hipError_t trsm_small(hipStream_t s, TrsmKind kind, int nb, int ncols, const double *T, int ldt,
                       float *B, int ldb, const int *stop, int max_wg) {
     return trsm_small_impl<float>(s, kind, nb, ncols, T, ldt, B, ldb, stop, max_wg);
+}
+
+hipError_t trsm_rltn_small(hipStream_t s, int nb, int nrows, const double *T, int ldt, double *B, int ldb,
+                           const int *stop, bool prio) {
+    if (nb <= 0 || nrows <= 0) return hipSuccess;
+    if (nb > RNC) return hipErrorInvalidValue;
+    return launch_right<double>(s, nb, nrows, T, ldt, B, ldb, stop, prio);
 }
 
 // Blocked solve with an n x n triangle: 128-wide diagonal solves, the rest
