@@ -464,16 +464,24 @@ __global__ __launch_bounds__(256) void trsv_sf_kernel(int n, int nrhs, const dou
         const int c = wave;
         const double sum = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
         double x = live ? B[(size_t)r + (size_t)c * ldb] - sum : 0.0;
+        // x_j from lane j by readlane (a register read, where a shuffle is
+        // an LDS round trip on each of the 64 dependent steps)
+        auto from_lane = [](double v, int l) {
+            const long long b = __double_as_longlong(v);
+            const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+            const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+            return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+        };
         if (forward) {
             for (int j = 0; j < kb; ++j) {
                 if (KIND == cdf::TRSM_LLNN && lane == j) x = x / Ts[j + j * 65];
-                const double xj = __shfl(x, j);
+                const double xj = from_lane(x, j);
                 if (lane > j && lane < kb) x = fma(-Ts[lane + j * 65], xj, x);
             }
         } else {
             for (int j = kb - 1; j >= 0; --j) {
                 if (lane == j) x = x / Ts[j + j * 65];
-                const double xj = __shfl(x, j);
+                const double xj = from_lane(x, j);
                 if (lane < j) x = fma(-Ts[lane + j * 65], xj, x);
             }
         }
