@@ -251,8 +251,8 @@ hipError_t trsm_inv_lower(hipStream_t s, bool transposed, int n, int nrhs, const
 // Cholesky of one diagonal block (n <= 128) held in LDS; stops at the first
 // non-positive pivot, writing info_base + j + 1 into *info if *info == 0.
 // *info != 0 on entry makes the kernel return without touching A.
-// prio: the block is on the critical chain beside a co-running update (its
-// wave issues at raised priority; blocks of at most 64 columns).
+// prio: the block is on the critical chain beside the low-precision update
+// (blocks of at most 64 columns then run as one wave at raised priority).
 hipError_t potrf_diag(hipStream_t s, int n, double *A, int lda, int *info, int info_base, bool prio = false);
 
 // Mixed-precision helpers.
